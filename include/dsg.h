@@ -1,0 +1,154 @@
+/*
+ * dsg.h -- C ABI of the MI355X densest-subgraph peeling library (libdsg.so).
+ *
+ * The library runs the iterated load-weighted peeling of Greedy++
+ * (Sukprasert, Liu, Dhulipala, Shun, "Practical Parallel Algorithms for
+ * Near-Optimal Densest Subgraphs on Massive Graphs", arXiv 2311.04333) on one
+ * AMD Instinct MI355X (gfx950).  Three orderings are provided:
+ *
+ *   DSG_SEQ  -- exact sequential Greedy++ (Algorithm 2 with the load ordering
+ *               of Section 2): one vertex at a time, minimum of load+degree,
+ *               ties to the lower vertex id.
+ *   DSG_PEEL -- the parallel ordering of ParallelGreedy++ (Section 3.3):
+ *               round-synchronous peeling.  Each round peels every remaining
+ *               vertex with load+degree <= (1 + eps) * (round minimum), and
+ *               eps = eps_num/eps_den is exact.  Effects of one round's
+ *               peels on degrees are delayed to the end of the round.
+ *               Positions inside a round follow ascending vertex id, so a
+ *               same-round edge is charged to its lower-id endpoint.
+ *   DSG_SORT -- GreedySorting++ / ParallelGreedySorting++ (Sections 3.2,
+ *               3.3): order by the load at the start of the iteration,
+ *               ties to the lower id.
+ *
+ * Every ordering feeds the same density-and-load computation (Algorithm 3):
+ * each edge charges its earlier endpoint, the suffix sums give
+ * |E(S_i)| of every suffix S_i of the order, the best suffix density of the
+ * iteration is kept as an exact (edges, vertices) pair, and the loads grow by
+ * the charges.  The best subgraph found so far is replaced only by a
+ * strictly denser one (Algorithm 2), starting from the input graph itself.
+ *
+ * Conventions
+ *   - Every call returns dsg_status.  No C++ exception crosses this ABI.
+ *     dsg_last_error() returns a message for the calling thread's last
+ *     failure.
+ *   - "d_" pointers are device pointers (HIP, on the context's device).
+ *     "h_" pointers are host pointers.  The caller owns all of them.
+ *   - The graph is an undirected simple graph given as a symmetric int32
+ *     CSR: offsets[n+1], adj[nnz], nnz = 2m, every row strictly increasing,
+ *     no self-loops, and every u in row v has v in row u.  Isolated vertices
+ *     are allowed.
+ *   - The library allocates no device memory.  All device state lives in
+ *     one caller-provided workspace of dsg_workspace_bytes() bytes, which
+ *     must stay alive (with the CSR) until dsg_graph_destroy.
+ *   - Work is enqueued asynchronously on the context's HIP stream.  The
+ *     dsg_get_* calls synchronise that stream before reading.
+ *   - Handles are not thread-safe; use one context per host thread.
+ */
+#ifndef DSG_H
+#define DSG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DSG_OK = 0,
+    DSG_EINVAL = -1,    /* bad argument or invalid CSR (message says which) */
+    DSG_ENOMEM = -2,    /* workspace smaller than dsg_workspace_bytes() */
+    DSG_EDEVICE = -3,   /* HIP runtime error (message has the HIP error string) */
+    DSG_EOVERFLOW = -4, /* the run could overflow the 31-bit device loads */
+    DSG_ESTATE = -5,    /* call not valid in the handle's state */
+    DSG_EBUSY = -6      /* server admission refused (over the HBM budget) */
+} dsg_status;
+
+typedef enum { DSG_SEQ = 0, DSG_PEEL = 1, DSG_SORT = 2 } dsg_variant;
+
+/* flags for dsg_graph_create */
+#define DSG_VALIDATE 1 /* check every CSR property listed above on the device */
+
+typedef struct dsg_ctx dsg_ctx;
+typedef struct dsg_graph dsg_graph;
+
+/* Context: binds a device and a stream.  hip_stream is a hipStream_t (for
+ * example torch.cuda.current_stream().cuda_stream); NULL means the null
+ * stream.  Fails with DSG_EDEVICE if the device cannot be used. */
+dsg_status dsg_ctx_create(int device, void* hip_stream, dsg_ctx** out);
+dsg_status dsg_ctx_destroy(dsg_ctx* ctx);
+
+/* Bytes of workspace a graph of n vertices and nnz CSR entries needs, with
+ * room for t_cap recorded iterations (per-iteration densities and digests).
+ * n >= 1, 0 <= nnz < 2^31, t_cap >= 1. */
+dsg_status dsg_workspace_bytes(int32_t n, int64_t nnz, int32_t t_cap, int64_t* bytes);
+
+/* Bind a CSR already resident on the device.  d_workspace must be 256-byte
+ * aligned and hold at least dsg_workspace_bytes(n, nnz, t_cap) bytes.  The
+ * state is reset: loads 0, best = the input graph (iteration 0).  With
+ * DSG_VALIDATE the CSR is checked and an invalid one gives DSG_EINVAL.
+ * This call synchronises the stream once (it reads the maximum degree). */
+dsg_status dsg_graph_create(dsg_ctx* ctx, int32_t n, int64_t nnz, const int32_t* d_offsets, const int32_t* d_adj,
+                            void* d_workspace, int64_t workspace_bytes, int32_t t_cap, int32_t flags,
+                            dsg_graph** out);
+
+/* Run T more iterations of the given variant (T >= 0), appending to the
+ * current state: loads and best carry over, so run(a) then run(b) equals
+ * run(a + b).  eps = eps_num / eps_den with eps_num >= 0, eps_den >= 1; only
+ * DSG_PEEL reads it.  DSG_SEQ requires n <= 32768 (its state sits in LDS).
+ * Fails with DSG_EINVAL if the recorded iterations would exceed t_cap, and
+ * with DSG_EOVERFLOW if (iterations + 1) * max_degree could reach 2^31.
+ * Asynchronous: returns once the work is enqueued. */
+dsg_status dsg_run(dsg_graph* g, int32_t T, int32_t eps_num, int32_t eps_den, dsg_variant variant);
+
+/* Loads to 0, best to the input graph, history cleared.  Asynchronous. */
+dsg_status dsg_reset(dsg_graph* g);
+
+/* Wait for everything enqueued on the graph's stream. */
+dsg_status dsg_sync(dsg_graph* g);
+
+/* Best subgraph so far: its edge and vertex counts, the iteration that found
+ * it (0 = the input graph) and its index i in that iteration's order (the
+ * set is the suffix of the order from position i). */
+dsg_status dsg_get_best(dsg_graph* g, int64_t* edges, int64_t* verts, int32_t* iter, int32_t* index);
+
+/* h_mask[v] = 1 if v belongs to the best subgraph, else 0 (n bytes). */
+dsg_status dsg_get_best_mask(dsg_graph* g, uint8_t* h_mask);
+
+/* Current loads (n int64 values). */
+dsg_status dsg_get_loads(dsg_graph* g, int64_t* h_loads);
+
+/* Per-iteration best suffix (edges, vertices, index), oldest first.  Writes
+ * min(cap, count) entries of each non-NULL array.  *count gets the number
+ * of iterations recorded. */
+dsg_status dsg_get_iter_densities(dsg_graph* g, int64_t* h_edges, int64_t* h_verts, int32_t* h_index, int32_t cap,
+                                  int32_t* count);
+
+/* Order of the last iteration: h_round[v] = its peeling round (DSG_PEEL) or
+ * its position (DSG_SEQ, DSG_SORT), h_pos[v] = its position.  Either
+ * pointer may be NULL.  *n_rounds gets the number of rounds of that
+ * iteration (n for DSG_SEQ and DSG_SORT). */
+dsg_status dsg_get_order(dsg_graph* g, int32_t* h_round, int32_t* h_pos, int32_t* n_rounds);
+
+/* Per-iteration order digests, oldest first: the sum mod 2^64 over all v of
+ * mix64(((uint64_t)v << 32) | (uint32_t)round[v]).  Here mix64(z) is the
+ * SplitMix64 output function applied to z + 0x9E3779B97F4A7C15, and round
+ * is as in dsg_get_order.  Also the number of rounds of each iteration
+ * (h_rounds may be NULL). */
+dsg_status dsg_get_iter_digests(dsg_graph* g, uint64_t* h_digest, int32_t* h_rounds, int32_t cap, int32_t* count);
+
+/* Release the handle.  Caller memory (CSR, workspace) is not freed. */
+dsg_status dsg_graph_destroy(dsg_graph* g);
+
+/* Device time of the last dsg_run, in milliseconds (HIP events around the
+ * enqueued work of that call, on the graph's stream).  The call waits for
+ * the work to finish. */
+dsg_status dsg_last_run_ms(dsg_graph* g, float* ms);
+
+/* Message for the calling thread's last failed call ("" if none). */
+const char* dsg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DSG_H */
