@@ -94,7 +94,7 @@ dsg_status dsg_graph_create(dsg_ctx* ctx, int32_t n, int64_t nnz, const int32_t*
 /* Run T more iterations of the given variant (T >= 0), appending to the
  * current state: loads and best carry over, so run(a) then run(b) equals
  * run(a + b).  eps = eps_num / eps_den with eps_num >= 0, eps_den >= 1; only
- * DSG_PEEL reads it.  DSG_SEQ requires n <= 32768 (its state sits in LDS).
+ * DSG_PEEL reads it.  DSG_SEQ requires n <= 16000 (its state sits in LDS).
  * Fails with DSG_EINVAL if the recorded iterations would exceed t_cap, and
  * with DSG_EOVERFLOW if (iterations + 1) * max_degree could reach 2^31.
  * Asynchronous: returns once the work is enqueued. */
@@ -103,7 +103,9 @@ dsg_status dsg_run(dsg_graph* g, int32_t T, int32_t eps_num, int32_t eps_den, ds
 /* Loads to 0, best to the input graph, history cleared.  Asynchronous. */
 dsg_status dsg_reset(dsg_graph* g);
 
-/* Wait for everything enqueued on the graph's stream. */
+/* Wait for everything enqueued on the graph's stream.  Returns DSG_EDEVICE if a
+ * kernel-side consistency check (bounded round loop, sweep item bounds)
+ * fired during the work. */
 dsg_status dsg_sync(dsg_graph* g);
 
 /* Best subgraph so far: its edge and vertex counts, the iteration that found

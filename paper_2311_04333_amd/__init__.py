@@ -1,0 +1,266 @@
+"""Python binding of libdsg.so: Greedy++ peeling on one MI355X.
+
+This module only marshals arguments.  Every step of the algorithm runs in the
+library's HIP kernels (csrc/), behind the C ABI declared in include/dsg.h.
+PyTorch supplies device memory (the CSR tensors and the workspace) and the
+HIP stream.  When the compiled library is missing, importing this package
+still works, but any call raises RuntimeError.  There is no fallback path.
+
+    import paper_2311_04333_amd as dsg
+    ctx = dsg.Context(0)
+    g = dsg.Graph(ctx, offsets, adj, t_cap=64)   # numpy or torch CSR
+    g.run(20, eps=(1, 10), variant="peel")
+    edges, verts, it, idx = g.best()
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from fractions import Fraction
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdsg.so")
+_lib = None
+
+VARIANTS = {"seq": 0, "peel": 1, "sort": 2}
+STATUS = {0: "DSG_OK", -1: "DSG_EINVAL", -2: "DSG_ENOMEM", -3: "DSG_EDEVICE", -4: "DSG_EOVERFLOW",
+          -5: "DSG_ESTATE", -6: "DSG_EBUSY"}
+VALIDATE = 1
+
+# every entry point declared in include/dsg.h: (name, restype, argtypes)
+_P = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
+SIGNATURES = [
+    ("dsg_ctx_create", ctypes.c_int, [ctypes.c_int, _P, _P]),
+    ("dsg_ctx_destroy", ctypes.c_int, [_P]),
+    ("dsg_workspace_bytes", ctypes.c_int, [_I32, _I64, _I32, _P]),
+    ("dsg_graph_create", ctypes.c_int, [_P, _I32, _I64, _P, _P, _P, _I64, _I32, _I32, _P]),
+    ("dsg_run", ctypes.c_int, [_P, _I32, _I32, _I32, ctypes.c_int]),
+    ("dsg_reset", ctypes.c_int, [_P]),
+    ("dsg_sync", ctypes.c_int, [_P]),
+    ("dsg_get_best", ctypes.c_int, [_P, _P, _P, _P, _P]),
+    ("dsg_get_best_mask", ctypes.c_int, [_P, _P]),
+    ("dsg_get_loads", ctypes.c_int, [_P, _P]),
+    ("dsg_get_iter_densities", ctypes.c_int, [_P, _P, _P, _P, _I32, _P]),
+    ("dsg_get_order", ctypes.c_int, [_P, _P, _P, _P]),
+    ("dsg_get_iter_digests", ctypes.c_int, [_P, _P, _P, _I32, _P]),
+    ("dsg_graph_destroy", ctypes.c_int, [_P]),
+    ("dsg_last_run_ms", ctypes.c_int, [_P, _P]),
+    ("dsg_last_error", ctypes.c_char_p, []),
+]
+
+
+class DsgError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+def build(force: bool = True) -> str:
+    """Compile libdsg.so for gfx950 (hipcc); see _build.py."""
+    from . import _build
+
+    return _build.build_library(force=force)
+
+
+def library():
+    """The loaded libdsg.so.  Raises RuntimeError if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libdsg.so not found at {LIB_PATH}: build it first "
+                           "(python -c 'import __graft_entry__ as g; g.build()')")
+    # torch ships its own HIP runtime; load it first so that libdsg.so binds
+    # to the same runtime (same SONAME) instead of a second copy from ROCm,
+    # which would own the device separately from torch's allocations
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, res, args in SIGNATURES:
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != 0:
+        msg = library().dsg_last_error()
+        raise DsgError(status, msg.decode() if msg else "")
+
+
+def parse_eps(eps) -> tuple[int, int]:
+    """eps as an exact rational (num, den); a decimal string or float literal is read exactly."""
+    if isinstance(eps, tuple):
+        num, den = int(eps[0]), int(eps[1])
+    else:
+        f = Fraction(str(eps))
+        num, den = f.numerator, f.denominator
+    if num < 0 or den < 1 or num >= 2 ** 31 or den >= 2 ** 31:
+        raise ValueError("eps must be a non-negative rational with 31-bit numerator and denominator")
+    return num, den
+
+
+def workspace_bytes(n: int, nnz: int, t_cap: int) -> int:
+    out = ctypes.c_int64()
+    _check(library().dsg_workspace_bytes(n, nnz, t_cap, ctypes.addressof(out)))
+    return out.value
+
+
+class Context:
+    """A device and a HIP stream (torch's current stream by default)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+
+        self.device = device
+        self.torch_device = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.torch_device)
+        self.stream = stream
+        handle = ctypes.c_void_p()
+        _check(library().dsg_ctx_create(device, ctypes.c_void_p(stream.cuda_stream), ctypes.addressof(handle)))
+        self._h = handle
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            library().dsg_ctx_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Graph:
+    """A CSR graph resident on the device plus its peeling state.
+
+    ``offsets``/``adj`` may be numpy arrays (copied to the device) or int32
+    device tensors (used in place).  The workspace is a torch uint8 tensor
+    owned by this object.
+    """
+
+    def __init__(self, ctx: Context, offsets, adj, t_cap: int = 64, validate: bool = True):
+        import torch
+
+        self.ctx = ctx
+        dev = ctx.torch_device
+        self.offsets = self._dev_i32(offsets, dev)
+        self.adj = self._dev_i32(adj, dev)
+        self.n = int(self.offsets.numel()) - 1
+        self.nnz = int(self.adj.numel())
+        self.m = self.nnz // 2
+        self.t_cap = t_cap
+        nbytes = workspace_bytes(self.n, self.nnz, t_cap)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        handle = ctypes.c_void_p()
+        adj_ptr = self.adj.data_ptr() if self.nnz > 0 else 0
+        _check(library().dsg_graph_create(ctx.handle, self.n, self.nnz, ctypes.c_void_p(self.offsets.data_ptr()),
+                                          ctypes.c_void_p(adj_ptr), ctypes.c_void_p(aligned), nbytes, t_cap,
+                                          VALIDATE if validate else 0, ctypes.addressof(handle)))
+        self._h = handle
+
+    @staticmethod
+    def _dev_i32(x, dev):
+        import torch
+
+        if isinstance(x, torch.Tensor):
+            t = x.to(device=dev, dtype=torch.int32)
+        else:
+            t = torch.from_numpy(np.ascontiguousarray(x, dtype=np.int32)).to(dev)
+        if t.numel() == 0:
+            t = torch.zeros(1, dtype=torch.int32, device=dev)[:0]
+        return t.contiguous()
+
+    # ------------------------------------------------------------ running
+    def run(self, T: int, eps=(0, 1), variant: str = "peel"):
+        num, den = parse_eps(eps)
+        _check(library().dsg_run(self._h, T, num, den, VARIANTS[variant]))
+        return self
+
+    def reset(self):
+        _check(library().dsg_reset(self._h))
+        return self
+
+    def sync(self):
+        _check(library().dsg_sync(self._h))
+
+    def last_run_ms(self) -> float:
+        ms = ctypes.c_float()
+        _check(library().dsg_last_run_ms(self._h, ctypes.addressof(ms)))
+        return ms.value
+
+    # ------------------------------------------------------------ results
+    def best(self):
+        """(edges, vertices, iteration, index) of the best subgraph so far."""
+        e, v = ctypes.c_int64(), ctypes.c_int64()
+        it, idx = ctypes.c_int32(), ctypes.c_int32()
+        _check(library().dsg_get_best(self._h, ctypes.addressof(e), ctypes.addressof(v), ctypes.addressof(it),
+                                      ctypes.addressof(idx)))
+        return e.value, v.value, it.value, idx.value
+
+    def best_mask(self) -> np.ndarray:
+        out = np.zeros(self.n, dtype=np.uint8)
+        _check(library().dsg_get_best_mask(self._h, out.ctypes.data))
+        return out.astype(bool)
+
+    def loads(self) -> np.ndarray:
+        out = np.zeros(self.n, dtype=np.int64)
+        _check(library().dsg_get_loads(self._h, out.ctypes.data))
+        return out
+
+    def iter_densities(self):
+        """Per-iteration densest suffix: list of (edges, vertices, index)."""
+        cnt = ctypes.c_int32()
+        _check(library().dsg_get_iter_densities(self._h, None, None, None, 0, ctypes.addressof(cnt)))
+        k = cnt.value
+        e = np.zeros(max(k, 1), dtype=np.int64)
+        v = np.zeros(max(k, 1), dtype=np.int64)
+        i = np.zeros(max(k, 1), dtype=np.int32)
+        _check(library().dsg_get_iter_densities(self._h, e.ctypes.data, v.ctypes.data, i.ctypes.data, k,
+                                                ctypes.addressof(cnt)))
+        return [(int(e[t]), int(v[t]), int(i[t])) for t in range(k)]
+
+    def order(self):
+        """(round[n], pos[n], number of rounds) of the last iteration."""
+        rnd = np.zeros(self.n, dtype=np.int32)
+        pos = np.zeros(self.n, dtype=np.int32)
+        nr = ctypes.c_int32()
+        _check(library().dsg_get_order(self._h, rnd.ctypes.data, pos.ctypes.data, ctypes.addressof(nr)))
+        return rnd, pos, nr.value
+
+    def digests(self):
+        """(per-iteration order digests, per-iteration round counts)."""
+        cnt = ctypes.c_int32()
+        _check(library().dsg_get_iter_digests(self._h, None, None, 0, ctypes.addressof(cnt)))
+        k = cnt.value
+        d = np.zeros(max(k, 1), dtype=np.uint64)
+        r = np.zeros(max(k, 1), dtype=np.int32)
+        _check(library().dsg_get_iter_digests(self._h, d.ctypes.data, r.ctypes.data, k, ctypes.addressof(cnt)))
+        return [int(x) for x in d[:k]], [int(x) for x in r[:k]]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            library().dsg_graph_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,42 @@
+"""Build step for libdsg.so (hipcc cross-compiles gfx950; no GPU needed)."""
+from __future__ import annotations
+
+import os
+import subprocess
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+SOURCES = [os.path.join(CSRC, "dsg_kernels.hip"), os.path.join(CSRC, "dsg_api.hip")]
+OUT = os.path.join(HERE, "libdsg.so")
+
+HIPCC_FLAGS = [
+    "--offload-arch=gfx950",
+    # code object v5 loads under both torch's bundled HIP runtime and ROCm's
+    "-mcode-object-version=5",
+    "-O3",
+    "-std=c++17",
+    "-fPIC",
+    "-shared",
+    # no packed-FP32 instructions anywhere (the kernels are integer-only)
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wno-unused-command-line-argument",
+]
+
+
+def hipcc() -> str:
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    path = os.path.join(rocm, "bin", "hipcc")
+    return path if os.path.exists(path) else "hipcc"
+
+
+def build_library(force: bool = True, extra=()) -> str:
+    if not force and os.path.exists(OUT):
+        return OUT
+    tmp = OUT + ".tmp"
+    cmd = [hipcc(), *HIPCC_FLAGS, *extra, "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-o", tmp, *SOURCES]
+    res = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    if res.returncode != 0:
+        raise RuntimeError("hipcc failed:\n" + " ".join(cmd) + "\n" + res.stdout)
+    os.replace(tmp, OUT)
+    return OUT

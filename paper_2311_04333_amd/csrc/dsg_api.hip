@@ -1,0 +1,438 @@
+// dsg_api.hip -- the C ABI of libdsg.so (declared in include/dsg.h).
+//
+// Host side only: argument checks, workspace carving, kernel sequencing and
+// result fetches.  Every step of the algorithm runs in the kernels of
+// dsg_kernels.hip.  The library allocates no device memory; all state lives
+// in the caller's workspace.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "dsg.h"
+#include "dsg_device.h"
+#include "dsg_internal.h"
+
+using dsg::GraphDev;
+
+struct dsg_ctx {
+    int device;
+    hipStream_t stream;
+    int num_cu;
+    int peel_grid;
+    int sort_grid;
+};
+
+struct dsg_graph {
+    dsg_ctx* ctx;
+    GraphDev d;
+    char* ws;
+    long long ws_bytes;
+    int t_cap;
+    int recorded;     // iterations recorded in the history
+    int iters_done;   // iterations performed since the last reset (host mirror)
+    int last_variant; // -1 = none yet
+    hipEvent_t ev0, ev1;
+    bool timed;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+dsg_status fail(dsg_status st, const std::string& msg) {
+    g_err = msg;
+    return st;
+}
+
+dsg_status hip_fail(hipError_t e, const char* where) {
+    return fail(DSG_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define DSG_HIP(call, where)                                 \
+    do {                                                     \
+        hipError_t _e = (call);                              \
+        if (_e != hipSuccess) return hip_fail(_e, (where));  \
+    } while (0)
+
+struct Layout {
+    long long off[40];
+    int count = 0;
+    long long total = 0;
+    long long add(long long bytes) {
+        long long at = total;
+        off[count++] = at;
+        total += (bytes + 255) / 256 * 256;
+        return at;
+    }
+};
+
+// Sizes of every workspace region; the same function both sizes and carves.
+long long carve(int n, long long nnz, int t_cap, char* base, GraphDev* g) {
+    Layout L;
+    const long long N = n;
+    const long long nch = nnz / dsg::SWEEP_CH + 2;
+    const long long ntiles = (N + 4095) / 4096 + 1;
+    const long long rtiles = (N + 4095) / 4096 + 1;
+    long long o_ctl = L.add(dsg::ctl_bytes());
+    long long o_load = L.add(4 * N), o_prio = L.add(4 * N), o_rnd = L.add(4 * N), o_inc = L.add(4 * N);
+    long long o_order = L.add(4 * N), o_best = L.add(4 * N);
+    long long o_kA = L.add(4 * N), o_kB = L.add(4 * N), o_vA = L.add(4 * N), o_vB = L.add(4 * N);
+    long long o_L0 = L.add(4 * N), o_L1 = L.add(4 * N), o_iv = L.add(4 * N), o_ie = L.add(4 * (N + 1));
+    long long o_siv = L.add(4 * N), o_sie = L.add(4 * (N + 1)), o_A = L.add(4 * N);
+    long long o_chunk = L.add(4 * nch), o_schunk = L.add(4 * nch);
+    long long o_ts = L.add(8 * ntiles), o_to = L.add(8 * ntiles), o_tb = L.add(24 * ntiles);
+    long long o_rh = L.add(4 * 256 * rtiles);
+    long long o_he = L.add(8LL * t_cap), o_hv = L.add(8LL * t_cap), o_hi = L.add(4LL * t_cap);
+    long long o_rd = L.add(4LL * t_cap), o_dg = L.add(8LL * t_cap);
+    if (base && g) {
+        g->ctl = reinterpret_cast<dsg::Ctl*>(base + o_ctl);
+        g->load = reinterpret_cast<int*>(base + o_load);
+        g->prio = reinterpret_cast<int*>(base + o_prio);
+        g->rnd = reinterpret_cast<int*>(base + o_rnd);
+        g->inc = reinterpret_cast<int*>(base + o_inc);
+        g->order = reinterpret_cast<int*>(base + o_order);
+        g->best_order = reinterpret_cast<int*>(base + o_best);
+        g->kA = reinterpret_cast<int*>(base + o_kA);
+        g->kB = reinterpret_cast<int*>(base + o_kB);
+        g->vA = reinterpret_cast<int*>(base + o_vA);
+        g->vB = reinterpret_cast<int*>(base + o_vB);
+        g->L0 = reinterpret_cast<int*>(base + o_L0);
+        g->L1 = reinterpret_cast<int*>(base + o_L1);
+        g->iv = reinterpret_cast<int*>(base + o_iv);
+        g->ie = reinterpret_cast<int*>(base + o_ie);
+        g->siv = reinterpret_cast<int*>(base + o_siv);
+        g->sie = reinterpret_cast<int*>(base + o_sie);
+        g->A = reinterpret_cast<int*>(base + o_A);
+        g->chunk = reinterpret_cast<int*>(base + o_chunk);
+        g->schunk = reinterpret_cast<int*>(base + o_schunk);
+        g->tile_sum = reinterpret_cast<long long*>(base + o_ts);
+        g->tile_off = reinterpret_cast<long long*>(base + o_to);
+        g->tile_best = reinterpret_cast<long long*>(base + o_tb);
+        g->rhist = reinterpret_cast<int*>(base + o_rh);
+        g->hist_e = reinterpret_cast<long long*>(base + o_he);
+        g->hist_v = reinterpret_cast<long long*>(base + o_hv);
+        g->hist_i = reinterpret_cast<int*>(base + o_hi);
+        g->rounds = reinterpret_cast<int*>(base + o_rd);
+        g->digest = reinterpret_cast<unsigned long long*>(base + o_dg);
+    }
+    return L.total;
+}
+
+const char* err_name(int code) {
+    switch (code) {
+        case dsg::ERR_OFF_FIRST: return "offsets[0] != 0";
+        case dsg::ERR_OFF_LAST: return "offsets[n] != nnz";
+        case dsg::ERR_OFF_DECREASING: return "offsets decrease";
+        case dsg::ERR_ADJ_RANGE: return "adjacency entry outside [0, n)";
+        case dsg::ERR_SELF_LOOP: return "self-loop";
+        case dsg::ERR_ROW_ORDER: return "row not strictly increasing (unsorted or duplicate entry)";
+        case dsg::ERR_ASYMMETRIC: return "CSR not symmetric";
+        case dsg::ERR_INTERNAL: return "internal consistency check failed";
+        default: return "unknown";
+    }
+}
+
+dsg_status read_ctl(dsg_graph* g, dsg::Ctl* out) {
+    DSG_HIP(hipStreamSynchronize(g->ctx->stream), "hipStreamSynchronize");
+    DSG_HIP(hipMemcpy(out, g->d.ctl, sizeof(dsg::Ctl), hipMemcpyDeviceToHost), "hipMemcpy(ctl)");
+    return DSG_OK;
+}
+
+dsg_status check_errors(dsg_graph* g, const char* stage) {
+    dsg::Ctl c;
+    dsg_status st = read_ctl(g, &c);
+    if (st != DSG_OK) return st;
+    if (c.err_count != 0) {
+        char buf[256];
+        snprintf(buf, sizeof buf, "invalid CSR (%s): %s at %s %d (%d problems)", stage, err_name(c.err_code),
+                 c.err_code == dsg::ERR_ADJ_RANGE ? "entry" : "vertex", c.err_vertex, c.err_count);
+        return fail(DSG_EINVAL, buf);
+    }
+    return DSG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* dsg_last_error(void) { return g_err.c_str(); }
+
+dsg_status dsg_ctx_create(int device, void* hip_stream, dsg_ctx** out) {
+    if (!out) return fail(DSG_EINVAL, "out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    DSG_HIP(hipGetDeviceCount(&ndev), "hipGetDeviceCount");
+    if (device < 0 || device >= ndev) return fail(DSG_EDEVICE, "no such device");
+    DSG_HIP(hipSetDevice(device), "hipSetDevice");
+    hipDeviceProp_t prop;
+    DSG_HIP(hipGetDeviceProperties(&prop, device), "hipGetDeviceProperties");
+    if (!prop.cooperativeLaunch) return fail(DSG_EDEVICE, "device lacks cooperative launch");
+    dsg_ctx* c = new (std::nothrow) dsg_ctx();
+    if (!c) return fail(DSG_ENOMEM, "host allocation failed");
+    c->device = device;
+    c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    c->num_cu = prop.multiProcessorCount;
+    int per_cu = dsg::peel_blocks_per_cu();
+    int want = 2;
+    if (const char* e = getenv("DSG_PEEL_BLOCKS_PER_CU")) want = atoi(e);
+    if (want < 1) want = 1;
+    if (per_cu > want) per_cu = want;
+    c->peel_grid = c->num_cu * per_cu;
+    c->sort_grid = c->num_cu * 8;
+    *out = c;
+    return DSG_OK;
+}
+
+dsg_status dsg_ctx_destroy(dsg_ctx* ctx) {
+    delete ctx;
+    return DSG_OK;
+}
+
+dsg_status dsg_workspace_bytes(int32_t n, int64_t nnz, int32_t t_cap, int64_t* bytes) {
+    if (!bytes) return fail(DSG_EINVAL, "bytes is NULL");
+    if (n < 1) return fail(DSG_EINVAL, "n must be >= 1");
+    if (nnz < 0 || nnz >= (1LL << 31)) return fail(DSG_EINVAL, "nnz must be in [0, 2^31)");
+    if (t_cap < 1) return fail(DSG_EINVAL, "t_cap must be >= 1");
+    *bytes = carve(n, nnz, t_cap, nullptr, nullptr);
+    return DSG_OK;
+}
+
+dsg_status dsg_graph_create(dsg_ctx* ctx, int32_t n, int64_t nnz, const int32_t* d_offsets, const int32_t* d_adj,
+                            void* d_workspace, int64_t workspace_bytes, int32_t t_cap, int32_t flags,
+                            dsg_graph** out) {
+    if (!ctx || !out || !d_offsets || !d_workspace) return fail(DSG_EINVAL, "NULL argument");
+    *out = nullptr;
+    if (n < 1) return fail(DSG_EINVAL, "n must be >= 1");
+    if (nnz < 0 || nnz >= (1LL << 31)) return fail(DSG_EINVAL, "nnz must be in [0, 2^31)");
+    if (nnz > 0 && !d_adj) return fail(DSG_EINVAL, "adj is NULL");
+    if (t_cap < 1) return fail(DSG_EINVAL, "t_cap must be >= 1");
+    if (reinterpret_cast<uintptr_t>(d_workspace) % 256 != 0) return fail(DSG_EINVAL, "workspace not 256-byte aligned");
+    long long need = carve(n, nnz, t_cap, nullptr, nullptr);
+    if (workspace_bytes < need) return fail(DSG_ENOMEM, "workspace smaller than dsg_workspace_bytes()");
+    DSG_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    dsg_graph* g = new (std::nothrow) dsg_graph();
+    if (!g) return fail(DSG_ENOMEM, "host allocation failed");
+    g->ctx = ctx;
+    g->ws = static_cast<char*>(d_workspace);
+    g->ws_bytes = workspace_bytes;
+    g->t_cap = t_cap;
+    g->last_variant = -1;
+    g->d.n = n;
+    g->d.nnz = nnz;
+    g->d.off = d_offsets;
+    g->d.adj = d_adj;
+    carve(n, nnz, t_cap, g->ws, &g->d);
+    hipStream_t s = ctx->stream;
+    auto bail = [&](dsg_status st) {
+        delete g;
+        return st;
+    };
+    hipError_t e;
+    if ((e = dsg::launch_zero_ctl(g->d, s)) != hipSuccess) return bail(hip_fail(e, "zero ctl"));
+    if ((e = dsg::launch_check_offsets(g->d, s)) != hipSuccess) return bail(hip_fail(e, "check offsets"));
+    dsg_status st = check_errors(g, "offsets");
+    if (st != DSG_OK) return bail(st);
+    if ((e = dsg::launch_check_range(g->d, s)) != hipSuccess) return bail(hip_fail(e, "check range"));
+    st = check_errors(g, "entries");
+    if (st != DSG_OK) return bail(st);
+    if (flags & DSG_VALIDATE) {
+        if ((e = dsg::launch_check_rows(g->d, s)) != hipSuccess) return bail(hip_fail(e, "check rows"));
+        st = check_errors(g, "rows");
+        if (st != DSG_OK) return bail(st);
+    }
+    if ((e = dsg::launch_build_static_items(g->d, s)) != hipSuccess) return bail(hip_fail(e, "static items"));
+    dsg::Ctl c;
+    st = read_ctl(g, &c);
+    if (st != DSG_OK) return bail(st);
+    long long items = 0;
+    if ((e = hipMemcpy(&items, g->d.tile_off, sizeof(long long), hipMemcpyDeviceToHost)) != hipSuccess)
+        return bail(hip_fail(e, "hipMemcpy(items)"));
+    g->d.n_items = (int)items;
+    g->d.max_deg = c.max_deg;
+    if ((e = dsg::launch_reset_state(g->d, s)) != hipSuccess) return bail(hip_fail(e, "reset"));
+    if ((e = hipEventCreate(&g->ev0)) != hipSuccess) return bail(hip_fail(e, "hipEventCreate"));
+    if ((e = hipEventCreate(&g->ev1)) != hipSuccess) {
+        (void)hipEventDestroy(g->ev0);
+        return bail(hip_fail(e, "hipEventCreate"));
+    }
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) {
+        (void)hipEventDestroy(g->ev0);
+        (void)hipEventDestroy(g->ev1);
+        return bail(hip_fail(e, "hipStreamSynchronize"));
+    }
+    *out = g;
+    return DSG_OK;
+}
+
+dsg_status dsg_run(dsg_graph* g, int32_t T, int32_t eps_num, int32_t eps_den, dsg_variant variant) {
+    if (!g) return fail(DSG_EINVAL, "graph is NULL");
+    if (T < 0) return fail(DSG_EINVAL, "T must be >= 0");
+    if (eps_num < 0 || eps_den < 1) return fail(DSG_EINVAL, "eps must be eps_num >= 0, eps_den >= 1");
+    if (variant != DSG_SEQ && variant != DSG_PEEL && variant != DSG_SORT) return fail(DSG_EINVAL, "unknown variant");
+    if ((long long)g->recorded + T > g->t_cap) return fail(DSG_EINVAL, "T exceeds the history capacity t_cap");
+    if (variant == DSG_SEQ && g->d.n > dsg::SEQ_MAX_N) return fail(DSG_EINVAL, "DSG_SEQ supports n <= 16000");
+    if (variant == DSG_PEEL && g->d.n >= dsg::PEEL_MAX_N) return fail(DSG_EINVAL, "DSG_PEEL supports n < 2^26");
+    // loads grow by at most max_degree per iteration; priorities add one more
+    if (((long long)g->iters_done + T + 1) * (long long)g->d.max_deg >= (1LL << 31))
+        return fail(DSG_EOVERFLOW, "loads could exceed 31 bits");
+    DSG_HIP(hipSetDevice(g->ctx->device), "hipSetDevice");
+    hipStream_t s = g->ctx->stream;
+    DSG_HIP(hipEventRecord(g->ev0, s), "hipEventRecord");
+    for (int t = 0; t < T; t++) {
+        const int slot = g->recorded + t;
+        hipError_t e;
+        if (variant == DSG_PEEL) {
+            e = dsg::enqueue_iter_peel(g->d, slot, eps_num, eps_den, g->ctx->peel_grid, s);
+        } else if (variant == DSG_SORT) {
+            long long bound = (long long)(g->iters_done + t) * (long long)g->d.max_deg;
+            int bits = 0;
+            while (bits < 31 && (bound >> bits) != 0) bits++;
+            e = dsg::enqueue_iter_sort(g->d, slot, bits, g->ctx->sort_grid, s);
+        } else {
+            e = dsg::enqueue_iter_seq(g->d, slot, s);
+        }
+        if (e != hipSuccess) return hip_fail(e, "enqueue iteration");
+    }
+    DSG_HIP(hipEventRecord(g->ev1, s), "hipEventRecord");
+    g->timed = true;
+    g->recorded += T;
+    g->iters_done += T;
+    if (T > 0) g->last_variant = variant;
+    return DSG_OK;
+}
+
+dsg_status dsg_reset(dsg_graph* g) {
+    if (!g) return fail(DSG_EINVAL, "graph is NULL");
+    DSG_HIP(hipSetDevice(g->ctx->device), "hipSetDevice");
+    hipError_t e = dsg::launch_reset_state(g->d, g->ctx->stream);
+    if (e != hipSuccess) return hip_fail(e, "reset");
+    g->recorded = 0;
+    g->iters_done = 0;
+    g->last_variant = -1;
+    g->timed = false;
+    return DSG_OK;
+}
+
+dsg_status dsg_sync(dsg_graph* g) {
+    if (!g) return fail(DSG_EINVAL, "graph is NULL");
+    dsg::Ctl c;
+    dsg_status st = read_ctl(g, &c);
+    if (st != DSG_OK) return st;
+    if (c.err_count != 0) return fail(DSG_EDEVICE, "a kernel consistency check failed");
+    return DSG_OK;
+}
+
+dsg_status dsg_last_run_ms(dsg_graph* g, float* ms) {
+    if (!g || !ms) return fail(DSG_EINVAL, "NULL argument");
+    if (!g->timed) return fail(DSG_ESTATE, "no run recorded");
+    DSG_HIP(hipEventSynchronize(g->ev1), "hipEventSynchronize");
+    DSG_HIP(hipEventElapsedTime(ms, g->ev0, g->ev1), "hipEventElapsedTime");
+    return DSG_OK;
+}
+
+dsg_status dsg_get_best(dsg_graph* g, int64_t* edges, int64_t* verts, int32_t* iter, int32_t* index) {
+    if (!g) return fail(DSG_EINVAL, "graph is NULL");
+    dsg::Ctl c;
+    dsg_status st = read_ctl(g, &c);
+    if (st != DSG_OK) return st;
+    if (edges) *edges = c.best_e;
+    if (verts) *verts = c.best_v;
+    if (iter) *iter = c.best_iter;
+    if (index) *index = (int32_t)c.best_idx;
+    return DSG_OK;
+}
+
+dsg_status dsg_get_best_mask(dsg_graph* g, uint8_t* h_mask) {
+    if (!g || !h_mask) return fail(DSG_EINVAL, "NULL argument");
+    dsg::Ctl c;
+    dsg_status st = read_ctl(g, &c);
+    if (st != DSG_OK) return st;
+    const int n = g->d.n;
+    if (c.best_iter == 0) {
+        memset(h_mask, 1, (size_t)n);
+        return DSG_OK;
+    }
+    std::vector<int32_t> ord((size_t)n);
+    DSG_HIP(hipMemcpy(ord.data(), g->d.best_order, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost),
+            "hipMemcpy(best order)");
+    memset(h_mask, 0, (size_t)n);
+    for (long long i = c.best_idx; i < n; i++) h_mask[ord[(size_t)i]] = 1;
+    return DSG_OK;
+}
+
+dsg_status dsg_get_loads(dsg_graph* g, int64_t* h_loads) {
+    if (!g || !h_loads) return fail(DSG_EINVAL, "NULL argument");
+    DSG_HIP(hipStreamSynchronize(g->ctx->stream), "hipStreamSynchronize");
+    std::vector<int32_t> tmp((size_t)g->d.n);
+    DSG_HIP(hipMemcpy(tmp.data(), g->d.load, sizeof(int32_t) * (size_t)g->d.n, hipMemcpyDeviceToHost),
+            "hipMemcpy(loads)");
+    for (int v = 0; v < g->d.n; v++) h_loads[v] = tmp[(size_t)v];
+    return DSG_OK;
+}
+
+dsg_status dsg_get_iter_densities(dsg_graph* g, int64_t* h_edges, int64_t* h_verts, int32_t* h_index, int32_t cap,
+                                  int32_t* count) {
+    if (!g) return fail(DSG_EINVAL, "graph is NULL");
+    DSG_HIP(hipStreamSynchronize(g->ctx->stream), "hipStreamSynchronize");
+    const int k = cap < g->recorded ? cap : g->recorded;
+    if (k > 0) {
+        if (h_edges)
+            DSG_HIP(hipMemcpy(h_edges, g->d.hist_e, 8 * (size_t)k, hipMemcpyDeviceToHost), "hipMemcpy(hist)");
+        if (h_verts)
+            DSG_HIP(hipMemcpy(h_verts, g->d.hist_v, 8 * (size_t)k, hipMemcpyDeviceToHost), "hipMemcpy(hist)");
+        if (h_index)
+            DSG_HIP(hipMemcpy(h_index, g->d.hist_i, 4 * (size_t)k, hipMemcpyDeviceToHost), "hipMemcpy(hist)");
+    }
+    if (count) *count = g->recorded;
+    return DSG_OK;
+}
+
+dsg_status dsg_get_order(dsg_graph* g, int32_t* h_round, int32_t* h_pos, int32_t* n_rounds) {
+    if (!g) return fail(DSG_EINVAL, "graph is NULL");
+    if (g->last_variant < 0) return fail(DSG_ESTATE, "no iteration has run");
+    DSG_HIP(hipStreamSynchronize(g->ctx->stream), "hipStreamSynchronize");
+    const int n = g->d.n;
+    if (h_round)
+        DSG_HIP(hipMemcpy(h_round, g->d.rnd, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost), "hipMemcpy(round)");
+    if (h_pos) {
+        std::vector<int32_t> ord((size_t)n);
+        DSG_HIP(hipMemcpy(ord.data(), g->d.order, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost),
+                "hipMemcpy(order)");
+        for (int i = 0; i < n; i++) h_pos[ord[(size_t)i]] = i;
+    }
+    if (n_rounds) {
+        int r = 0;
+        DSG_HIP(hipMemcpy(&r, g->d.rounds + (g->recorded - 1), sizeof(int), hipMemcpyDeviceToHost), "hipMemcpy(rounds)");
+        *n_rounds = r;
+    }
+    return DSG_OK;
+}
+
+dsg_status dsg_get_iter_digests(dsg_graph* g, uint64_t* h_digest, int32_t* h_rounds, int32_t cap, int32_t* count) {
+    if (!g) return fail(DSG_EINVAL, "graph is NULL");
+    DSG_HIP(hipStreamSynchronize(g->ctx->stream), "hipStreamSynchronize");
+    const int k = cap < g->recorded ? cap : g->recorded;
+    if (k > 0) {
+        if (h_digest)
+            DSG_HIP(hipMemcpy(h_digest, g->d.digest, 8 * (size_t)k, hipMemcpyDeviceToHost), "hipMemcpy(digest)");
+        if (h_rounds)
+            DSG_HIP(hipMemcpy(h_rounds, g->d.rounds, 4 * (size_t)k, hipMemcpyDeviceToHost), "hipMemcpy(rounds)");
+    }
+    if (count) *count = g->recorded;
+    return DSG_OK;
+}
+
+dsg_status dsg_graph_destroy(dsg_graph* g) {
+    if (!g) return DSG_OK;
+    (void)hipEventDestroy(g->ev0);
+    (void)hipEventDestroy(g->ev1);
+    delete g;
+    return DSG_OK;
+}
+
+}  // extern "C"

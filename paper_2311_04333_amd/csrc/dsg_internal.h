@@ -1,0 +1,106 @@
+// dsg_internal.h -- constants, kernel argument blocks and launchers shared by
+// the kernels (dsg_kernels.hip) and the C ABI (dsg_api.hip).  Internal.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dsg {
+
+struct Ctl;
+
+constexpr int SWEEP_CH = 2048;     // edges per sweep chunk (items per chunk <= this)
+constexpr int PEEL_BLK = 512;      // threads per block of the persistent round kernel
+constexpr int SORT_BLK = 512;      // threads per block of the SORT sweep
+constexpr int SEQ_BLK = 1024;      // threads of the single SEQ block
+constexpr int SEQ_MAX_N = 16000;   // SEQ keeps n priorities in LDS (< 64 KB)
+constexpr int PEEL_MAX_N = 1 << 26;  // frontier item counter has 26 bits
+
+struct PeelArgs {
+    int n;
+    int eps_num;
+    int eps_den;
+    int pad;
+    const int* off;
+    const int* adj;
+    int* prio;
+    int* rnd;
+    int* inc;
+    int* L0;
+    int* L1;
+    int* iv;
+    int* ie;
+    int* chunk_item;
+    Ctl* ctl;
+};
+
+struct SweepArgs {
+    int K;
+    int pad;
+    long long E;
+    const int* iv;
+    const int* ie;
+    const int* chunk_item;
+    const int* off;
+    const int* adj;
+    int* inc;
+    const int* pos;
+    Ctl* ctl;
+};
+
+// Device pointers of one graph's state, carved from the workspace.
+struct GraphDev {
+    int n;
+    long long nnz;
+    const int* off;
+    const int* adj;
+    Ctl* ctl;
+    int* load;
+    int* prio;
+    int* rnd;
+    int* inc;
+    int* order;
+    int* best_order;
+    int* kA;
+    int* kB;
+    int* vA;
+    int* vB;
+    int* L0;
+    int* L1;
+    int* iv;
+    int* ie;
+    int* siv;
+    int* sie;
+    int* A;
+    int* chunk;
+    int* schunk;
+    long long* tile_sum;
+    long long* tile_off;
+    long long* tile_best;
+    int* rhist;
+    long long* hist_e;
+    long long* hist_v;
+    int* hist_i;
+    int* rounds;
+    unsigned long long* digest;
+    int n_items;  // vertices with degree > 0
+    int max_deg;
+};
+
+// launchers (enqueue on `s`; return the first HIP error)
+hipError_t launch_check_offsets(const GraphDev& g, hipStream_t s);
+hipError_t launch_check_range(const GraphDev& g, hipStream_t s);
+hipError_t launch_check_rows(const GraphDev& g, hipStream_t s);
+hipError_t launch_build_static_items(const GraphDev& g, hipStream_t s);
+hipError_t launch_reset_state(const GraphDev& g, hipStream_t s);
+hipError_t launch_zero_ctl(const GraphDev& g, hipStream_t s);
+
+// one iteration; `slot` is the history index written by this iteration
+hipError_t enqueue_iter_peel(const GraphDev& g, int slot, int eps_num, int eps_den, int peel_grid, hipStream_t s);
+hipError_t enqueue_iter_sort(const GraphDev& g, int slot, int key_bits, int sort_grid, hipStream_t s);
+hipError_t enqueue_iter_seq(const GraphDev& g, int slot, hipStream_t s);
+
+int peel_blocks_per_cu();
+int ctl_bytes();
+
+}  // namespace dsg

@@ -1,0 +1,935 @@
+// dsg_kernels.hip -- HIP kernels for the Greedy++ peeling hot path on gfx950.
+//
+// Method: Sukprasert, Liu, Dhulipala, Shun, arXiv 2311.04333.
+//   * ordering of one iteration:
+//       SEQ  -- load ordering of Section 2, one vertex at a time (k_seq_order);
+//       PEEL -- round-synchronous (1+eps)-of-minimum peeling, the parallel
+//               ordering of Section 3.3 (k_peel_init + k_peel_rounds);
+//       SORT -- sort by start-of-iteration load, Sections 3.2/3.3 (radix sort
+//               + k_sort_pos + k_sweep_sort);
+//   * Algorithm 3 (density and load computation): each edge charges its
+//     earlier endpoint (owner-computes sweep), suffix sums over positions, the
+//     densest suffix as an exact rational, loads += charges (k_gather_A,
+//     k_tile_sums, k_suffix_argmax, k_iter_end, k_finalize).
+// All arithmetic is integer.  Device loads are int32; the host guarantees
+// (iterations + 1) * max_degree < 2^31 so loads and priorities cannot wrap.
+#include "dsg_device.h"
+#include "dsg_internal.h"
+
+namespace dsg {
+
+// ================================================================ graph checks
+// Offsets: off[0] == 0, off[n] == nnz, non-decreasing; also max degree.
+__global__ void k_check_offsets(int n, long long nnz, const int* __restrict__ off, Ctl* ctl) {
+    __shared__ int sh[WAVE];
+    int local_max = 0;
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        int a = off[v], b = off[v + 1];
+        if (b < a) {
+            if (atomicAdd(&ctl->err_count, 1) == 0) {
+                ctl->err_code = ERR_OFF_DECREASING;
+                ctl->err_vertex = v;
+            }
+        } else {
+            local_max = max(local_max, b - a);
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (off[0] != 0 && atomicAdd(&ctl->err_count, 1) == 0) {
+            ctl->err_code = ERR_OFF_FIRST;
+            ctl->err_vertex = 0;
+        }
+        if ((long long)off[n] != nnz && atomicAdd(&ctl->err_count, 1) == 0) {
+            ctl->err_code = ERR_OFF_LAST;
+            ctl->err_vertex = n;
+        }
+    }
+    int lane = threadIdx.x & (WAVE - 1);
+    for (int o = WAVE / 2; o > 0; o >>= 1) local_max = max(local_max, __shfl_xor(local_max, o, WAVE));
+    if (lane == 0) atomicMax(&ctl->max_deg, local_max);
+    (void)sh;
+}
+
+// Entries: every adj value in [0, n).  Runs only after the offsets passed.
+__global__ void k_check_range(int n, long long nnz, const int* __restrict__ adj, Ctl* ctl) {
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < nnz;
+         e += (long long)gridDim.x * blockDim.x) {
+        int u = adj[e];
+        if (u < 0 || u >= n) {
+            if (atomicAdd(&ctl->err_count, 1) == 0) {
+                ctl->err_code = ERR_ADJ_RANGE;
+                ctl->err_vertex = (int)(e & 0x7fffffff);
+            }
+        }
+    }
+}
+
+// Full CSR check (DSG_VALIDATE): no self-loops, rows strictly increasing,
+// symmetric (u in row v  =>  v in row u, by binary search).
+__global__ void k_check_rows(int n, const int* __restrict__ off, const int* __restrict__ adj, Ctl* ctl) {
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        int a = off[v], b = off[v + 1];
+        int code = ERR_NONE;
+        for (int e = a; e < b && code == ERR_NONE; e++) {
+            int u = adj[e];
+            if (u == v) code = ERR_SELF_LOOP;
+            else if (e > a && adj[e - 1] >= u) code = ERR_ROW_ORDER;
+            else {
+                int lo = off[u], hi = off[u + 1] - 1;
+                bool found = false;
+                while (lo <= hi) {
+                    int mid = (lo + hi) >> 1;
+                    int w = adj[mid];
+                    if (w == v) { found = true; break; }
+                    if (w < v) lo = mid + 1; else hi = mid - 1;
+                }
+                if (!found) code = ERR_ASYMMETRIC;
+            }
+        }
+        if (code != ERR_NONE && atomicAdd(&ctl->err_count, 1) == 0) {
+            ctl->err_code = code;
+            ctl->err_vertex = v;
+        }
+    }
+}
+
+__global__ void k_ctl_reset(Ctl* ctl, long long m, int n) {
+    if (threadIdx.x == 0) {
+        ctl->best_e = m;
+        ctl->best_v = n;
+        ctl->best_iter = 0;
+        ctl->best_idx = 0;
+        ctl->iters_done = 0;
+        ctl->improved = 0;
+        ctl->nrounds = 0;
+    }
+}
+
+__global__ void k_fill_i32(int* __restrict__ p, int v, long long cnt) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
+         i += (long long)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// ====================================================== generic tile scans
+// Exclusive prefix sum of int32 counts over n entries, in three steps:
+// per-tile sums, a one-block scan of the tile sums, per-tile scan + offset.
+constexpr int SCAN_BLK = 256;
+constexpr int SCAN_ITEMS = 16;
+constexpr int SCAN_TILE = SCAN_BLK * SCAN_ITEMS;
+
+__global__ __launch_bounds__(SCAN_BLK) void k_scan_tile_sums(const int* __restrict__ in, long long n,
+                                                             long long* __restrict__ tile_sum) {
+    __shared__ long long sh[SCAN_BLK / WAVE];
+    long long base = (long long)blockIdx.x * SCAN_TILE;
+    long long s = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; k++) {
+        long long i = base + k * SCAN_BLK + threadIdx.x;
+        if (i < n) s += in[i];
+    }
+    s = block_sum<SCAN_BLK>(s, sh);
+    if (threadIdx.x == 0) tile_sum[blockIdx.x] = s;
+}
+
+// One block: exclusive scan of tile sums in place; total into *total.
+__global__ __launch_bounds__(1024) void k_scan_top(long long* __restrict__ tile_sum, int ntiles,
+                                                   long long* __restrict__ total) {
+    __shared__ long long sh[1024 / WAVE];
+    long long carry = 0;
+    for (int base = 0; base < ntiles; base += 1024) {
+        int i = base + threadIdx.x;
+        long long v = i < ntiles ? tile_sum[i] : 0;
+        long long tot;
+        long long ex = block_excl_scan<1024>(v, &tot, sh);
+        if (i < ntiles) tile_sum[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0 && total) *total = carry;
+}
+
+// ============================================================ radix sort
+// Stable LSD radix sort of (key, value) int32 pairs by 8-bit digits.  Tile
+// = 256 threads x 16 items.  Inside a tile, wave w owns the contiguous items
+// [w*1024, (w+1)*1024) and walks them in 16 steps of 64 consecutive items.
+// The stable rank among equal digits in a step comes from 8 ballots; the
+// earlier steps of the wave and the earlier waves of the tile come from LDS
+// counters; the earlier tiles come from the scanned digit-major histogram.
+constexpr int RBLK = 256;
+constexpr int RITEMS = 16;
+constexpr int RTILE = RBLK * RITEMS;
+constexpr int RBINS = 256;
+
+// Pass activity: for the PEEL sort by round the number of significant bits
+// is known only on the device (ctl->nrounds); a pass above it is inactive
+// and becomes a plain copy so the result lands in the same buffer.
+__device__ __forceinline__ bool pass_active(const Ctl* ctl, int shift, int dyn) {
+    if (!dyn || shift == 0) return true;
+    unsigned int maxkey = (unsigned int)max(ctl->nrounds - 1, 0);
+    return (maxkey >> shift) != 0;
+}
+
+__global__ __launch_bounds__(RBLK) void k_radix_hist(const int* __restrict__ keys, int n, int shift,
+                                                     int* __restrict__ hist, int ntiles, const Ctl* ctl,
+                                                     int dyn) {
+    if (!pass_active(ctl, shift, dyn)) return;
+    __shared__ int h[RBINS];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    int base = blockIdx.x * RTILE;
+#pragma unroll
+    for (int k = 0; k < RITEMS; k++) {
+        int i = base + k * RBLK + threadIdx.x;
+        if (i < n) atomicAdd(&h[((unsigned int)keys[i] >> shift) & 0xFF], 1);
+    }
+    __syncthreads();
+    hist[threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
+}
+
+// digit-major exclusive scan of hist[RBINS * ntiles], single block
+__global__ __launch_bounds__(1024) void k_radix_scan(int* __restrict__ hist, int total, const Ctl* ctl, int shift,
+                                                     int dyn) {
+    if (!pass_active(ctl, shift, dyn)) return;
+    __shared__ int sh[1024 / WAVE];
+    // each thread owns a contiguous segment
+    int per = (total + 1023) / 1024;
+    int beg = min(total, threadIdx.x * per), end = min(total, beg + per);
+    int s = 0;
+    for (int i = beg; i < end; i++) s += hist[i];
+    int tot;
+    int ex = block_excl_scan<1024>(s, &tot, sh);
+    for (int i = beg; i < end; i++) {
+        int c = hist[i];
+        hist[i] = ex;
+        ex += c;
+    }
+}
+
+// keys_in: key of item i; vals_in: value of item i (nullptr = i itself).
+// keys_out may be nullptr (last pass).  Inactive pass: copy.
+__global__ __launch_bounds__(RBLK) void k_radix_scatter(const int* __restrict__ keys_in,
+                                                        const int* __restrict__ vals_in, int* __restrict__ keys_out,
+                                                        int* __restrict__ vals_out, int n, int shift,
+                                                        const int* __restrict__ hist, int ntiles, const Ctl* ctl,
+                                                        int dyn) {
+    const int tid = threadIdx.x;
+    const int lane = tid & (WAVE - 1);
+    const int wid = tid / WAVE;
+    const int base = blockIdx.x * RTILE;
+    if (!pass_active(ctl, shift, dyn)) {
+        for (int k = 0; k < RITEMS; k++) {
+            int i = base + k * RBLK + tid;
+            if (i < n) {
+                if (keys_out) keys_out[i] = keys_in[i];
+                vals_out[i] = vals_in ? vals_in[i] : i;
+            }
+        }
+        return;
+    }
+    __shared__ int wcnt[RBLK / WAVE][RBINS];
+    __shared__ int tbase[RBINS];
+    for (int d = tid; d < RBINS * (RBLK / WAVE); d += RBLK) (&wcnt[0][0])[d] = 0;
+    __syncthreads();
+    int key[RITEMS], rank[RITEMS];
+    const unsigned long long lower = (lane == 0) ? 0ull : (~0ull >> (WAVE - lane));
+    const int wbase = base + wid * (WAVE * RITEMS);
+#pragma unroll
+    for (int s = 0; s < RITEMS; s++) {
+        int i = wbase + s * WAVE + lane;
+        bool ok = i < n;
+        int k = ok ? keys_in[i] : 0;
+        key[s] = k;
+        unsigned int d = ((unsigned int)k >> shift) & 0xFF;
+        unsigned long long peers = __ballot(ok);
+#pragma unroll
+        for (int b = 0; b < 8; b++) {
+            unsigned long long m = __ballot((d >> b) & 1);
+            peers &= ((d >> b) & 1) ? m : ~m;
+        }
+        int before = __popcll(peers & lower);
+        int prev = ok ? wcnt[wid][d] : 0;
+        rank[s] = prev + before;
+        // all lanes of the wave have read the counter before any lane updates it
+        __builtin_amdgcn_wave_barrier();
+        if (ok && before == 0) wcnt[wid][d] = prev + __popcll(peers);
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    // per digit: global base of this tile + counts of earlier waves
+    {
+        int d = tid;  // RBLK == RBINS
+        int run = hist[d * ntiles + blockIdx.x];
+        tbase[d] = run;
+#pragma unroll
+        for (int w = 0; w < RBLK / WAVE; w++) {
+            int c = wcnt[w][d];
+            wcnt[w][d] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < RITEMS; s++) {
+        int i = wbase + s * WAVE + lane;
+        if (i < n) {
+            unsigned int d = ((unsigned int)key[s] >> shift) & 0xFF;
+            int dst = wcnt[wid][d] + rank[s];
+            if (keys_out) keys_out[dst] = key[s];
+            vals_out[dst] = vals_in ? vals_in[i] : i;
+        }
+    }
+    (void)tbase;
+}
+
+// ============================================================ static items
+// Items of the full graph for the SORT sweep: every vertex with degree > 0,
+// in id order, with its edge start; chunk_item[c] = item containing edge c*CH.
+__global__ void k_nonzero_flags(int n, const int* __restrict__ off, int* __restrict__ flag) {
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+        flag[v] = off[v + 1] > off[v] ? 1 : 0;
+}
+
+__global__ __launch_bounds__(SCAN_BLK) void k_compact_items(int n, const int* __restrict__ off,
+                                                            const long long* __restrict__ tile_off,
+                                                            int* __restrict__ iv, int* __restrict__ ie,
+                                                            int* __restrict__ chunk_item) {
+    __shared__ int sh[SCAN_BLK / WAVE];
+    long long base = (long long)blockIdx.x * SCAN_TILE;
+    long long run = tile_off[blockIdx.x];
+    for (int k = 0; k < SCAN_ITEMS; k++) {
+        long long v = base + k * SCAN_BLK + threadIdx.x;
+        int a = 0, b = 0, f = 0;
+        if (v < n) {
+            a = off[v];
+            b = off[v + 1];
+            f = b > a;
+        }
+        int tot;
+        int ex = block_excl_scan<SCAN_BLK>(f, &tot, sh);
+        if (f) {
+            int item = (int)(run + ex);
+            iv[item] = (int)v;
+            ie[item] = a;
+            for (long long c = ((long long)a + SWEEP_CH - 1) / SWEEP_CH; c * SWEEP_CH < b; c++) chunk_item[c] = item;
+        }
+        run += tot;
+    }
+}
+
+// ========================================================== edge sweep
+// Edge-balanced sweep over the concatenated rows of an item list.  Block b
+// takes chunks c = b, b + grid, ... of SWEEP_CH consecutive edges; the items
+// overlapping a chunk (at most SWEEP_CH, since every item has an edge in it)
+// are staged in LDS, and each thread finds its edge's item by binary search
+// there.  Per-item counts are gathered in LDS and added to inc[] once per
+// chunk.  Op decides what an edge (v, u) contributes.
+struct SweepLds {
+    int fe[SWEEP_CH];
+    int row[SWEEP_CH];
+    int v[SWEEP_CH];
+    int cnt[SWEEP_CH];
+    int aux[SWEEP_CH];
+};
+
+template <int BLK, class Op>
+__device__ __forceinline__ void sweep_chunks(int K, long long E, const int* __restrict__ iv, const int* __restrict__ ie,
+                                             const int* __restrict__ chunk_item, const int* __restrict__ off,
+                                             const int* __restrict__ adj, int* __restrict__ inc, Op& op,
+                                             SweepLds& s, int block, int nblocks) {
+    const long long nchunks = (E + SWEEP_CH - 1) / SWEEP_CH;
+    for (long long c = block; c < nchunks; c += nblocks) {
+        const long long x0 = c * SWEEP_CH;
+        const long long x1 = min(E, x0 + SWEEP_CH);
+        const int k0 = chunk_item[c];
+        int k1;
+        if (c + 1 < nchunks) {
+            k1 = chunk_item[c + 1];
+            if ((long long)ie[k1] == x1) k1 -= 1;
+        } else {
+            k1 = K - 1;
+        }
+        const int nitems = k1 - k0 + 1;
+        if (nitems < 1 || nitems > SWEEP_CH) {
+            // impossible when every item has an edge in the chunk; refuse to
+            // index LDS out of range if the item list is ever inconsistent
+            if (threadIdx.x == 0) op.flag_error();
+            continue;
+        }
+        for (int j = threadIdx.x; j < nitems; j += BLK) {
+            int v = iv[k0 + j];
+            s.fe[j] = ie[k0 + j];
+            s.v[j] = v;
+            s.row[j] = off[v];
+            s.cnt[j] = 0;
+            s.aux[j] = op.item_aux(v);
+        }
+        __syncthreads();
+        for (long long x = x0 + threadIdx.x; x < x1; x += BLK) {
+            int lo = 0, hi = nitems - 1;
+            while (lo < hi) {
+                int mid = (lo + hi + 1) >> 1;
+                if ((long long)s.fe[mid] <= x) lo = mid; else hi = mid - 1;
+            }
+            const int v = s.v[lo];
+            const int u = adj[s.row[lo] + (int)(x - s.fe[lo])];
+            if (op.edge(v, u, s.aux[lo])) atomicAdd(&s.cnt[lo], 1);
+        }
+        __syncthreads();
+        for (int j = threadIdx.x; j < nitems; j += BLK)
+            if (s.cnt[j]) atomicAdd(&inc[s.v[j]], s.cnt[j]);
+        __syncthreads();
+    }
+}
+
+// ============================================================== PEEL
+// Iteration start: prio = load + degree, round = -1 (alive), charge = 0;
+// the minimum priority seeds round 0.
+__global__ __launch_bounds__(256) void k_peel_init(int n, const int* __restrict__ off, const int* __restrict__ load,
+                                                   int* __restrict__ prio, int* __restrict__ rnd,
+                                                   int* __restrict__ inc, Ctl* ctl) {
+    __shared__ unsigned int sh[256 / WAVE];
+    unsigned int lmin = 0xFFFFFFFFu;
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        int p = load[v] + (off[v + 1] - off[v]);
+        prio[v] = p;
+        rnd[v] = -1;
+        inc[v] = 0;
+        lmin = min(lmin, (unsigned int)p);
+    }
+    lmin = block_min<256>(lmin, sh);
+    if (threadIdx.x == 0) atomicMin(&ctl->mn[0], lmin);
+}
+
+__global__ void k_iter_begin(Ctl* ctl) {
+    if (threadIdx.x < 4) {
+        ctl->mn[threadIdx.x] = 0xFFFFFFFFu;
+        ctl->lcnt[threadIdx.x] = 0;
+        ctl->fcnt[threadIdx.x] = 0;
+    }
+    if (threadIdx.x == 0) {
+        ctl->bar_count = 0;
+        ctl->nrounds = 0;
+        ctl->improved = 0;
+    }
+}
+
+struct PeelEdgeOp {
+    const int* rnd;
+    int* prio;
+    int r;
+    unsigned int lmin;
+    Ctl* ctl;
+    __device__ void flag_error() { atomicAdd(&ctl->err_count, 1); ctl->err_code = ERR_INTERNAL; }
+    __device__ __forceinline__ int item_aux(int) const { return 0; }
+    __device__ __forceinline__ bool edge(int v, int u, int) {
+        const int ru = rnd[u];
+        if (ru < 0) {
+            // u survives the round: it loses one degree, and its new priority
+            // is a candidate for the next round's minimum (its last decrement
+            // yields its final value)
+            const int old = atomicSub(&prio[u], 1);
+            lmin = min(lmin, (unsigned int)(old - 1));
+            return true;
+        }
+        // same-round edge: charged to the lower id
+        return ru == r && u > v;
+    }
+};
+
+constexpr unsigned long long FCNT_SHIFT = 38;
+constexpr unsigned long long FCNT_MASK = (1ull << FCNT_SHIFT) - 1;
+
+// Persistent round loop of one PEEL iteration (cooperative launch).  Per
+// round r:
+//   select: mn = ring.mn[r]; thr = floor((q + p) mn / q); every alive vertex
+//     of the list L_r with prio <= thr is marked round r and, if it has
+//     edges, appended to the item list with its edge start (one packed 64-bit
+//     atomic per block keeps items and edge offsets consistent).  Others go
+//     to L_{r+1} and offer their priority to ring.mn[r+1].
+//   barrier
+//   sweep: edge-balanced over the round's items (PeelEdgeOp).
+//   barrier
+// L_0 is implicit (all vertices).  The loop ends when L_r is empty; every
+// block reads the same counters after a barrier, so all leave together.
+__global__ __launch_bounds__(PEEL_BLK) void k_peel_rounds(PeelArgs a) {
+    __shared__ SweepLds s;
+    __shared__ unsigned long long shs[PEEL_BLK / WAVE];
+    __shared__ unsigned int shm[PEEL_BLK / WAVE];
+    __shared__ unsigned long long s_fbase;
+    __shared__ unsigned int s_lbase;
+    Ctl* ctl = a.ctl;
+    const unsigned int nblocks = gridDim.x;
+    const long long q = a.eps_den, p = a.eps_num;
+    int prevLc = a.n + 1;
+    for (int r = 0;; r++) {
+        const int slot = r & 3, nslot = (r + 1) & 3;
+        const unsigned int mn = __hip_atomic_load(&ctl->mn[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int Lc = (r == 0) ? a.n
+                                : (int)__hip_atomic_load(&ctl->lcnt[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (Lc == 0) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) ctl->nrounds = r;
+            break;
+        }
+        if (Lc >= prevLc) {
+            // every round peels the minimum vertex, so the alive count must
+            // fall; all blocks see the same counts and leave together
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                ctl->nrounds = r;
+                atomicAdd(&ctl->err_count, 1);
+                ctl->err_code = ERR_INTERNAL;
+            }
+            break;
+        }
+        prevLc = Lc;
+        const long long thr = ((q + p) * (long long)mn) / q;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            const int zs = (r + 2) & 3;
+            ctl->mn[zs] = 0xFFFFFFFFu;
+            ctl->lcnt[zs] = 0;
+            ctl->fcnt[zs] = 0;
+        }
+        const int* __restrict__ Lin = (r & 1) ? a.L1 : a.L0;
+        int* __restrict__ Lout = (r & 1) ? a.L0 : a.L1;
+        unsigned int lmin = 0xFFFFFFFFu;
+        // ---------------- select
+        for (int base = blockIdx.x * PEEL_BLK; base < Lc; base += nblocks * PEEL_BLK) {
+            const int idx = base + threadIdx.x;
+            int u = -1, d = 0;
+            bool isItem = false, isSurv = false;
+            if (idx < Lc) {
+                u = (r == 0) ? idx : Lin[idx];
+                const int pu = a.prio[u];
+                if ((long long)pu <= thr) {
+                    a.rnd[u] = r;
+                    d = a.off[u + 1] - a.off[u];
+                    isItem = d > 0;
+                } else {
+                    isSurv = true;
+                    lmin = min(lmin, (unsigned int)pu);
+                }
+            }
+            // packed local scan: [edges:32][survivors:11][items:11]
+            unsigned long long val = (isItem ? ((1ull << 43) | (unsigned long long)d) : 0ull) |
+                                     (isSurv ? (1ull << 32) : 0ull);
+            unsigned long long tot;
+            unsigned long long ex = block_excl_scan<PEEL_BLK>(val, &tot, shs);
+            if (threadIdx.x == 0) {
+                const unsigned long long titems = tot >> 43, tsurv = (tot >> 32) & 0x7FF,
+                                         tedges = tot & 0xFFFFFFFFull;
+                s_fbase = (titems | tedges) ? atomicAdd(&ctl->fcnt[slot], (titems << FCNT_SHIFT) | tedges) : 0ull;
+                s_lbase = tsurv ? atomicAdd(&ctl->lcnt[nslot], (unsigned int)tsurv) : 0u;
+            }
+            __syncthreads();
+            if (isItem) {
+                const unsigned long long fb = s_fbase;
+                const int item = (int)((fb >> FCNT_SHIFT) + (ex >> 43));
+                const long long start = (long long)(fb & FCNT_MASK) + (long long)(ex & 0xFFFFFFFFull);
+                a.iv[item] = u;
+                a.ie[item] = (int)start;
+                for (long long c = (start + SWEEP_CH - 1) / SWEEP_CH; c * SWEEP_CH < start + d; c++)
+                    a.chunk_item[c] = item;
+            }
+            if (isSurv) Lout[s_lbase + (unsigned int)((ex >> 32) & 0x7FF)] = u;
+            __syncthreads();
+        }
+        grid_barrier(ctl, nblocks);
+        // ---------------- sweep
+        const unsigned long long f = __hip_atomic_load(&ctl->fcnt[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int K = (int)(f >> FCNT_SHIFT);
+        const long long E = (long long)(f & FCNT_MASK);
+        PeelEdgeOp op{a.rnd, a.prio, r, lmin, ctl};
+        sweep_chunks<PEEL_BLK>(K, E, a.iv, a.ie, a.chunk_item, a.off, a.adj, a.inc, op, s, blockIdx.x, nblocks);
+        const unsigned int bmin = block_min<PEEL_BLK>(op.lmin, shm);
+        if (threadIdx.x == 0 && bmin != 0xFFFFFFFFu) atomicMin(&ctl->mn[nslot], bmin);
+        grid_barrier(ctl, nblocks);
+    }
+}
+
+// ============================================================== SORT
+// pos[order[i]] = i (kept in rnd[], which is the "round" of SORT), charge 0.
+__global__ void k_sort_pos(int n, const int* __restrict__ order, int* __restrict__ rnd, int* __restrict__ inc) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        rnd[order[i]] = i;
+        inc[i] = 0;
+    }
+}
+
+struct SortEdgeOp {
+    const int* pos;
+    Ctl* ctl;
+    __device__ void flag_error() { atomicAdd(&ctl->err_count, 1); ctl->err_code = ERR_INTERNAL; }
+    __device__ __forceinline__ int item_aux(int v) const { return pos[v]; }
+    // the edge is charged to v when v comes first in the order
+    __device__ __forceinline__ bool edge(int, int u, int pv) const { return pos[u] > pv; }
+};
+
+__global__ __launch_bounds__(SORT_BLK) void k_sweep_sort(SweepArgs a) {
+    __shared__ SweepLds s;
+    SortEdgeOp op{a.pos, a.ctl};
+    sweep_chunks<SORT_BLK>(a.K, a.E, a.iv, a.ie, a.chunk_item, a.off, a.adj, a.inc, op, s, blockIdx.x, gridDim.x);
+}
+
+// =============================================================== SEQ
+// One block runs the n single-vertex steps of the sequential load ordering.
+// prio (load + current degree) lives in LDS; a peeled vertex gets the key
+// 0xFFFFFFFF.  Each step: block argmin of (prio, id), record, decrement the
+// neighbours still present.
+__global__ __launch_bounds__(SEQ_BLK) void k_seq_order(int n, const int* __restrict__ off,
+                                                       const int* __restrict__ adj, const int* __restrict__ load,
+                                                       int* __restrict__ order, int* __restrict__ rnd,
+                                                       int* __restrict__ inc) {
+    extern __shared__ unsigned int sprio[];
+    __shared__ unsigned long long shk[SEQ_BLK / WAVE];
+    __shared__ int s_win;
+    for (int v = threadIdx.x; v < n; v += SEQ_BLK) sprio[v] = (unsigned int)(load[v] + (off[v + 1] - off[v]));
+    __syncthreads();
+    for (int j = 0; j < n; j++) {
+        unsigned long long best = ~0ull;
+        for (int v = threadIdx.x; v < n; v += SEQ_BLK) {
+            unsigned long long k = ((unsigned long long)sprio[v] << 32) | (unsigned int)v;
+            best = k < best ? k : best;
+        }
+        best = block_min<SEQ_BLK>(best, shk);
+        const int w = (int)(best & 0xFFFFFFFFull);
+        if (threadIdx.x == 0) {
+            order[j] = w;
+            rnd[w] = j;
+            inc[w] = (int)sprio[w] - load[w];
+            sprio[w] = 0xFFFFFFFFu;
+            s_win = w;
+        }
+        __syncthreads();
+        const int a0 = off[s_win], a1 = off[s_win + 1];
+        for (int e = a0 + threadIdx.x; e < a1; e += SEQ_BLK) {
+            const int u = adj[e];
+            if (sprio[u] != 0xFFFFFFFFu) sprio[u] -= 1;
+        }
+        __syncthreads();
+    }
+}
+
+// ======================================================== Algorithm 3
+// A[i] = charge of the vertex at position i; per-tile sums.
+__global__ __launch_bounds__(SCAN_BLK) void k_gather_A(int n, const int* __restrict__ order,
+                                                       const int* __restrict__ inc, int* __restrict__ A,
+                                                       long long* __restrict__ tile_sum) {
+    __shared__ long long sh[SCAN_BLK / WAVE];
+    long long base = (long long)blockIdx.x * SCAN_TILE;
+    long long s = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; k++) {
+        long long i = base + k * SCAN_BLK + threadIdx.x;
+        if (i < n) {
+            int x = inc[order[i]];
+            A[i] = x;
+            s += x;
+        }
+    }
+    s = block_sum<SCAN_BLK>(s, sh);
+    if (threadIdx.x == 0) tile_sum[blockIdx.x] = s;
+}
+
+// One block: suffix offsets of tiles, off[b] = sum of tiles after b.
+__global__ __launch_bounds__(1024) void k_suffix_top(const long long* __restrict__ tile_sum,
+                                                     long long* __restrict__ tile_off, int ntiles) {
+    __shared__ long long sh[1024 / WAVE];
+    long long carry = 0;
+    // walk tiles from the end; reversed index r = ntiles-1-b
+    for (int base = 0; base < ntiles; base += 1024) {
+        int rr = base + threadIdx.x;
+        int b = ntiles - 1 - rr;
+        long long v = rr < ntiles ? tile_sum[b] : 0;
+        long long tot;
+        long long ex = block_excl_scan<1024>(v, &tot, sh);
+        if (rr < ntiles) tile_off[b] = carry + ex;
+        carry += tot;
+    }
+}
+
+struct Cand {
+    long long e, v, i;
+};
+
+// a better than b: strictly denser, or equally dense with a smaller index
+__device__ __forceinline__ bool cand_better(const Cand& a, const Cand& b) {
+    long long l = a.e * b.v, r = b.e * a.v;
+    return l > r || (l == r && a.i < b.i);
+}
+
+__device__ __forceinline__ Cand cand_shfl(const Cand& c, int o) {
+    return Cand{__shfl_xor(c.e, o, WAVE), __shfl_xor(c.v, o, WAVE), __shfl_xor(c.i, o, WAVE)};
+}
+
+template <int BLK>
+__device__ __forceinline__ Cand block_best(Cand c, Cand* sh) {
+    constexpr int NW = BLK / WAVE;
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) {
+        Cand w = cand_shfl(c, o);
+        if (cand_better(w, c)) c = w;
+    }
+    const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
+    if (lane == 0) sh[wid] = c;
+    __syncthreads();
+    Cand b = sh[0];
+#pragma unroll
+    for (int w = 1; w < NW; w++)
+        if (cand_better(sh[w], b)) b = sh[w];
+    __syncthreads();
+    return b;
+}
+
+// Per tile: B[i] = (suffix of later tiles) + sum of A[j], j >= i in the tile;
+// candidate i has (B[i], n - i); the tile's densest, ties to smallest i.
+// Thread t owns items [base + 16t, base + 16t + 16) (contiguous).
+__global__ __launch_bounds__(SCAN_BLK) void k_suffix_argmax(int n, const int* __restrict__ A,
+                                                            const long long* __restrict__ tile_off,
+                                                            long long* __restrict__ tile_best) {
+    __shared__ long long sh[SCAN_BLK / WAVE];
+    __shared__ Cand shc[SCAN_BLK / WAVE];
+    const long long base = (long long)blockIdx.x * SCAN_TILE + (long long)threadIdx.x * SCAN_ITEMS;
+    int x[SCAN_ITEMS];
+    long long mysum = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; k++) {
+        long long i = base + k;
+        x[k] = i < n ? A[i] : 0;
+        mysum += x[k];
+    }
+    // suffix over threads: reverse-order exclusive scan
+    long long tot;
+    // exclusive scan in forward order gives sum of earlier threads; suffix = tot - excl - mine
+    long long ex = block_excl_scan<SCAN_BLK>(mysum, &tot, sh);
+    long long suffix_after = tile_off[blockIdx.x] + (tot - ex - mysum);
+    Cand best{-1, 1, 0x7FFFFFFFFFFFFFFFll};
+    long long run = suffix_after;
+#pragma unroll
+    for (int k = SCAN_ITEMS - 1; k >= 0; k--) {
+        long long i = base + k;
+        run += x[k];
+        if (i < n) {
+            Cand c{run, (long long)n - i, i};
+            if (best.e < 0 || cand_better(c, best)) best = c;
+        }
+    }
+    best = block_best<SCAN_BLK>(best, shc);
+    if (threadIdx.x == 0) {
+        tile_best[3 * blockIdx.x] = best.e;
+        tile_best[3 * blockIdx.x + 1] = best.v;
+        tile_best[3 * blockIdx.x + 2] = best.i;
+    }
+}
+
+// One block: the iteration's densest suffix, history record, best update.
+__global__ __launch_bounds__(1024) void k_iter_end(const long long* __restrict__ tile_best, int ntiles, Ctl* ctl,
+                                                   long long* __restrict__ hist_e, long long* __restrict__ hist_v,
+                                                   int* __restrict__ hist_i, unsigned long long* __restrict__ digest,
+                                                   int* __restrict__ rounds, int slot, int nrounds_static) {
+    __shared__ Cand shc[1024 / WAVE];
+    Cand best{-1, 1, 0x7FFFFFFFFFFFFFFFll};
+    for (int b = threadIdx.x; b < ntiles; b += 1024) {
+        Cand c{tile_best[3 * b], tile_best[3 * b + 1], tile_best[3 * b + 2]};
+        if (c.e >= 0 && (best.e < 0 || cand_better(c, best))) best = c;
+    }
+    best = block_best<1024>(best, shc);
+    if (threadIdx.x == 0) {
+        hist_e[slot] = best.e;
+        hist_v[slot] = best.v;
+        hist_i[slot] = (int)best.i;
+        digest[slot] = 0;
+        rounds[slot] = nrounds_static > 0 ? nrounds_static : ctl->nrounds;
+        const int it = ctl->iters_done + 1;
+        ctl->iters_done = it;
+        // strict improvement only (the input graph is the initial best)
+        if (best.e * ctl->best_v > ctl->best_e * best.v) {
+            ctl->best_e = best.e;
+            ctl->best_v = best.v;
+            ctl->best_iter = it;
+            ctl->best_idx = best.i;
+            ctl->improved = 1;
+        } else {
+            ctl->improved = 0;
+        }
+    }
+}
+
+// load += charge; digest of (v, round); snapshot of the order on improvement.
+__global__ __launch_bounds__(256) void k_finalize(int n, int* __restrict__ load, const int* __restrict__ inc,
+                                                  const int* __restrict__ rnd, const int* __restrict__ order,
+                                                  int* __restrict__ best_order, const Ctl* ctl,
+                                                  unsigned long long* __restrict__ digest_slot) {
+    __shared__ unsigned long long sh[256 / WAVE];
+    const bool improved = ctl->improved != 0;
+    unsigned long long h = 0;
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        load[v] += inc[v];
+        h += mix64(((unsigned long long)(unsigned int)v << 32) | (unsigned long long)(unsigned int)rnd[v]);
+        if (improved) best_order[v] = order[v];
+    }
+    h = block_sum<256>(h, sh);
+    if (threadIdx.x == 0) atomicAdd(digest_slot, h);
+}
+
+// ================================================================= launchers
+namespace {
+inline int grid_for(long long n, int blk, int cap = 4096) {
+    long long g = (n + blk - 1) / blk;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+inline int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
+}  // namespace
+
+int ctl_bytes() { return (int)sizeof(Ctl); }
+
+int peel_blocks_per_cu() {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(k_peel_rounds), PEEL_BLK, 0) !=
+        hipSuccess)
+        return 1;
+    return nb < 1 ? 1 : nb;
+}
+
+hipError_t launch_zero_ctl(const GraphDev& g, hipStream_t s) {
+    const int words = (int)(sizeof(Ctl) / sizeof(int));
+    k_fill_i32<<<1, 256, 0, s>>>(reinterpret_cast<int*>(g.ctl), 0, words);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_offsets(const GraphDev& g, hipStream_t s) {
+    k_check_offsets<<<grid_for(g.n, 256), 256, 0, s>>>(g.n, g.nnz, g.off, g.ctl);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_range(const GraphDev& g, hipStream_t s) {
+    if (g.nnz > 0) k_check_range<<<grid_for(g.nnz, 256, 16384), 256, 0, s>>>(g.n, g.nnz, g.adj, g.ctl);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_rows(const GraphDev& g, hipStream_t s) {
+    k_check_rows<<<grid_for(g.n, 256), 256, 0, s>>>(g.n, g.off, g.adj, g.ctl);
+    return hipGetLastError();
+}
+
+hipError_t launch_build_static_items(const GraphDev& g, hipStream_t s) {
+    const int ntiles = ceil_div(g.n, SCAN_TILE);
+    k_nonzero_flags<<<grid_for(g.n, 256), 256, 0, s>>>(g.n, g.off, g.A);
+    k_scan_tile_sums<<<ntiles, SCAN_BLK, 0, s>>>(g.A, g.n, g.tile_sum);
+    k_scan_top<<<1, 1024, 0, s>>>(g.tile_sum, ntiles, g.tile_off);
+    // tile_off[0] receives the total after the scan of tile_sum in place; the
+    // compaction reads the scanned tile_sum as its offsets
+    k_compact_items<<<ntiles, SCAN_BLK, 0, s>>>(g.n, g.off, g.tile_sum, g.siv, g.sie, g.schunk);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset_state(const GraphDev& g, hipStream_t s) {
+    k_fill_i32<<<grid_for(g.n, 256), 256, 0, s>>>(g.load, 0, g.n);
+    k_ctl_reset<<<1, 64, 0, s>>>(g.ctl, g.nnz / 2, g.n);
+    return hipGetLastError();
+}
+
+// Stable LSD radix sort of the n vertex ids by key_src[v] over `passes`
+// 8-bit digits; the sorted ids land in g.order.  dyn = 1: passes above the
+// device-known key range (ctl->nrounds) become copies.
+static hipError_t enqueue_radix(const GraphDev& g, const int* key_src, int passes, int dyn, hipStream_t s) {
+    const int rt = ceil_div(g.n, RTILE);
+    for (int p = 0; p < passes; p++) {
+        const int shift = 8 * p;
+        const int* kin = p == 0 ? key_src : ((p - 1) & 1 ? g.kB : g.kA);
+        const int* vin = p == 0 ? nullptr : ((p - 1) & 1 ? g.vB : g.vA);
+        int* kout = p == passes - 1 ? nullptr : (p & 1 ? g.kB : g.kA);
+        int* vout = p == passes - 1 ? g.order : (p & 1 ? g.vB : g.vA);
+        k_radix_hist<<<rt, RBLK, 0, s>>>(kin, g.n, shift, g.rhist, rt, g.ctl, dyn);
+        k_radix_scan<<<1, 1024, 0, s>>>(g.rhist, RBINS * rt, g.ctl, shift, dyn);
+        k_radix_scatter<<<rt, RBLK, 0, s>>>(kin, vin, kout, vout, g.n, shift, g.rhist, rt, g.ctl, dyn);
+    }
+    return hipGetLastError();
+}
+
+// Algorithm 3 on the order in g.order with charges in g.inc, then the
+// history record, best update, load update and digest.
+static hipError_t enqueue_alg3(const GraphDev& g, int slot, int nrounds_static, hipStream_t s) {
+    const int ntiles = ceil_div(g.n, SCAN_TILE);
+    k_gather_A<<<ntiles, SCAN_BLK, 0, s>>>(g.n, g.order, g.inc, g.A, g.tile_sum);
+    k_suffix_top<<<1, 1024, 0, s>>>(g.tile_sum, g.tile_off, ntiles);
+    k_suffix_argmax<<<ntiles, SCAN_BLK, 0, s>>>(g.n, g.A, g.tile_off, g.tile_best);
+    k_iter_end<<<1, 1024, 0, s>>>(g.tile_best, ntiles, g.ctl, g.hist_e, g.hist_v, g.hist_i, g.digest, g.rounds, slot,
+                                  nrounds_static);
+    k_finalize<<<grid_for(g.n, 256, 2048), 256, 0, s>>>(g.n, g.load, g.inc, g.rnd, g.order, g.best_order, g.ctl,
+                                                        g.digest + slot);
+    return hipGetLastError();
+}
+
+static int bits_for(long long maxval) {
+    int b = 0;
+    while (b < 62 && (maxval >> b) != 0) b++;
+    return b;
+}
+
+hipError_t enqueue_iter_peel(const GraphDev& g, int slot, int eps_num, int eps_den, int peel_grid, hipStream_t s) {
+    k_iter_begin<<<1, 64, 0, s>>>(g.ctl);
+    k_peel_init<<<grid_for(g.n, 256, 2048), 256, 0, s>>>(g.n, g.off, g.load, g.prio, g.rnd, g.inc, g.ctl);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    PeelArgs a{};
+    a.n = g.n;
+    a.eps_num = eps_num;
+    a.eps_den = eps_den;
+    a.off = g.off;
+    a.adj = g.adj;
+    a.prio = g.prio;
+    a.rnd = g.rnd;
+    a.inc = g.inc;
+    a.L0 = g.L0;
+    a.L1 = g.L1;
+    a.iv = g.iv;
+    a.ie = g.ie;
+    a.chunk_item = g.chunk;
+    a.ctl = g.ctl;
+    void* args[] = {&a};
+    e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_peel_rounds), dim3(peel_grid), dim3(PEEL_BLK), args,
+                                   0, s);
+    if (e != hipSuccess) return e;
+    // rounds <= n, so ceil(bits(n-1)/8) digit passes cover every round index
+    int passes = (bits_for(g.n > 1 ? g.n - 1 : 1) + 7) / 8;
+    if (passes < 1) passes = 1;
+    e = enqueue_radix(g, g.rnd, passes, 1, s);
+    if (e != hipSuccess) return e;
+    return enqueue_alg3(g, slot, 0, s);
+}
+
+hipError_t enqueue_iter_sort(const GraphDev& g, int slot, int key_bits, int sort_grid, hipStream_t s) {
+    k_iter_begin<<<1, 64, 0, s>>>(g.ctl);
+    int passes = (key_bits + 7) / 8;
+    if (passes < 1) passes = 1;
+    hipError_t e = enqueue_radix(g, g.load, passes, 0, s);
+    if (e != hipSuccess) return e;
+    k_sort_pos<<<grid_for(g.n, 256, 2048), 256, 0, s>>>(g.n, g.order, g.rnd, g.inc);
+    SweepArgs a{};
+    a.K = g.n_items;
+    a.E = g.nnz;
+    a.iv = g.siv;
+    a.ie = g.sie;
+    a.chunk_item = g.schunk;
+    a.off = g.off;
+    a.adj = g.adj;
+    a.inc = g.inc;
+    a.pos = g.rnd;
+    a.ctl = g.ctl;
+    if (g.nnz > 0) k_sweep_sort<<<sort_grid, SORT_BLK, 0, s>>>(a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return enqueue_alg3(g, slot, g.n, s);
+}
+
+hipError_t enqueue_iter_seq(const GraphDev& g, int slot, hipStream_t s) {
+    k_iter_begin<<<1, 64, 0, s>>>(g.ctl);
+    k_seq_order<<<1, SEQ_BLK, sizeof(unsigned int) * (size_t)g.n, s>>>(g.n, g.off, g.adj, g.load, g.order, g.rnd,
+                                                                          g.inc);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return enqueue_alg3(g, slot, g.n, s);
+}
+
+}  // namespace dsg

@@ -1,0 +1,75 @@
+"""CPU checks of the boundary: the library loads and exports every entry point that include/dsg.h declares.
+
+No compute call is made here (no GPU in this environment); dsg_workspace_bytes is pure host arithmetic.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dsg.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:dsg_status|const char\s*\*)\s*(dsg_\w+)\s*\(", text, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2311_04333_amd as dsg
+
+    return dsg.library()
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    assert "dsg_run" in names and "dsg_graph_create" in names and len(names) >= 15
+
+
+def test_library_exports_every_declared_symbol(lib):
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_the_header():
+    import paper_2311_04333_amd as dsg
+
+    assert sorted(n for n, _, _ in dsg.SIGNATURES) == declared_functions()
+
+
+def test_workspace_bytes_host_logic(lib):
+    import paper_2311_04333_amd as dsg
+
+    small = dsg.workspace_bytes(2000, 41216, 16)
+    big = dsg.workspace_bytes(4194304, 128312518, 64)
+    assert 0 < small < big
+    assert big % 256 == 0
+    # state grows linearly in n and nnz: about 18 int32 arrays of n plus chunk maps
+    assert 4194304 * 4 * 16 < big < 4194304 * 4 * 24 + 128312518
+    with pytest.raises(dsg.DsgError):
+        dsg.workspace_bytes(0, 0, 1)
+    with pytest.raises(dsg.DsgError):
+        dsg.workspace_bytes(10, 1 << 31, 1)
+
+
+def test_eps_parsing_is_exact():
+    import paper_2311_04333_amd as dsg
+
+    assert dsg.parse_eps("0.1") == (1, 10)
+    assert dsg.parse_eps(0.05) == (1, 20)
+    assert dsg.parse_eps((3, 7)) == (3, 7)
+    with pytest.raises(ValueError):
+        dsg.parse_eps((-1, 2))
+
+
+def test_missing_library_fails_loudly(tmp_path, monkeypatch):
+    import paper_2311_04333_amd as dsg
+
+    monkeypatch.setattr(dsg, "LIB_PATH", str(tmp_path / "nope.so"))
+    monkeypatch.setattr(dsg, "_lib", None)
+    with pytest.raises(RuntimeError):
+        dsg.library()

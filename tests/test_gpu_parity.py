@@ -1,0 +1,188 @@
+"""GPU path (through the C ABI) against the CPU oracle, bit for bit.
+
+Every case runs the HIP library and the oracle on the same seeded input and
+compares every output exactly: loads, per-iteration (edges, vertices, index),
+best pair, best vertex set, order digests, rounds per iteration, and the last
+iteration's rounds and positions.  Sizes span several tiles and sweep chunks
+with ragged tails, plus the degenerate cases: one vertex, no edges, stars,
+cliques, paths, isolated vertices, and rounds that hold a single vertex or
+every vertex.
+"""
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+from gpu_helpers import assert_same, log
+from pins import _small_graphs
+
+pytestmark = pytest.mark.gpu
+
+VARIANTS = [("seq", (0, 1)), ("peel", (1, 10)), ("peel", (0, 1)), ("peel", (1, 20)), ("sort", (0, 1))]
+
+
+@pytest.fixture(scope="module")
+def dsg():
+    import torch
+
+    import paper_2311_04333_amd as dsg
+
+    assert torch.cuda.is_available()
+    dsg.library()
+    return dsg
+
+
+@pytest.fixture(scope="module")
+def ctx(dsg):
+    c = dsg.Context(0)
+    yield c
+    c.close()
+
+
+def run_both(dsg, ctx, o, a, T, variant, eps, t_cap=64):
+    g = dsg.Graph(ctx, o, a, t_cap=t_cap)
+    g.run(T, eps, variant)
+    ref = oracle.run(o, a, T, variant, eps)
+    return g, ref
+
+
+def edge_cases():
+    cases = {
+        "single_vertex": (np.array([0, 0], np.int32), np.zeros(0, np.int32)),
+        "no_edges_n7": (np.zeros(8, np.int32), np.zeros(0, np.int32)),
+        "one_edge": graphgen.from_edges(2, [(0, 1)]),
+        "triangle": graphgen.complete(3),
+        "K8": graphgen.complete(8),
+        "K40": graphgen.complete(40),
+        "star_9": graphgen.from_edges(10, [(0, j) for j in range(1, 10)]),
+        "star_3000": graphgen.from_edges(3001, [(0, j) for j in range(1, 3001)]),
+        "path_50": graphgen.from_edges(50, [(i, i + 1) for i in range(49)]),
+        "isolated_mix": graphgen.from_edges(30, [(3, 7), (7, 11), (3, 11), (20, 21), (21, 29)]),
+        "two_cliques": graphgen.from_edges(11, [(i, j) for i in range(6) for j in range(i + 1, 6)] +
+                                           [(6 + i, 6 + j) for i in range(5) for j in range(i + 1, 5)]),
+    }
+    for i, (o, a) in enumerate(_small_graphs()):
+        cases[f"gnp_{i}"] = (o, a)
+    return cases
+
+
+@pytest.mark.parametrize("name", list(edge_cases().keys()))
+def test_edge_cases_all_variants(dsg, ctx, name):
+    o, a = edge_cases()[name]
+    for variant, eps in VARIANTS:
+        log(f"case={name} variant={variant} eps={eps}")
+        g, ref = run_both(dsg, ctx, o, a, 6, variant, eps)
+        assert_same(g, ref, f"{name}/{variant}/{eps}")
+        g.close()
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_config1_all_variants(dsg, ctx, seed):
+    """ER n=2000, m=20000 + planted 50-set, T=10: sequential and eps-peeling semantics."""
+    o, a = graphgen.config1(seed)
+    for variant, eps in VARIANTS:
+        log(f"config1 seed={seed} variant={variant} eps={eps}")
+        g, ref = run_both(dsg, ctx, o, a, 10, variant, eps)
+        assert_same(g, ref, f"config1/{seed}/{variant}")
+        g.close()
+
+
+@pytest.mark.parametrize("n,m", [(4097, 30000), (8191, 90000), (12289, 60000), (40000, 400000)])
+def test_ragged_multi_tile(dsg, ctx, n, m):
+    """Sizes that are not multiples of the 4096-element tiles or the 2048-edge chunks."""
+    o, a = graphgen.er_planted(7 + n, n, m, 60, 1, 2)
+    for variant, eps in VARIANTS:
+        if variant == "seq" and n > 16000:
+            continue
+        log(f"ragged n={n} m={m} variant={variant} eps={eps}")
+        g, ref = run_both(dsg, ctx, o, a, 4, variant, eps)
+        assert_same(g, ref, f"ragged/{n}/{variant}")
+        g.close()
+
+
+@pytest.mark.parametrize("scale", [12, 16])
+def test_rmat_skewed(dsg, ctx, scale):
+    """R-MAT (hubs, many isolated vertices) with the configuration's quadrant probabilities."""
+    o, a = graphgen.rmat(3, scale, 16 << scale)
+    for variant, eps in [("peel", (1, 10)), ("peel", (1, 20)), ("peel", (0, 1)), ("sort", (0, 1))]:
+        log(f"rmat scale={scale} variant={variant} eps={eps}")
+        g, ref = run_both(dsg, ctx, o, a, 5, variant, eps)
+        assert_same(g, ref, f"rmat{scale}/{variant}/{eps}")
+        g.close()
+
+
+def test_chunglu_small(dsg, ctx):
+    """Chung-Lu power law (the shape of the 40M-vertex configuration) at n=200k."""
+    o, a = graphgen.chunglu(5, 200_000, 2.1, 30.0, 10_000.0)
+    for variant, eps in [("peel", (1, 20)), ("sort", (0, 1))]:
+        log(f"chunglu n=200k variant={variant}")
+        g, ref = run_both(dsg, ctx, o, a, 3, variant, eps)
+        assert_same(g, ref, f"chunglu/{variant}")
+        g.close()
+
+
+def test_resume_and_mixed_variants(dsg, ctx):
+    """run(a) then run(b) appends; mixing variants and eps between calls matches the oracle doing the same."""
+    o, a = graphgen.config1(4)
+    g = dsg.Graph(ctx, o, a, t_cap=32)
+    ref = None
+    for T, variant, eps in [(2, "peel", (1, 10)), (3, "sort", (0, 1)), (1, "seq", (0, 1)), (2, "peel", (1, 20)),
+                            (0, "peel", (1, 10)), (2, "peel", (1, 10))]:
+        log(f"resume step T={T} variant={variant}")
+        g.run(T, eps, variant)
+        ref = oracle.run(o, a, T, variant, eps, state=ref)
+    assert_same(g, ref, "resume")
+    one = dsg.Graph(ctx, o, a, t_cap=32).run(7, (1, 10), "peel")
+    two = dsg.Graph(ctx, o, a, t_cap=32).run(3, (1, 10), "peel").run(4, (1, 10), "peel")
+    assert np.array_equal(one.loads(), two.loads()) and one.best() == two.best()
+    assert one.digests() == two.digests()
+
+
+def test_reset(dsg, ctx):
+    o, a = graphgen.config1(5)
+    g = dsg.Graph(ctx, o, a, t_cap=16).run(4, (1, 10), "peel")
+    g.reset().run(3, (0, 1), "sort")
+    assert_same(g, oracle.run(o, a, 3, "sort"), "reset")
+
+
+def test_deterministic(dsg, ctx):
+    """Atomics only commute integers: two runs are bit-identical."""
+    o, a = graphgen.rmat(9, 14, 16 << 14)
+    r1 = dsg.Graph(ctx, o, a, t_cap=8).run(5, (1, 10), "peel")
+    r2 = dsg.Graph(ctx, o, a, t_cap=8).run(5, (1, 10), "peel")
+    assert np.array_equal(r1.loads(), r2.loads())
+    assert r1.digests() == r2.digests() and r1.best() == r2.best()
+
+
+def test_invalid_csr_rejected(dsg, ctx):
+    """Validation turns every broken CSR property into DSG_EINVAL before any peeling kernel runs."""
+    good_o, good_a = graphgen.from_edges(4, [(0, 1), (1, 2), (2, 3)])
+    bad = {
+        "asymmetric": (good_o, np.array([1, 0, 2, 1, 3, 1], np.int32)),
+        "self_loop": (np.array([0, 1, 2], np.int32), np.array([0, 1], np.int32)),
+        "unsorted": (np.array([0, 2, 3, 4], np.int32), np.array([2, 1, 0, 0], np.int32)),
+        "out_of_range": (good_o, np.array([1, 0, 2, 1, 3, 9], np.int32)),
+        "offsets_decrease": (np.array([0, 3, 2, 6, 6], np.int32), good_a),
+        "offsets_end": (np.array([0, 1, 3, 5, 5], np.int32), good_a),
+    }
+    for name, (o, a) in bad.items():
+        log(f"invalid csr case={name}")
+        with pytest.raises(dsg.DsgError) as ei:
+            dsg.Graph(ctx, o, a, t_cap=4)
+        assert ei.value.status == -1, name
+
+
+def test_guards(dsg, ctx):
+    """Overflow guard, history capacity and the SEQ size limit fail cleanly without running kernels."""
+    o, a = graphgen.from_edges(1 << 16, [(0, j) for j in range(1, 1 << 16)])
+    g = dsg.Graph(ctx, o, a, t_cap=40000)
+    with pytest.raises(dsg.DsgError) as ei:
+        g.run(33000, (1, 10), "peel")  # (33000 + 1) * 65535 >= 2^31
+    assert ei.value.status == -4
+    with pytest.raises(dsg.DsgError) as ei:
+        g.run(1, (1, 10), "seq")  # n = 65536 > 16000
+    assert ei.value.status == -1
+    small = dsg.Graph(ctx, *graphgen.complete(5), t_cap=2)
+    small.run(2, (0, 1), "sort")
+    with pytest.raises(dsg.DsgError):
+        small.run(1, (0, 1), "sort")
