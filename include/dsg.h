@@ -146,6 +146,16 @@ dsg_status dsg_graph_destroy(dsg_graph* g);
  * the work to finish. */
 dsg_status dsg_last_run_ms(dsg_graph* g, float* ms);
 
+/* Optional per-launch timing of each iteration's dominant kernel (the PEEL
+ * round loop, the SORT sweep, the SEQ peel): HIP events are recorded on the
+ * graph's stream right before and after every such launch of later dsg_run
+ * calls.  Off by default (enable = 0). */
+dsg_status dsg_set_kernel_timing(dsg_graph* g, int32_t enable);
+
+/* Sum of the timed launch durations of the last dsg_run, in milliseconds, and
+ * the number of timed launches (0 when timing is off).  Waits for the work. */
+dsg_status dsg_get_kernel_timing(dsg_graph* g, float* total_ms, int32_t* launches);
+
 /* Message for the calling thread's last failed call ("" if none). */
 const char* dsg_last_error(void);
 

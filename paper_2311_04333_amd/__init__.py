@@ -49,6 +49,8 @@ SIGNATURES = [
     ("dsg_get_iter_digests", ctypes.c_int, [_P, _P, _P, _I32, _P]),
     ("dsg_graph_destroy", ctypes.c_int, [_P]),
     ("dsg_last_run_ms", ctypes.c_int, [_P, _P]),
+    ("dsg_set_kernel_timing", ctypes.c_int, [_P, _I32]),
+    ("dsg_get_kernel_timing", ctypes.c_int, [_P, _P, _P]),
     ("dsg_last_error", ctypes.c_char_p, []),
 ]
 
@@ -204,6 +206,17 @@ class Graph:
         ms = ctypes.c_float()
         _check(library().dsg_last_run_ms(self._h, ctypes.addressof(ms)))
         return ms.value
+
+    def set_kernel_timing(self, enable: bool = True):
+        _check(library().dsg_set_kernel_timing(self._h, 1 if enable else 0))
+        return self
+
+    def kernel_timing(self):
+        """(total ms, launches) of the dominant kernel over the last run (timing must be enabled)."""
+        ms = ctypes.c_float()
+        cnt = ctypes.c_int32()
+        _check(library().dsg_get_kernel_timing(self._h, ctypes.addressof(ms), ctypes.addressof(cnt)))
+        return ms.value, cnt.value
 
     # ------------------------------------------------------------ results
     def best(self):

@@ -38,6 +38,9 @@ struct dsg_graph {
     int last_variant; // -1 = none yet
     hipEvent_t ev0, ev1;
     bool timed;
+    bool ktime;                    // per-launch timing of the dominant kernel
+    std::vector<hipEvent_t> kev;   // 2 events per timed launch
+    int klaunches;                 // timed launches of the last dsg_run
 };
 
 namespace {
@@ -75,10 +78,11 @@ struct Layout {
 long long carve(int n, long long nnz, int t_cap, char* base, GraphDev* g) {
     Layout L;
     const long long N = n;
-    const long long nch = nnz / dsg::SWEEP_CH + 2;
+    const long long nch = nnz / dsg::MIN_CH + 2;
     const long long ntiles = (N + 4095) / 4096 + 1;
     const long long rtiles = (N + 4095) / 4096 + 1;
     long long o_ctl = L.add(dsg::ctl_bytes());
+    long long o_gs = L.add(sizeof(dsg::GridSync));
     long long o_load = L.add(4 * N), o_prio = L.add(4 * N), o_rnd = L.add(4 * N), o_inc = L.add(4 * N);
     long long o_order = L.add(4 * N), o_best = L.add(4 * N);
     long long o_kA = L.add(4 * N), o_kB = L.add(4 * N), o_vA = L.add(4 * N), o_vB = L.add(4 * N);
@@ -91,6 +95,7 @@ long long carve(int n, long long nnz, int t_cap, char* base, GraphDev* g) {
     long long o_rd = L.add(4LL * t_cap), o_dg = L.add(8LL * t_cap);
     if (base && g) {
         g->ctl = reinterpret_cast<dsg::Ctl*>(base + o_ctl);
+        g->gsync = reinterpret_cast<dsg::GridSync*>(base + o_gs);
         g->load = reinterpret_cast<int*>(base + o_load);
         g->prio = reinterpret_cast<int*>(base + o_prio);
         g->rnd = reinterpret_cast<int*>(base + o_rnd);
@@ -178,11 +183,10 @@ dsg_status dsg_ctx_create(int device, void* hip_stream, dsg_ctx** out) {
     c->stream = reinterpret_cast<hipStream_t>(hip_stream);
     c->num_cu = prop.multiProcessorCount;
     int per_cu = dsg::peel_blocks_per_cu();
-    int want = 2;
-    if (const char* e = getenv("DSG_PEEL_BLOCKS_PER_CU")) want = atoi(e);
-    if (want < 1) want = 1;
-    if (per_cu > want) per_cu = want;
-    c->peel_grid = c->num_cu * per_cu;
+    // one block per CU: the round loop's grid syncs cost grow with the
+    // number of blocks, and 1024 threads per CU keep enough loads in flight
+    if (per_cu < 1) return fail(DSG_EDEVICE, "round kernel cannot be resident");
+    c->peel_grid = c->num_cu;
     c->sort_grid = c->num_cu * 8;
     *out = c;
     return DSG_OK;
@@ -282,21 +286,32 @@ dsg_status dsg_run(dsg_graph* g, int32_t T, int32_t eps_num, int32_t eps_den, ds
         return fail(DSG_EOVERFLOW, "loads could exceed 31 bits");
     DSG_HIP(hipSetDevice(g->ctx->device), "hipSetDevice");
     hipStream_t s = g->ctx->stream;
+    if (g->ktime) {
+        while ((int)g->kev.size() < 2 * T) {
+            hipEvent_t ev;
+            DSG_HIP(hipEventCreate(&ev), "hipEventCreate");
+            g->kev.push_back(ev);
+        }
+    }
+    g->klaunches = 0;
     DSG_HIP(hipEventRecord(g->ev0, s), "hipEventRecord");
     for (int t = 0; t < T; t++) {
         const int slot = g->recorded + t;
+        hipEvent_t ea = g->ktime ? g->kev[2 * t] : nullptr;
+        hipEvent_t eb = g->ktime ? g->kev[2 * t + 1] : nullptr;
         hipError_t e;
         if (variant == DSG_PEEL) {
-            e = dsg::enqueue_iter_peel(g->d, slot, eps_num, eps_den, g->ctx->peel_grid, s);
+            e = dsg::enqueue_iter_peel(g->d, slot, eps_num, eps_den, g->ctx->peel_grid, s, ea, eb);
         } else if (variant == DSG_SORT) {
             long long bound = (long long)(g->iters_done + t) * (long long)g->d.max_deg;
             int bits = 0;
             while (bits < 31 && (bound >> bits) != 0) bits++;
-            e = dsg::enqueue_iter_sort(g->d, slot, bits, g->ctx->sort_grid, s);
+            e = dsg::enqueue_iter_sort(g->d, slot, bits, g->ctx->sort_grid, s, ea, eb);
         } else {
-            e = dsg::enqueue_iter_seq(g->d, slot, s);
+            e = dsg::enqueue_iter_seq(g->d, slot, s, ea, eb);
         }
         if (e != hipSuccess) return hip_fail(e, "enqueue iteration");
+        if (g->ktime) g->klaunches++;
     }
     DSG_HIP(hipEventRecord(g->ev1, s), "hipEventRecord");
     g->timed = true;
@@ -332,6 +347,26 @@ dsg_status dsg_last_run_ms(dsg_graph* g, float* ms) {
     if (!g->timed) return fail(DSG_ESTATE, "no run recorded");
     DSG_HIP(hipEventSynchronize(g->ev1), "hipEventSynchronize");
     DSG_HIP(hipEventElapsedTime(ms, g->ev0, g->ev1), "hipEventElapsedTime");
+    return DSG_OK;
+}
+
+dsg_status dsg_set_kernel_timing(dsg_graph* g, int32_t enable) {
+    if (!g) return fail(DSG_EINVAL, "graph is NULL");
+    g->ktime = enable != 0;
+    return DSG_OK;
+}
+
+dsg_status dsg_get_kernel_timing(dsg_graph* g, float* total_ms, int32_t* launches) {
+    if (!g || !total_ms || !launches) return fail(DSG_EINVAL, "NULL argument");
+    float tot = 0.f;
+    for (int i = 0; i < g->klaunches; i++) {
+        float ms = 0.f;
+        DSG_HIP(hipEventSynchronize(g->kev[2 * i + 1]), "hipEventSynchronize");
+        DSG_HIP(hipEventElapsedTime(&ms, g->kev[2 * i], g->kev[2 * i + 1]), "hipEventElapsedTime");
+        tot += ms;
+    }
+    *total_ms = tot;
+    *launches = g->klaunches;
     return DSG_OK;
 }
 
@@ -429,6 +464,7 @@ dsg_status dsg_get_iter_digests(dsg_graph* g, uint64_t* h_digest, int32_t* h_rou
 
 dsg_status dsg_graph_destroy(dsg_graph* g) {
     if (!g) return DSG_OK;
+    for (hipEvent_t ev : g->kev) (void)hipEventDestroy(ev);
     (void)hipEventDestroy(g->ev0);
     (void)hipEventDestroy(g->ev1);
     delete g;

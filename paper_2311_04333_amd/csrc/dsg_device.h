@@ -14,10 +14,7 @@ constexpr int WAVE = 64;
 // two rounds ahead of its use, so no round reads a slot that another round
 // is still writing.
 struct alignas(256) Ctl {
-    // grid barrier of the persistent round kernel
-    unsigned int bar_count;
-    unsigned int bar_gen;
-    unsigned int pad0[2];
+    unsigned int pad0[4];
     // per-round ring: minimum priority, survivor count, packed frontier
     // counter (items << 38 | edges)
     unsigned int mn[4];
@@ -142,23 +139,79 @@ __device__ __forceinline__ T block_min(T v, T* sh) {
 }
 
 // ------------------------------------------------------------ grid barrier
-// Sense-reversing barrier over all blocks of a co-resident (cooperative)
-// grid.  Release at agent scope before arriving, acquire after leaving, so
-// plain stores made before the barrier by any block are visible to plain
-// loads after it.
-__device__ __forceinline__ void grid_barrier(Ctl* ctl, unsigned int nblocks) {
-    __syncthreads();
+// XCD (accelerator complex die) of the executing wave: hardware register
+// XCC_ID, bits [2:0].  MI355X has 8 XCDs, each with its own L2.
+__device__ __forceinline__ unsigned int xcd_id() {
+    return __builtin_amdgcn_s_getreg((20) | (0 << 6) | (3 << 11)) & 0x7u;
+}
+
+// State of the XCD-grouped grid barrier; every field sits on its own cache
+// line.  Zeroed before each launch of a kernel that uses it.
+struct alignas(256) GridSync {
+    unsigned int gen;
+    unsigned int pad0[63];
+    unsigned int started;
+    unsigned int pad1[63];
+    unsigned int gsize[8];
+    unsigned int pad2[56];
+    unsigned int xcnt[8][64];    // arrivals per XCD (monotonic)
+    unsigned int xflag[8][64];   // epoch whose XCD data has been released
+};
+
+__device__ __forceinline__ unsigned int ld_agent(const unsigned int* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long ld_agent_u64(const unsigned long long* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(unsigned int* p, unsigned int v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Called once at kernel start by every block: count the blocks of each XCD
+// in this launch (the block-to-XCD placement is the hardware's choice).
+__device__ __forceinline__ void grid_sync_init(GridSync* gs, unsigned int nblocks, unsigned int xid) {
     if (threadIdx.x == 0) {
-        unsigned int gen = __hip_atomic_load(&ctl->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        unsigned int arrived =
-            __hip_atomic_fetch_add(&ctl->bar_count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (arrived == nblocks - 1) {
-            __hip_atomic_store(&ctl->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&ctl->bar_gen, gen + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            while (__hip_atomic_load(&ctl->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen)
-                __builtin_amdgcn_s_sleep(1);
+        __hip_atomic_fetch_add(&gs->gsize[xid], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(&gs->started, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        while (ld_agent(&gs->started) < nblocks) __builtin_amdgcn_s_sleep(1);
+    }
+    __syncthreads();
+}
+
+// Grid barrier with one L2 write-back per XCD instead of one per block
+// (per-block agent-scope releases dominate the cost of a barrier at 256
+// blocks).  Blocks of an XCD arrive on that XCD's counter after their own
+// stores have completed into the shared L2.  The last arrival of an XCD
+// issues the agent-scope release that writes that L2 back.  It waits for the
+// write-back to finish, then raises the XCD flag.  Block 0 waits for every
+// XCD flag and publishes the epoch.  Every block then performs its own
+// agent-scope acquire (L1 and L2 invalidate, waited for).  `epoch` counts
+// the block's barriers in this launch.
+__device__ __forceinline__ void grid_sync(GridSync* gs, unsigned int xid, unsigned int& epoch) {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    epoch++;
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_s_waitcnt(0);
+        const unsigned int gsz = ld_agent(&gs->gsize[xid]);
+        const unsigned int a =
+            __hip_atomic_fetch_add(&gs->xcnt[xid][0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (a == epoch * gsz - 1) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            st_agent(&gs->xflag[xid][0], epoch);
         }
+        if (blockIdx.x == 0) {
+            for (int x = 0; x < 8; x++)
+                if (ld_agent(&gs->gsize[x]))
+                    while (ld_agent(&gs->xflag[x][0]) < epoch) __builtin_amdgcn_s_sleep(1);
+            st_agent(&gs->gen, epoch);
+        }
+        while (ld_agent(&gs->gen) < epoch) __builtin_amdgcn_s_sleep(1);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     }
     __syncthreads();
 }

@@ -8,10 +8,13 @@
 namespace dsg {
 
 struct Ctl;
+struct GridSync;
 
-constexpr int SWEEP_CH = 2048;     // edges per sweep chunk (items per chunk <= this)
-constexpr int PEEL_BLK = 512;      // threads per block of the persistent round kernel
+constexpr int PEEL_BLK = 1024;     // threads per block of the persistent round kernel (one block per CU)
+constexpr int PEEL_CH = 4096;      // edges per PEEL sweep chunk (items per chunk <= this)
 constexpr int SORT_BLK = 512;      // threads per block of the SORT sweep
+constexpr int SORT_CH = 4096;      // edges per SORT sweep chunk
+constexpr int MIN_CH = PEEL_CH < SORT_CH ? PEEL_CH : SORT_CH;
 constexpr int SEQ_BLK = 1024;      // threads of the single SEQ block
 constexpr int SEQ_MAX_N = 16000;   // SEQ keeps n priorities in LDS (< 64 KB)
 constexpr int PEEL_MAX_N = 1 << 26;  // frontier item counter has 26 bits
@@ -32,6 +35,7 @@ struct PeelArgs {
     int* ie;
     int* chunk_item;
     Ctl* ctl;
+    GridSync* gs;
 };
 
 struct SweepArgs {
@@ -55,6 +59,7 @@ struct GraphDev {
     const int* off;
     const int* adj;
     Ctl* ctl;
+    GridSync* gsync;
     int* load;
     int* prio;
     int* rnd;
@@ -95,10 +100,14 @@ hipError_t launch_build_static_items(const GraphDev& g, hipStream_t s);
 hipError_t launch_reset_state(const GraphDev& g, hipStream_t s);
 hipError_t launch_zero_ctl(const GraphDev& g, hipStream_t s);
 
-// one iteration; `slot` is the history index written by this iteration
-hipError_t enqueue_iter_peel(const GraphDev& g, int slot, int eps_num, int eps_den, int peel_grid, hipStream_t s);
-hipError_t enqueue_iter_sort(const GraphDev& g, int slot, int key_bits, int sort_grid, hipStream_t s);
-hipError_t enqueue_iter_seq(const GraphDev& g, int slot, hipStream_t s);
+// One iteration; `slot` is the history index written by this iteration.
+// ev_a / ev_b (may be null) are recorded on `s` right before and after the
+// iteration's dominant kernel (PEEL round loop, SORT sweep, SEQ peel).
+hipError_t enqueue_iter_peel(const GraphDev& g, int slot, int eps_num, int eps_den, int peel_grid, hipStream_t s,
+                             hipEvent_t ev_a, hipEvent_t ev_b);
+hipError_t enqueue_iter_sort(const GraphDev& g, int slot, int key_bits, int sort_grid, hipStream_t s, hipEvent_t ev_a,
+                             hipEvent_t ev_b);
+hipError_t enqueue_iter_seq(const GraphDev& g, int slot, hipStream_t s, hipEvent_t ev_a, hipEvent_t ev_b);
 
 int peel_blocks_per_cu();
 int ctl_bytes();

@@ -186,22 +186,60 @@ __global__ __launch_bounds__(RBLK) void k_radix_hist(const int* __restrict__ key
     hist[threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
 }
 
-// digit-major exclusive scan of hist[RBINS * ntiles], single block
-__global__ __launch_bounds__(1024) void k_radix_scan(int* __restrict__ hist, int total, const Ctl* ctl, int shift,
-                                                     int dyn) {
+// Digit-major exclusive scan of hist[RBINS * ntiles] in three kernels:
+// per-tile sums, one-block scan of those sums, in-tile scan plus offset.
+__global__ __launch_bounds__(SCAN_BLK) void k_rscan_tiles(const int* __restrict__ hist, int total,
+                                                          long long* __restrict__ tile_sum, const Ctl* ctl, int shift,
+                                                          int dyn) {
     if (!pass_active(ctl, shift, dyn)) return;
-    __shared__ int sh[1024 / WAVE];
-    // each thread owns a contiguous segment
-    int per = (total + 1023) / 1024;
-    int beg = min(total, threadIdx.x * per), end = min(total, beg + per);
-    int s = 0;
-    for (int i = beg; i < end; i++) s += hist[i];
-    int tot;
-    int ex = block_excl_scan<1024>(s, &tot, sh);
-    for (int i = beg; i < end; i++) {
-        int c = hist[i];
-        hist[i] = ex;
-        ex += c;
+    __shared__ long long sh[SCAN_BLK / WAVE];
+    const long long base = (long long)blockIdx.x * SCAN_TILE + (long long)threadIdx.x * SCAN_ITEMS;
+    long long s = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; k++) {
+        long long i = base + k;
+        if (i < total) s += hist[i];
+    }
+    s = block_sum<SCAN_BLK>(s, sh);
+    if (threadIdx.x == 0) tile_sum[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(1024) void k_rscan_top(long long* __restrict__ tile_sum, int ntiles, const Ctl* ctl,
+                                                    int shift, int dyn) {
+    if (!pass_active(ctl, shift, dyn)) return;
+    __shared__ long long sh[1024 / WAVE];
+    long long carry = 0;
+    for (int base = 0; base < ntiles; base += 1024) {
+        int i = base + threadIdx.x;
+        long long v = i < ntiles ? tile_sum[i] : 0;
+        long long tot;
+        long long ex = block_excl_scan<1024>(v, &tot, sh);
+        if (i < ntiles) tile_sum[i] = carry + ex;
+        carry += tot;
+    }
+}
+
+__global__ __launch_bounds__(SCAN_BLK) void k_rscan_apply(int* __restrict__ hist, int total,
+                                                          const long long* __restrict__ tile_sum, const Ctl* ctl,
+                                                          int shift, int dyn) {
+    if (!pass_active(ctl, shift, dyn)) return;
+    __shared__ long long sh[SCAN_BLK / WAVE];
+    const long long base = (long long)blockIdx.x * SCAN_TILE + (long long)threadIdx.x * SCAN_ITEMS;
+    int x[SCAN_ITEMS];
+    long long mine = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; k++) {
+        long long i = base + k;
+        x[k] = i < total ? hist[i] : 0;
+        mine += x[k];
+    }
+    long long tot;
+    long long run = tile_sum[blockIdx.x] + block_excl_scan<SCAN_BLK>(mine, &tot, sh);
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; k++) {
+        long long i = base + k;
+        if (i < total) hist[i] = (int)run;
+        run += x[k];
     }
 }
 
@@ -310,7 +348,7 @@ __global__ __launch_bounds__(SCAN_BLK) void k_compact_items(int n, const int* __
             int item = (int)(run + ex);
             iv[item] = (int)v;
             ie[item] = a;
-            for (long long c = ((long long)a + SWEEP_CH - 1) / SWEEP_CH; c * SWEEP_CH < b; c++) chunk_item[c] = item;
+            for (long long c = ((long long)a + SORT_CH - 1) / SORT_CH; c * SORT_CH < b; c++) chunk_item[c] = item;
         }
         run += tot;
     }
@@ -318,28 +356,54 @@ __global__ __launch_bounds__(SCAN_BLK) void k_compact_items(int n, const int* __
 
 // ========================================================== edge sweep
 // Edge-balanced sweep over the concatenated rows of an item list.  Block b
-// takes chunks c = b, b + grid, ... of SWEEP_CH consecutive edges; the items
-// overlapping a chunk (at most SWEEP_CH, since every item has an edge in it)
-// are staged in LDS, and each thread finds its edge's item by binary search
-// there.  Per-item counts are gathered in LDS and added to inc[] once per
-// chunk.  Op decides what an edge (v, u) contributes.
+// takes chunks c = b, b + grid, ... of CH consecutive edges.  The items
+// overlapping a chunk are staged in LDS; there are at most CH of them,
+// since every item has an edge in the chunk.  Each thread finds its edge's
+// item by binary search there.  Per-item counts are gathered in LDS and
+// added to inc[] once per chunk.  Op decides what an edge (v, u)
+// contributes.
+template <int CH>
 struct SweepLds {
-    int fe[SWEEP_CH];
-    int row[SWEEP_CH];
-    int v[SWEEP_CH];
-    int cnt[SWEEP_CH];
-    int aux[SWEEP_CH];
+    int fe[CH];
+    int row[CH];
+    int v[CH];
+    int cnt[CH];
 };
 
-template <int BLK, class Op>
+// Open-addressing LDS table that aggregates degree decrements per target
+// vertex within one chunk.  A hub adjacent to many of the chunk's edges then
+// receives one global atomic instead of one per edge (same-address atomics
+// serialise at about 11 ns each).  At most CH distinct keys go into 2*CH
+// slots, so probing always finds a free slot.
+template <int SLOTS>
+struct DecTable {
+    int key[SLOTS];
+    int cnt[SLOTS];
+};
+constexpr int DEC_EMPTY = -1;
+
+template <int SLOTS>
+__device__ __forceinline__ void dec_add(DecTable<SLOTS>& t, int u) {
+    unsigned int h = ((unsigned int)u * 0x9E3779B1u) >> (32 - __builtin_ctz(SLOTS));
+    while (true) {
+        int k = atomicCAS(&t.key[h], DEC_EMPTY, u);
+        if (k == DEC_EMPTY || k == u) {
+            atomicAdd(&t.cnt[h], 1);
+            return;
+        }
+        h = (h + 1) & (SLOTS - 1);
+    }
+}
+
+template <int BLK, int CH, class Op>
 __device__ __forceinline__ void sweep_chunks(int K, long long E, const int* __restrict__ iv, const int* __restrict__ ie,
                                              const int* __restrict__ chunk_item, const int* __restrict__ off,
                                              const int* __restrict__ adj, int* __restrict__ inc, Op& op,
-                                             SweepLds& s, int block, int nblocks) {
-    const long long nchunks = (E + SWEEP_CH - 1) / SWEEP_CH;
+                                             SweepLds<CH>& s, int block, int nblocks) {
+    const long long nchunks = (E + CH - 1) / CH;
     for (long long c = block; c < nchunks; c += nblocks) {
-        const long long x0 = c * SWEEP_CH;
-        const long long x1 = min(E, x0 + SWEEP_CH);
+        const long long x0 = c * CH;
+        const long long x1 = min(E, x0 + CH);
         const int k0 = chunk_item[c];
         int k1;
         if (c + 1 < nchunks) {
@@ -349,7 +413,7 @@ __device__ __forceinline__ void sweep_chunks(int K, long long E, const int* __re
             k1 = K - 1;
         }
         const int nitems = k1 - k0 + 1;
-        if (nitems < 1 || nitems > SWEEP_CH) {
+        if (nitems < 1 || nitems > CH) {
             // impossible when every item has an edge in the chunk; refuse to
             // index LDS out of range if the item list is ever inconsistent
             if (threadIdx.x == 0) op.flag_error();
@@ -361,7 +425,7 @@ __device__ __forceinline__ void sweep_chunks(int K, long long E, const int* __re
             s.v[j] = v;
             s.row[j] = off[v];
             s.cnt[j] = 0;
-            s.aux[j] = op.item_aux(v);
+            op.stage_item(j, v);
         }
         __syncthreads();
         for (long long x = x0 + threadIdx.x; x < x1; x += BLK) {
@@ -372,11 +436,12 @@ __device__ __forceinline__ void sweep_chunks(int K, long long E, const int* __re
             }
             const int v = s.v[lo];
             const int u = adj[s.row[lo] + (int)(x - s.fe[lo])];
-            if (op.edge(v, u, s.aux[lo])) atomicAdd(&s.cnt[lo], 1);
+            if (op.edge(v, u, lo)) atomicAdd(&s.cnt[lo], 1);
         }
         __syncthreads();
         for (int j = threadIdx.x; j < nitems; j += BLK)
             if (s.cnt[j]) atomicAdd(&inc[s.v[j]], s.cnt[j]);
+        op.flush_chunk();
         __syncthreads();
     }
 }
@@ -400,72 +465,113 @@ __global__ __launch_bounds__(256) void k_peel_init(int n, const int* __restrict_
     if (threadIdx.x == 0) atomicMin(&ctl->mn[0], lmin);
 }
 
-__global__ void k_iter_begin(Ctl* ctl) {
+// Clears the per-iteration control fields and the grid-barrier state.
+__global__ void k_iter_begin(Ctl* ctl, GridSync* gs) {
     if (threadIdx.x < 4) {
         ctl->mn[threadIdx.x] = 0xFFFFFFFFu;
         ctl->lcnt[threadIdx.x] = 0;
         ctl->fcnt[threadIdx.x] = 0;
     }
     if (threadIdx.x == 0) {
-        ctl->bar_count = 0;
         ctl->nrounds = 0;
         ctl->improved = 0;
     }
+    if (gs) {
+        unsigned int* w = reinterpret_cast<unsigned int*>(gs);
+        for (unsigned int i = threadIdx.x; i < sizeof(GridSync) / 4; i += blockDim.x) w[i] = 0;
+    }
 }
 
+constexpr int PEEL_SLOTS = 2 * PEEL_CH;
+
+struct PeelLds {
+    SweepLds<PEEL_CH> sw;
+    DecTable<PEEL_SLOTS> dec;
+};
+
+// What an edge (v, u) of a frontier vertex v does in round r:
+//   u alive after the round (round[u] == -1): v is charged the edge, and
+//     u loses one degree (aggregated per chunk in LDS, then one atomicSub
+//     per distinct u); u's new priority bids for the next round's minimum.
+//     Its last decrement yields its final value.
+//   u peeled in the same round: the edge goes to the lower id.
+//   u peeled earlier: nothing.
 struct PeelEdgeOp {
     const int* rnd;
     int* prio;
     int r;
     unsigned int lmin;
     Ctl* ctl;
-    __device__ void flag_error() { atomicAdd(&ctl->err_count, 1); ctl->err_code = ERR_INTERNAL; }
-    __device__ __forceinline__ int item_aux(int) const { return 0; }
+    DecTable<PEEL_SLOTS>* dec;
+    __device__ void flag_error() {
+        atomicAdd(&ctl->err_count, 1);
+        ctl->err_code = ERR_INTERNAL;
+    }
+    __device__ __forceinline__ void stage_item(int, int) {}
     __device__ __forceinline__ bool edge(int v, int u, int) {
         const int ru = rnd[u];
         if (ru < 0) {
-            // u survives the round: it loses one degree, and its new priority
-            // is a candidate for the next round's minimum (its last decrement
-            // yields its final value)
-            const int old = atomicSub(&prio[u], 1);
-            lmin = min(lmin, (unsigned int)(old - 1));
+            dec_add(*dec, u);
             return true;
         }
-        // same-round edge: charged to the lower id
         return ru == r && u > v;
+    }
+    __device__ __forceinline__ void flush_chunk() {
+        __syncthreads();
+        for (int slot = threadIdx.x; slot < PEEL_SLOTS; slot += blockDim.x) {
+            const int u = dec->key[slot];
+            if (u != DEC_EMPTY) {
+                const int c = dec->cnt[slot];
+                const int old = atomicSub(&prio[u], c);
+                lmin = min(lmin, (unsigned int)(old - c));
+                dec->key[slot] = DEC_EMPTY;
+                dec->cnt[slot] = 0;
+            }
+        }
     }
 };
 
 constexpr unsigned long long FCNT_SHIFT = 38;
 constexpr unsigned long long FCNT_MASK = (1ull << FCNT_SHIFT) - 1;
 
-// Persistent round loop of one PEEL iteration (cooperative launch).  Per
-// round r:
-//   select: mn = ring.mn[r]; thr = floor((q + p) mn / q); every alive vertex
-//     of the list L_r with prio <= thr is marked round r and, if it has
-//     edges, appended to the item list with its edge start (one packed 64-bit
-//     atomic per block keeps items and edge offsets consistent).  Others go
-//     to L_{r+1} and offer their priority to ring.mn[r+1].
-//   barrier
+// Persistent round loop of one PEEL iteration (cooperative launch, one block
+// per CU).  Per round r:
+//   select: mn = ring.mn[r]; thr = floor((q + p) mn / q).  Block b owns a
+//     contiguous slice of the alive list L_r.  A counting pass classifies
+//     the slice: alive vertices with prio <= thr form the frontier and are
+//     marked round r; the others survive.  One atomic per counter reserves
+//     the block's output ranges.  The frontier items' count and edge total
+//     share one packed 64-bit atomic, so item order and edge offsets agree.
+//     A writing pass then appends frontier vertices that have edges to the
+//     item list with their edge starts and chunk markers, and the survivors
+//     to L_{r+1}.  Survivors bid their priority for ring.mn[r+1].
+//   grid sync
 //   sweep: edge-balanced over the round's items (PeelEdgeOp).
-//   barrier
-// L_0 is implicit (all vertices).  The loop ends when L_r is empty; every
-// block reads the same counters after a barrier, so all leave together.
+//   grid sync
+// L_0 is implicit (all vertices).  The loop ends when L_r is empty.  Every
+// block reads the same counters after a grid sync, so all leave together.
 __global__ __launch_bounds__(PEEL_BLK) void k_peel_rounds(PeelArgs a) {
-    __shared__ SweepLds s;
+    __shared__ PeelLds lds;
     __shared__ unsigned long long shs[PEEL_BLK / WAVE];
     __shared__ unsigned int shm[PEEL_BLK / WAVE];
     __shared__ unsigned long long s_fbase;
     __shared__ unsigned int s_lbase;
     Ctl* ctl = a.ctl;
+    GridSync* gs = a.gs;
     const unsigned int nblocks = gridDim.x;
+    const unsigned int xid = xcd_id();
+    unsigned int epoch = 0;
     const long long q = a.eps_den, p = a.eps_num;
+    for (int slot = threadIdx.x; slot < PEEL_SLOTS; slot += PEEL_BLK) {
+        lds.dec.key[slot] = DEC_EMPTY;
+        lds.dec.cnt[slot] = 0;
+    }
+    grid_sync_init(gs, nblocks, xid);
     int prevLc = a.n + 1;
     for (int r = 0;; r++) {
         const int slot = r & 3, nslot = (r + 1) & 3;
-        const unsigned int mn = __hip_atomic_load(&ctl->mn[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const int Lc = (r == 0) ? a.n
-                                : (int)__hip_atomic_load(&ctl->lcnt[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned int mn = ld_agent(&ctl->mn[slot]);
+        const int Lc = (r == 0) ? a.n : (int)ld_agent(&ctl->lcnt[slot]);
         if (Lc == 0) {
             if (blockIdx.x == 0 && threadIdx.x == 0) ctl->nrounds = r;
             break;
@@ -490,13 +596,42 @@ __global__ __launch_bounds__(PEEL_BLK) void k_peel_rounds(PeelArgs a) {
         }
         const int* __restrict__ Lin = (r & 1) ? a.L1 : a.L0;
         int* __restrict__ Lout = (r & 1) ? a.L0 : a.L1;
+        // ---------------- select: this block's slice of L_r
+        const int per = (Lc + (int)nblocks - 1) / (int)nblocks;
+        const int beg = min(Lc, (int)blockIdx.x * per), end = min(Lc, beg + per);
         unsigned int lmin = 0xFFFFFFFFu;
-        // ---------------- select
-        for (int base = blockIdx.x * PEEL_BLK; base < Lc; base += nblocks * PEEL_BLK) {
+        unsigned long long my_items = 0, my_edges = 0, my_surv = 0;
+        for (int idx = beg + threadIdx.x; idx < end; idx += PEEL_BLK) {
+            const int u = (r == 0) ? idx : Lin[idx];
+            const int pu = a.prio[u];
+            if ((long long)pu <= thr) {
+                const int d = a.off[u + 1] - a.off[u];
+                if (d > 0) {
+                    my_items++;
+                    my_edges += d;
+                }
+            } else {
+                my_surv++;
+                lmin = min(lmin, (unsigned int)pu);
+            }
+        }
+        {
+            unsigned long long packed = (my_items << FCNT_SHIFT) | my_edges;
+            packed = block_sum<PEEL_BLK>(packed, shs);
+            unsigned long long sv = block_sum<PEEL_BLK>(my_surv, shs);
+            if (threadIdx.x == 0) {
+                s_fbase = packed ? atomicAdd(&ctl->fcnt[slot], packed) : 0ull;
+                s_lbase = sv ? atomicAdd(&ctl->lcnt[nslot], (unsigned int)sv) : 0u;
+            }
+            __syncthreads();
+        }
+        unsigned long long fb = s_fbase;
+        unsigned int lb = s_lbase;
+        for (int base = beg; base < end; base += PEEL_BLK) {
             const int idx = base + threadIdx.x;
             int u = -1, d = 0;
             bool isItem = false, isSurv = false;
-            if (idx < Lc) {
+            if (idx < end) {
                 u = (r == 0) ? idx : Lin[idx];
                 const int pu = a.prio[u];
                 if ((long long)pu <= thr) {
@@ -505,7 +640,6 @@ __global__ __launch_bounds__(PEEL_BLK) void k_peel_rounds(PeelArgs a) {
                     isItem = d > 0;
                 } else {
                     isSurv = true;
-                    lmin = min(lmin, (unsigned int)pu);
                 }
             }
             // packed local scan: [edges:32][survivors:11][items:11]
@@ -513,35 +647,29 @@ __global__ __launch_bounds__(PEEL_BLK) void k_peel_rounds(PeelArgs a) {
                                      (isSurv ? (1ull << 32) : 0ull);
             unsigned long long tot;
             unsigned long long ex = block_excl_scan<PEEL_BLK>(val, &tot, shs);
-            if (threadIdx.x == 0) {
-                const unsigned long long titems = tot >> 43, tsurv = (tot >> 32) & 0x7FF,
-                                         tedges = tot & 0xFFFFFFFFull;
-                s_fbase = (titems | tedges) ? atomicAdd(&ctl->fcnt[slot], (titems << FCNT_SHIFT) | tedges) : 0ull;
-                s_lbase = tsurv ? atomicAdd(&ctl->lcnt[nslot], (unsigned int)tsurv) : 0u;
-            }
-            __syncthreads();
             if (isItem) {
-                const unsigned long long fb = s_fbase;
                 const int item = (int)((fb >> FCNT_SHIFT) + (ex >> 43));
                 const long long start = (long long)(fb & FCNT_MASK) + (long long)(ex & 0xFFFFFFFFull);
                 a.iv[item] = u;
                 a.ie[item] = (int)start;
-                for (long long c = (start + SWEEP_CH - 1) / SWEEP_CH; c * SWEEP_CH < start + d; c++)
+                for (long long c = (start + PEEL_CH - 1) / PEEL_CH; c * PEEL_CH < start + d; c++)
                     a.chunk_item[c] = item;
             }
-            if (isSurv) Lout[s_lbase + (unsigned int)((ex >> 32) & 0x7FF)] = u;
-            __syncthreads();
+            if (isSurv) Lout[lb + (unsigned int)((ex >> 32) & 0x7FF)] = u;
+            fb += ((tot >> 43) << FCNT_SHIFT) + (tot & 0xFFFFFFFFull);
+            lb += (unsigned int)((tot >> 32) & 0x7FF);
         }
-        grid_barrier(ctl, nblocks);
+        grid_sync(gs, xid, epoch);
         // ---------------- sweep
-        const unsigned long long f = __hip_atomic_load(&ctl->fcnt[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned long long f = ld_agent_u64(&ctl->fcnt[slot]);
         const int K = (int)(f >> FCNT_SHIFT);
         const long long E = (long long)(f & FCNT_MASK);
-        PeelEdgeOp op{a.rnd, a.prio, r, lmin, ctl};
-        sweep_chunks<PEEL_BLK>(K, E, a.iv, a.ie, a.chunk_item, a.off, a.adj, a.inc, op, s, blockIdx.x, nblocks);
+        PeelEdgeOp op{a.rnd, a.prio, r, lmin, ctl, &lds.dec};
+        sweep_chunks<PEEL_BLK, PEEL_CH>(K, E, a.iv, a.ie, a.chunk_item, a.off, a.adj, a.inc, op, lds.sw, blockIdx.x,
+                                        nblocks);
         const unsigned int bmin = block_min<PEEL_BLK>(op.lmin, shm);
         if (threadIdx.x == 0 && bmin != 0xFFFFFFFFu) atomicMin(&ctl->mn[nslot], bmin);
-        grid_barrier(ctl, nblocks);
+        grid_sync(gs, xid, epoch);
     }
 }
 
@@ -557,16 +685,23 @@ __global__ void k_sort_pos(int n, const int* __restrict__ order, int* __restrict
 struct SortEdgeOp {
     const int* pos;
     Ctl* ctl;
-    __device__ void flag_error() { atomicAdd(&ctl->err_count, 1); ctl->err_code = ERR_INTERNAL; }
-    __device__ __forceinline__ int item_aux(int v) const { return pos[v]; }
+    int* spos;  // LDS: position of each staged item
+    __device__ void flag_error() {
+        atomicAdd(&ctl->err_count, 1);
+        ctl->err_code = ERR_INTERNAL;
+    }
+    __device__ __forceinline__ void stage_item(int j, int v) { spos[j] = pos[v]; }
     // the edge is charged to v when v comes first in the order
-    __device__ __forceinline__ bool edge(int, int u, int pv) const { return pos[u] > pv; }
+    __device__ __forceinline__ bool edge(int, int u, int j) const { return pos[u] > spos[j]; }
+    __device__ __forceinline__ void flush_chunk() {}
 };
 
 __global__ __launch_bounds__(SORT_BLK) void k_sweep_sort(SweepArgs a) {
-    __shared__ SweepLds s;
-    SortEdgeOp op{a.pos, a.ctl};
-    sweep_chunks<SORT_BLK>(a.K, a.E, a.iv, a.ie, a.chunk_item, a.off, a.adj, a.inc, op, s, blockIdx.x, gridDim.x);
+    __shared__ SweepLds<SORT_CH> s;
+    __shared__ int spos[SORT_CH];
+    SortEdgeOp op{a.pos, a.ctl, spos};
+    sweep_chunks<SORT_BLK, SORT_CH>(a.K, a.E, a.iv, a.ie, a.chunk_item, a.off, a.adj, a.inc, op, s, blockIdx.x,
+                                    gridDim.x);
 }
 
 // =============================================================== SEQ
@@ -840,8 +975,12 @@ static hipError_t enqueue_radix(const GraphDev& g, const int* key_src, int passe
         const int* vin = p == 0 ? nullptr : ((p - 1) & 1 ? g.vB : g.vA);
         int* kout = p == passes - 1 ? nullptr : (p & 1 ? g.kB : g.kA);
         int* vout = p == passes - 1 ? g.order : (p & 1 ? g.vB : g.vA);
+        const int total = RBINS * rt;
+        const int st = ceil_div(total, SCAN_TILE);
         k_radix_hist<<<rt, RBLK, 0, s>>>(kin, g.n, shift, g.rhist, rt, g.ctl, dyn);
-        k_radix_scan<<<1, 1024, 0, s>>>(g.rhist, RBINS * rt, g.ctl, shift, dyn);
+        k_rscan_tiles<<<st, SCAN_BLK, 0, s>>>(g.rhist, total, g.tile_off, g.ctl, shift, dyn);
+        k_rscan_top<<<1, 1024, 0, s>>>(g.tile_off, st, g.ctl, shift, dyn);
+        k_rscan_apply<<<st, SCAN_BLK, 0, s>>>(g.rhist, total, g.tile_off, g.ctl, shift, dyn);
         k_radix_scatter<<<rt, RBLK, 0, s>>>(kin, vin, kout, vout, g.n, shift, g.rhist, rt, g.ctl, dyn);
     }
     return hipGetLastError();
@@ -867,8 +1006,9 @@ static int bits_for(long long maxval) {
     return b;
 }
 
-hipError_t enqueue_iter_peel(const GraphDev& g, int slot, int eps_num, int eps_den, int peel_grid, hipStream_t s) {
-    k_iter_begin<<<1, 64, 0, s>>>(g.ctl);
+hipError_t enqueue_iter_peel(const GraphDev& g, int slot, int eps_num, int eps_den, int peel_grid, hipStream_t s,
+                             hipEvent_t ev_a, hipEvent_t ev_b) {
+    k_iter_begin<<<1, 256, 0, s>>>(g.ctl, g.gsync);
     k_peel_init<<<grid_for(g.n, 256, 2048), 256, 0, s>>>(g.n, g.off, g.load, g.prio, g.rnd, g.inc, g.ctl);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -887,10 +1027,13 @@ hipError_t enqueue_iter_peel(const GraphDev& g, int slot, int eps_num, int eps_d
     a.ie = g.ie;
     a.chunk_item = g.chunk;
     a.ctl = g.ctl;
+    a.gs = g.gsync;
     void* args[] = {&a};
+    if (ev_a && (e = hipEventRecord(ev_a, s)) != hipSuccess) return e;
     e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_peel_rounds), dim3(peel_grid), dim3(PEEL_BLK), args,
                                    0, s);
     if (e != hipSuccess) return e;
+    if (ev_b && (e = hipEventRecord(ev_b, s)) != hipSuccess) return e;
     // rounds <= n, so ceil(bits(n-1)/8) digit passes cover every round index
     int passes = (bits_for(g.n > 1 ? g.n - 1 : 1) + 7) / 8;
     if (passes < 1) passes = 1;
@@ -899,8 +1042,9 @@ hipError_t enqueue_iter_peel(const GraphDev& g, int slot, int eps_num, int eps_d
     return enqueue_alg3(g, slot, 0, s);
 }
 
-hipError_t enqueue_iter_sort(const GraphDev& g, int slot, int key_bits, int sort_grid, hipStream_t s) {
-    k_iter_begin<<<1, 64, 0, s>>>(g.ctl);
+hipError_t enqueue_iter_sort(const GraphDev& g, int slot, int key_bits, int sort_grid, hipStream_t s, hipEvent_t ev_a,
+                             hipEvent_t ev_b) {
+    k_iter_begin<<<1, 64, 0, s>>>(g.ctl, nullptr);
     int passes = (key_bits + 7) / 8;
     if (passes < 1) passes = 1;
     hipError_t e = enqueue_radix(g, g.load, passes, 0, s);
@@ -917,18 +1061,24 @@ hipError_t enqueue_iter_sort(const GraphDev& g, int slot, int key_bits, int sort
     a.inc = g.inc;
     a.pos = g.rnd;
     a.ctl = g.ctl;
+    if (ev_a && (e = hipEventRecord(ev_a, s)) != hipSuccess) return e;
     if (g.nnz > 0) k_sweep_sort<<<sort_grid, SORT_BLK, 0, s>>>(a);
     e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (ev_b && (e = hipEventRecord(ev_b, s)) != hipSuccess) return e;
     if (e != hipSuccess) return e;
     return enqueue_alg3(g, slot, g.n, s);
 }
 
-hipError_t enqueue_iter_seq(const GraphDev& g, int slot, hipStream_t s) {
-    k_iter_begin<<<1, 64, 0, s>>>(g.ctl);
+hipError_t enqueue_iter_seq(const GraphDev& g, int slot, hipStream_t s, hipEvent_t ev_a, hipEvent_t ev_b) {
+    k_iter_begin<<<1, 64, 0, s>>>(g.ctl, nullptr);
+    hipError_t e;
+    if (ev_a && (e = hipEventRecord(ev_a, s)) != hipSuccess) return e;
     k_seq_order<<<1, SEQ_BLK, sizeof(unsigned int) * (size_t)g.n, s>>>(g.n, g.off, g.adj, g.load, g.order, g.rnd,
                                                                           g.inc);
-    hipError_t e = hipGetLastError();
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (ev_b && (e = hipEventRecord(ev_b, s)) != hipSuccess) return e;
     return enqueue_alg3(g, slot, g.n, s);
 }
 

@@ -1,0 +1,81 @@
+"""Write the stored expected values for the full-size parity checks.
+
+Calls only the CPU oracle (oracle/) on graphs from the seeded generators
+(graphgen/); nothing here touches the GPU path.  Usage:
+
+    python tests/golden/make_golden.py config2      # R-MAT scale 22, PEEL eps=1/10, T=20 (~2 min)
+
+Each file records the workload, a hash of the generated CSR (so a generator
+change is caught separately from a peeling mismatch), the per-iteration
+(edges, vertices, index), order digests and round counts, the best subgraph,
+and SHA-256 hashes of the final loads (int64) and of the best-set mask (uint8).
+"""
+import hashlib
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import graphgen  # noqa: E402
+import oracle  # noqa: E402
+
+
+def sha(a) -> str:
+    return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
+
+
+WORKLOADS = {
+    "config2": dict(gen=lambda: graphgen.config2(1), T=20, variant="peel", eps=(1, 10),
+                    desc="R-MAT scale 22, edge factor 16, (a,b,c,d)=(.57,.19,.19,.05), seed 1; PEEL eps=1/10, T=20"),
+    "config2_sort": dict(gen=lambda: graphgen.config2(1), T=20, variant="sort", eps=(0, 1),
+                         desc="R-MAT scale 22 as above; SORT, T=20"),
+}
+
+
+def make(name: str):
+    w = WORKLOADS[name]
+    t0 = time.time()
+    o, a = w["gen"]()
+    print(f"{name}: generated n={len(o) - 1} m={len(a) // 2} in {time.time() - t0:.1f}s", flush=True)
+    st = None
+    for t in range(w["T"]):
+        t1 = time.time()
+        st = oracle.run(o, a, 1, w["variant"], w["eps"], state=st)
+        print(f"  iteration {t + 1}/{w['T']}: {time.time() - t1:.1f}s rounds={st.rounds[-1]} hist={st.hist[-1]}",
+              flush=True)
+    out = {
+        "workload": name,
+        "description": w["desc"],
+        "n": len(o) - 1,
+        "m": len(a) // 2,
+        "csr_sha256": sha(o) + sha(a),
+        "T": w["T"],
+        "variant": w["variant"],
+        "eps": list(w["eps"]),
+        "hist": [list(h) for h in st.hist],
+        "hist_idx": st.hist_idx,
+        "digests": [str(d) for d in st.digests],
+        "rounds": st.rounds,
+        "best": [int(x) for x in st.best],
+        "loads_sha256": sha(st.loads.astype(np.int64)),
+        "loads_sum": int(st.loads.sum()),
+        "best_mask_sha256": sha(st.best_mask().astype(np.uint8)),
+        "last_round_sha256": sha(st.last_round.astype(np.int32)),
+        "last_pos_sha256": sha(st.last_pos.astype(np.int32)),
+        "oracle_seconds": round(time.time() - t0, 1),
+    }
+    path = os.path.join(HERE, f"{name}.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+    print("wrote", path)
+
+
+if __name__ == "__main__":
+    for name in sys.argv[1:] or ["config2"]:
+        make(name)
