@@ -73,6 +73,8 @@ def main():
     ap.add_argument("--scale", type=int, default=22)
     ap.add_argument("--cpu-iters", type=int, default=2, help="oracle iterations timed for cpu_baseline (0 = skip)")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="run one plain device copy of this many MiB first (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -92,6 +94,13 @@ def main():
     n, m = len(offsets) - 1, len(adj) // 2
     workload = f"rmat{args.scale}_{args.variant}"
     log(f"generated R-MAT scale {args.scale}: n={n} m={m} in {time.time() - t0:.1f}s")
+
+    if args.copy_calib_mib > 0:
+        src = torch.ones(args.copy_calib_mib << 18, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     ctx = dsg.Context(0)
     g = dsg.Graph(ctx, offsets, adj, t_cap=T)

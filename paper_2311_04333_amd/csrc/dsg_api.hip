@@ -87,8 +87,9 @@ long long carve(int n, long long nnz, int t_cap, char* base, GraphDev* g) {
     long long o_order = L.add(4 * N), o_best = L.add(4 * N);
     long long o_kA = L.add(4 * N), o_kB = L.add(4 * N), o_vA = L.add(4 * N), o_vB = L.add(4 * N);
     long long o_L0 = L.add(4 * N), o_L1 = L.add(4 * N), o_iv = L.add(4 * N), o_ie = L.add(4 * (N + 1));
+    long long o_ir = L.add(4 * N), o_sir = L.add(4 * N), o_iv1 = L.add(4 * N), o_st2 = L.add(4 * ((N + 15) / 16 + 1));
     long long o_siv = L.add(4 * N), o_sie = L.add(4 * (N + 1)), o_A = L.add(4 * N);
-    long long o_chunk = L.add(4 * nch), o_schunk = L.add(4 * nch);
+    long long o_cf = L.add(4 * nch), o_cl = L.add(4 * nch), o_scf = L.add(4 * nch), o_scl = L.add(4 * nch);
     long long o_ts = L.add(8 * ntiles), o_to = L.add(8 * ntiles), o_tb = L.add(24 * ntiles);
     long long o_rh = L.add(4 * 256 * rtiles);
     long long o_he = L.add(8LL * t_cap), o_hv = L.add(8LL * t_cap), o_hi = L.add(4LL * t_cap);
@@ -113,8 +114,14 @@ long long carve(int n, long long nnz, int t_cap, char* base, GraphDev* g) {
         g->siv = reinterpret_cast<int*>(base + o_siv);
         g->sie = reinterpret_cast<int*>(base + o_sie);
         g->A = reinterpret_cast<int*>(base + o_A);
-        g->chunk = reinterpret_cast<int*>(base + o_chunk);
-        g->schunk = reinterpret_cast<int*>(base + o_schunk);
+        g->ir = reinterpret_cast<int*>(base + o_ir);
+        g->iv1 = reinterpret_cast<int*>(base + o_iv1);
+        g->st2 = reinterpret_cast<unsigned int*>(base + o_st2);
+        g->sir = reinterpret_cast<int*>(base + o_sir);
+        g->cfirst = reinterpret_cast<int*>(base + o_cf);
+        g->clast = reinterpret_cast<int*>(base + o_cl);
+        g->scf = reinterpret_cast<int*>(base + o_scf);
+        g->scl = reinterpret_cast<int*>(base + o_scl);
         g->tile_sum = reinterpret_cast<long long*>(base + o_ts);
         g->tile_off = reinterpret_cast<long long*>(base + o_to);
         g->tile_best = reinterpret_cast<long long*>(base + o_tb);

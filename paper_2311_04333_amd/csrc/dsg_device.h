@@ -20,6 +20,7 @@ struct alignas(256) Ctl {
     unsigned int mn[4];
     unsigned int lcnt[4];
     unsigned long long fcnt[4];
+    unsigned int cnext[4];  // next sweep chunk to hand out, per round
     // results of the current iteration
     int nrounds;
     int improved;
@@ -136,6 +137,17 @@ __device__ __forceinline__ T block_min(T v, T* sh) {
     for (int w = 1; w < NW; w++) m = sh[w] < m ? sh[w] : m;
     __syncthreads();
     return m;
+}
+
+// Block barrier that orders LDS only: waits for this wave's LDS operations,
+// then s_barrier.  Unlike __syncthreads it does not wait for outstanding
+// global memory operations, so fire-and-forget global atomics stay in
+// flight across it.  Use only where no global data written before it is
+// read by another thread after it.
+__device__ __forceinline__ void lds_barrier() {
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
 }
 
 // ------------------------------------------------------------ grid barrier

@@ -31,9 +31,13 @@ struct PeelArgs {
     int* inc;
     int* L0;
     int* L1;
-    int* iv;
+    int* iv0;  // item vertices of even rounds
+    int* iv1;  // item vertices of odd rounds
+    unsigned int* st2;
     int* ie;
-    int* chunk_item;
+    int* ir;
+    int* cfirst;
+    int* clast;
     Ctl* ctl;
     GridSync* gs;
 };
@@ -44,7 +48,9 @@ struct SweepArgs {
     long long E;
     const int* iv;
     const int* ie;
-    const int* chunk_item;
+    const int* ir;
+    const int* cfirst;
+    const int* clast;
     const int* off;
     const int* adj;
     int* inc;
@@ -73,12 +79,18 @@ struct GraphDev {
     int* L0;
     int* L1;
     int* iv;
+    int* iv1;
+    unsigned int* st2;
     int* ie;
+    int* ir;
     int* siv;
     int* sie;
+    int* sir;
     int* A;
-    int* chunk;
-    int* schunk;
+    int* cfirst;
+    int* clast;
+    int* scf;
+    int* scl;
     long long* tile_sum;
     long long* tile_off;
     long long* tile_best;

@@ -319,9 +319,19 @@ __global__ __launch_bounds__(RBLK) void k_radix_scatter(const int* __restrict__ 
     (void)tbase;
 }
 
+// Writes the chunk markers of one item occupying edges [start, end).
+template <int CH>
+__device__ __forceinline__ void mark_chunks(long long start, long long end, int item, int* __restrict__ cfirst,
+                                            int* __restrict__ clast) {
+    for (long long c = (start + CH - 1) / CH; c * CH < end; c++) cfirst[c] = item;
+    // chunk c's last edge (c+1)*CH - 1 lies in [start, end)
+    for (long long c = (start + 1 + CH - 1) / CH - 1; (c + 1) * CH <= end; c++) clast[c] = item;
+}
+
+
 // ============================================================ static items
 // Items of the full graph for the SORT sweep: every vertex with degree > 0,
-// in id order, with its edge start; chunk_item[c] = item containing edge c*CH.
+// in id order, with its edge start, row base and chunk markers.
 __global__ void k_nonzero_flags(int n, const int* __restrict__ off, int* __restrict__ flag) {
     for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
         flag[v] = off[v + 1] > off[v] ? 1 : 0;
@@ -330,7 +340,8 @@ __global__ void k_nonzero_flags(int n, const int* __restrict__ off, int* __restr
 __global__ __launch_bounds__(SCAN_BLK) void k_compact_items(int n, const int* __restrict__ off,
                                                             const long long* __restrict__ tile_off,
                                                             int* __restrict__ iv, int* __restrict__ ie,
-                                                            int* __restrict__ chunk_item) {
+                                                            int* __restrict__ ir, int* __restrict__ cfirst,
+                                                            int* __restrict__ clast) {
     __shared__ int sh[SCAN_BLK / WAVE];
     long long base = (long long)blockIdx.x * SCAN_TILE;
     long long run = tile_off[blockIdx.x];
@@ -348,101 +359,119 @@ __global__ __launch_bounds__(SCAN_BLK) void k_compact_items(int n, const int* __
             int item = (int)(run + ex);
             iv[item] = (int)v;
             ie[item] = a;
-            for (long long c = ((long long)a + SORT_CH - 1) / SORT_CH; c * SORT_CH < b; c++) chunk_item[c] = item;
+            ir[item] = 0;  // the whole graph's rows are already concatenated in order
+            mark_chunks<SORT_CH>(a, b, item, cfirst, clast);
         }
         run += tot;
     }
 }
 
 // ========================================================== edge sweep
-// Edge-balanced sweep over the concatenated rows of an item list.  Block b
-// takes chunks c = b, b + grid, ... of CH consecutive edges.  The items
-// overlapping a chunk are staged in LDS; there are at most CH of them,
-// since every item has an edge in the chunk.  Each thread finds its edge's
-// item by binary search there.  Per-item counts are gathered in LDS and
-// added to inc[] once per chunk.  Op decides what an edge (v, u)
-// contributes.
+// Edge-balanced sweep over the concatenated rows of an item list.  An item
+// list holds, per item k: its vertex iv[k], its first edge ie[k] in the
+// concatenation, and ir[k] = offsets[v] - ie[k], so edge x of the item is
+// adj[ir[k] + x].  For every chunk c of CH consecutive edges it also holds
+// cfirst[c] and clast[c], the items holding the chunk's first and last edge
+// (clast of the final chunk is K - 1).  Block b takes chunks b, b + grid,
+// and so on.  The chunk's items (at most CH, since each has an edge in the
+// chunk) are staged in LDS.  Each thread handles EPT = CH / BLK edges.  It
+// finds their items by binary search in LDS, issues all EPT adjacency loads,
+// then all EPT neighbour-state gathers, then processes them.  That costs
+// two memory round trips per chunk instead of two per edge.  Per-item
+// counts are gathered in LDS and added to inc[] once per chunk.
 template <int CH>
 struct SweepLds {
     int fe[CH];
-    int row[CH];
+    int rb[CH];
     int v[CH];
     int cnt[CH];
 };
 
-// Open-addressing LDS table that aggregates degree decrements per target
-// vertex within one chunk.  A hub adjacent to many of the chunk's edges then
-// receives one global atomic instead of one per edge (same-address atomics
-// serialise at about 11 ns each).  At most CH distinct keys go into 2*CH
-// slots, so probing always finds a free slot.
-template <int SLOTS>
-struct DecTable {
-    int key[SLOTS];
-    int cnt[SLOTS];
-};
-constexpr int DEC_EMPTY = -1;
-
-template <int SLOTS>
-__device__ __forceinline__ void dec_add(DecTable<SLOTS>& t, int u) {
-    unsigned int h = ((unsigned int)u * 0x9E3779B1u) >> (32 - __builtin_ctz(SLOTS));
-    while (true) {
-        int k = atomicCAS(&t.key[h], DEC_EMPTY, u);
-        if (k == DEC_EMPTY || k == u) {
-            atomicAdd(&t.cnt[h], 1);
-            return;
-        }
-        h = (h + 1) & (SLOTS - 1);
-    }
-}
-
+// Chunks are handed out by an atomic counter (`cnext`, zero at the start)
+// when it is given, else statically (b, b + grid, ...).  The block
+// barriers inside a chunk order LDS only, so the chunk's global atomics
+// (charges, aggregated decrements) overlap the next chunk's loads.
 template <int BLK, int CH, class Op>
 __device__ __forceinline__ void sweep_chunks(int K, long long E, const int* __restrict__ iv, const int* __restrict__ ie,
-                                             const int* __restrict__ chunk_item, const int* __restrict__ off,
-                                             const int* __restrict__ adj, int* __restrict__ inc, Op& op,
-                                             SweepLds<CH>& s, int block, int nblocks) {
+                                             const int* __restrict__ ir, const int* __restrict__ cfirst,
+                                             const int* __restrict__ clast, const int* __restrict__ adj,
+                                             int* __restrict__ inc, Op& op, SweepLds<CH>& s, int block, int nblocks,
+                                             unsigned int* cnext, int* s_chunk) {
+    constexpr int EPT = CH / BLK;
+    static_assert(EPT * BLK == CH, "chunk must be a multiple of the block");
     const long long nchunks = (E + CH - 1) / CH;
-    for (long long c = block; c < nchunks; c += nblocks) {
+    long long c = block;
+    if (cnext) {
+        if (threadIdx.x == 0) *s_chunk = (int)atomicAdd(cnext, 1u);
+        lds_barrier();
+        c = *s_chunk;
+        lds_barrier();
+    }
+    for (; c < nchunks;) {
         const long long x0 = c * CH;
         const long long x1 = min(E, x0 + CH);
-        const int k0 = chunk_item[c];
-        int k1;
-        if (c + 1 < nchunks) {
-            k1 = chunk_item[c + 1];
-            if ((long long)ie[k1] == x1) k1 -= 1;
-        } else {
-            k1 = K - 1;
-        }
+        const int k0 = cfirst[c];
+        const int k1 = (c + 1 < nchunks) ? clast[c] : K - 1;
         const int nitems = k1 - k0 + 1;
         if (nitems < 1 || nitems > CH) {
             // impossible when every item has an edge in the chunk; refuse to
             // index LDS out of range if the item list is ever inconsistent
             if (threadIdx.x == 0) op.flag_error();
-            continue;
+            break;
         }
+        // grab the next chunk while this one is processed
+        if (cnext && threadIdx.x == 0) *s_chunk = (int)atomicAdd(cnext, 1u);
         for (int j = threadIdx.x; j < nitems; j += BLK) {
-            int v = iv[k0 + j];
+            const int v = iv[k0 + j];
             s.fe[j] = ie[k0 + j];
+            s.rb[j] = ir[k0 + j];
             s.v[j] = v;
-            s.row[j] = off[v];
             s.cnt[j] = 0;
             op.stage_item(j, v);
         }
-        __syncthreads();
-        for (long long x = x0 + threadIdx.x; x < x1; x += BLK) {
-            int lo = 0, hi = nitems - 1;
-            while (lo < hi) {
-                int mid = (lo + hi + 1) >> 1;
-                if ((long long)s.fe[mid] <= x) lo = mid; else hi = mid - 1;
+        lds_barrier();
+        // thread t owns the EPT consecutive edges from x0 + t*EPT: one binary
+        // search for the first, then a linear advance over item boundaries
+        const int xs = (int)x0 + (int)threadIdx.x * EPT;
+        int jj[EPT], uu[EPT], st[EPT];
+        {
+            int j = 0;
+            if ((long long)xs < x1) {
+                int hi = nitems - 1;
+                while (j < hi) {
+                    int mid = (j + hi + 1) >> 1;
+                    if (s.fe[mid] <= xs) j = mid; else hi = mid - 1;
+                }
             }
-            const int v = s.v[lo];
-            const int u = adj[s.row[lo] + (int)(x - s.fe[lo])];
-            if (op.edge(v, u, lo)) atomicAdd(&s.cnt[lo], 1);
+#pragma unroll
+            for (int e = 0; e < EPT; e++) {
+                const int x = xs + e;
+                if ((long long)x < x1) {
+                    while (j + 1 < nitems && s.fe[j + 1] <= x) j++;
+                    jj[e] = j;
+                    uu[e] = adj[s.rb[j] + x];
+                } else {
+                    jj[e] = -1;
+                    uu[e] = 0;
+                }
+            }
         }
-        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < EPT; e++) st[e] = jj[e] >= 0 ? op.gather(uu[e]) : 0;
+#pragma unroll
+        for (int e = 0; e < EPT; e++)
+            if (jj[e] >= 0 && op.edge(s.v[jj[e]], uu[e], st[e], jj[e])) atomicAdd(&s.cnt[jj[e]], 1);
+        lds_barrier();
         for (int j = threadIdx.x; j < nitems; j += BLK)
             if (s.cnt[j]) atomicAdd(&inc[s.v[j]], s.cnt[j]);
         op.flush_chunk();
-        __syncthreads();
+        lds_barrier();
+        if (cnext) {
+            c = *s_chunk;
+            lds_barrier();
+        } else {
+            c += nblocks;
+        }
     }
 }
 
@@ -451,9 +480,13 @@ __device__ __forceinline__ void sweep_chunks(int K, long long E, const int* __re
 // the minimum priority seeds round 0.
 __global__ __launch_bounds__(256) void k_peel_init(int n, const int* __restrict__ off, const int* __restrict__ load,
                                                    int* __restrict__ prio, int* __restrict__ rnd,
-                                                   int* __restrict__ inc, Ctl* ctl) {
+                                                   int* __restrict__ inc, unsigned int* __restrict__ st2, Ctl* ctl) {
     __shared__ unsigned int sh[256 / WAVE];
     unsigned int lmin = 0xFFFFFFFFu;
+    // 2-bit state per vertex, 16 per word: every vertex alive (01), none in
+    // a frontier
+    for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < (n + 15) / 16; w += gridDim.x * blockDim.x)
+        st2[w] = 0x55555555u;
     for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
         int p = load[v] + (off[v + 1] - off[v]);
         prio[v] = p;
@@ -471,6 +504,7 @@ __global__ void k_iter_begin(Ctl* ctl, GridSync* gs) {
         ctl->mn[threadIdx.x] = 0xFFFFFFFFu;
         ctl->lcnt[threadIdx.x] = 0;
         ctl->fcnt[threadIdx.x] = 0;
+        ctl->cnext[threadIdx.x] = 0;
     }
     if (threadIdx.x == 0) {
         ctl->nrounds = 0;
@@ -482,11 +516,23 @@ __global__ void k_iter_begin(Ctl* ctl, GridSync* gs) {
     }
 }
 
-constexpr int PEEL_SLOTS = 2 * PEEL_CH;
+// Open-addressing LDS table that aggregates degree decrements per target
+// vertex within one chunk.  A hub adjacent to many of the chunk's edges then
+// receives one global atomic instead of one per edge (same-address atomics
+// serialise at about 11 ns each).  Probing is bounded; a target that finds
+// no slot within PROBE steps is decremented directly in global memory.
+constexpr int DEC_SLOTS = 2 * PEEL_CH;  // at most PEEL_CH keys: probing always finds a slot
+constexpr int DEC_PROBE = 64;
+constexpr int DEC_EMPTY = -1;
+
+struct DecTable {
+    int key[DEC_SLOTS];
+    int cnt[DEC_SLOTS];
+};
 
 struct PeelLds {
     SweepLds<PEEL_CH> sw;
-    DecTable<PEEL_SLOTS> dec;
+    DecTable dec;
 };
 
 // What an edge (v, u) of a frontier vertex v does in round r:
@@ -496,34 +542,65 @@ struct PeelLds {
 //     Its last decrement yields its final value.
 //   u peeled in the same round: the edge goes to the lower id.
 //   u peeled earlier: nothing.
+// Vertex state during a round, 2 bits per vertex packed 16 to a word (so the
+// state of a 4M-vertex graph is 1 MB and stays in each XCD's L2 during the
+// sweep): bit 0 = not peeled before this round, bit 1 = in this round's
+// frontier.  01 = survives the round, 11 = peeled this round, 00 = peeled
+// earlier.
+__device__ __forceinline__ int st2_get(const unsigned int* st2, int u) {
+    return (int)((st2[u >> 4] >> ((u & 15) * 2)) & 3u);
+}
+
 struct PeelEdgeOp {
-    const int* rnd;
+    const unsigned int* st2;
     int* prio;
     int r;
     unsigned int lmin;
     Ctl* ctl;
-    DecTable<PEEL_SLOTS>* dec;
+    DecTable* dec;
     __device__ void flag_error() {
         atomicAdd(&ctl->err_count, 1);
         ctl->err_code = ERR_INTERNAL;
     }
     __device__ __forceinline__ void stage_item(int, int) {}
-    __device__ __forceinline__ bool edge(int v, int u, int) {
-        const int ru = rnd[u];
-        if (ru < 0) {
-            dec_add(*dec, u);
+    __device__ __forceinline__ int gather(int u) const { return st2_get(st2, u); }
+    __device__ __forceinline__ bool edge(int v, int u, int su, int) {
+        if (su == 1) {
+            unsigned int h = ((unsigned int)u * 0x9E3779B1u) >> (32 - __builtin_ctz(DEC_SLOTS));
+#pragma unroll 1
+            for (int probe = 0; probe < DEC_PROBE; probe++) {
+                const int k = atomicCAS(&dec->key[h], DEC_EMPTY, u);
+                if (k == DEC_EMPTY || k == u) {
+                    atomicAdd(&dec->cnt[h], 1);
+                    return true;
+                }
+                h = (h + 1) & (DEC_SLOTS - 1);
+            }
+            const int old = atomicSub(&prio[u], 1);
+            lmin = min(lmin, (unsigned int)(old - 1));
             return true;
         }
-        return ru == r && u > v;
+        return su == 3 && u > v;
     }
     __device__ __forceinline__ void flush_chunk() {
-        __syncthreads();
-        for (int slot = threadIdx.x; slot < PEEL_SLOTS; slot += blockDim.x) {
-            const int u = dec->key[slot];
-            if (u != DEC_EMPTY) {
-                const int c = dec->cnt[slot];
-                const int old = atomicSub(&prio[u], c);
-                lmin = min(lmin, (unsigned int)(old - c));
+        constexpr int PER = DEC_SLOTS / PEEL_BLK;
+        static_assert(PER * PEEL_BLK == DEC_SLOTS, "slots must be a multiple of the block");
+        lds_barrier();
+        int key[PER], c[PER], old[PER];
+#pragma unroll
+        for (int k = 0; k < PER; k++) {
+            const int slot = threadIdx.x + k * PEEL_BLK;
+            key[k] = dec->key[slot];
+            c[k] = dec->cnt[slot];
+        }
+#pragma unroll
+        for (int k = 0; k < PER; k++)
+            if (key[k] != DEC_EMPTY) old[k] = atomicSub(&prio[key[k]], c[k]);
+#pragma unroll
+        for (int k = 0; k < PER; k++) {
+            if (key[k] != DEC_EMPTY) {
+                lmin = min(lmin, (unsigned int)(old[k] - c[k]));
+                const int slot = threadIdx.x + k * PEEL_BLK;
                 dec->key[slot] = DEC_EMPTY;
                 dec->cnt[slot] = 0;
             }
@@ -533,6 +610,13 @@ struct PeelEdgeOp {
 
 constexpr unsigned long long FCNT_SHIFT = 38;
 constexpr unsigned long long FCNT_MASK = (1ull << FCNT_SHIFT) - 1;
+constexpr int SEL_U = 4;  // alive-list entries per thread per select tile
+// Packed per-tile scan value: [edges: bits 0-31][survivors: 32-44][items: 45-57].
+// A tile holds PEEL_BLK * SEL_U entries, so each count field needs 13 bits.
+constexpr int TSURV_SHIFT = 32;
+constexpr int TITEM_SHIFT = 45;
+constexpr unsigned long long TCNT_MASK = 0x1FFFull;
+static_assert(PEEL_BLK * SEL_U <= (int)TCNT_MASK, "tile counts must fit their packed fields");
 
 // Persistent round loop of one PEEL iteration (cooperative launch, one block
 // per CU).  Per round r:
@@ -542,9 +626,9 @@ constexpr unsigned long long FCNT_MASK = (1ull << FCNT_SHIFT) - 1;
 //     marked round r; the others survive.  One atomic per counter reserves
 //     the block's output ranges.  The frontier items' count and edge total
 //     share one packed 64-bit atomic, so item order and edge offsets agree.
-//     A writing pass then appends frontier vertices that have edges to the
-//     item list with their edge starts and chunk markers, and the survivors
-//     to L_{r+1}.  Survivors bid their priority for ring.mn[r+1].
+//     A writing pass then appends the frontier vertices that have edges to
+//     the item list (vertex, edge start, row base, chunk markers) and the
+//     survivors to L_{r+1}.  Survivors bid their priority for ring.mn[r+1].
 //   grid sync
 //   sweep: edge-balanced over the round's items (PeelEdgeOp).
 //   grid sync
@@ -556,13 +640,14 @@ __global__ __launch_bounds__(PEEL_BLK) void k_peel_rounds(PeelArgs a) {
     __shared__ unsigned int shm[PEEL_BLK / WAVE];
     __shared__ unsigned long long s_fbase;
     __shared__ unsigned int s_lbase;
+    __shared__ int s_chunk;
     Ctl* ctl = a.ctl;
     GridSync* gs = a.gs;
     const unsigned int nblocks = gridDim.x;
     const unsigned int xid = xcd_id();
     unsigned int epoch = 0;
     const long long q = a.eps_den, p = a.eps_num;
-    for (int slot = threadIdx.x; slot < PEEL_SLOTS; slot += PEEL_BLK) {
+    for (int slot = threadIdx.x; slot < DEC_SLOTS; slot += PEEL_BLK) {
         lds.dec.key[slot] = DEC_EMPTY;
         lds.dec.cnt[slot] = 0;
     }
@@ -593,26 +678,58 @@ __global__ __launch_bounds__(PEEL_BLK) void k_peel_rounds(PeelArgs a) {
             ctl->mn[zs] = 0xFFFFFFFFu;
             ctl->lcnt[zs] = 0;
             ctl->fcnt[zs] = 0;
+            ctl->cnext[zs] = 0;
         }
         const int* __restrict__ Lin = (r & 1) ? a.L1 : a.L0;
         int* __restrict__ Lout = (r & 1) ? a.L0 : a.L1;
-        // ---------------- select: this block's slice of L_r
+        int* __restrict__ ivr = (r & 1) ? a.iv1 : a.iv0;  // this round's item vertices
+        if (r > 0) {
+            // the previous round's frontier is peeled now: clear its state
+            // bits (its vertices with edges are exactly its item list; the
+            // isolated ones are never looked up)
+            const int* __restrict__ ivp = (r & 1) ? a.iv0 : a.iv1;
+            const int Kp = (int)(ld_agent_u64(&ctl->fcnt[(r - 1) & 3]) >> FCNT_SHIFT);
+            for (int k = blockIdx.x * PEEL_BLK + threadIdx.x; k < Kp; k += nblocks * PEEL_BLK) {
+                const int u = ivp[k];
+                atomicAnd(&a.st2[u >> 4], ~(3u << ((u & 15) * 2)));
+            }
+        }
+        // ---------------- select: this block's slice of L_r, in tiles of
+        // PEEL_BLK * SEL_U entries; thread t owns SEL_U consecutive entries
         const int per = (Lc + (int)nblocks - 1) / (int)nblocks;
         const int beg = min(Lc, (int)blockIdx.x * per), end = min(Lc, beg + per);
+        constexpr int TILE = PEEL_BLK * SEL_U;
         unsigned int lmin = 0xFFFFFFFFu;
         unsigned long long my_items = 0, my_edges = 0, my_surv = 0;
-        for (int idx = beg + threadIdx.x; idx < end; idx += PEEL_BLK) {
-            const int u = (r == 0) ? idx : Lin[idx];
-            const int pu = a.prio[u];
-            if ((long long)pu <= thr) {
-                const int d = a.off[u + 1] - a.off[u];
-                if (d > 0) {
-                    my_items++;
-                    my_edges += d;
+        for (int base = beg; base < end; base += TILE) {
+            int u[SEL_U], pu[SEL_U];
+#pragma unroll
+            for (int k = 0; k < SEL_U; k++) {
+                const int idx = base + (int)threadIdx.x * SEL_U + k;
+                u[k] = idx < end ? ((r == 0) ? idx : Lin[idx]) : -1;
+            }
+#pragma unroll
+            for (int k = 0; k < SEL_U; k++) pu[k] = u[k] >= 0 ? a.prio[u[k]] : 0;
+            int o0[SEL_U], o1[SEL_U];
+#pragma unroll
+            for (int k = 0; k < SEL_U; k++) {
+                const bool fr = u[k] >= 0 && (long long)pu[k] <= thr;
+                o0[k] = fr ? a.off[u[k]] : 0;
+                o1[k] = fr ? a.off[u[k] + 1] : 0;
+            }
+#pragma unroll
+            for (int k = 0; k < SEL_U; k++) {
+                if (u[k] < 0) continue;
+                if ((long long)pu[k] <= thr) {
+                    const int d = o1[k] - o0[k];
+                    if (d > 0) {
+                        my_items++;
+                        my_edges += d;
+                    }
+                } else {
+                    my_surv++;
+                    lmin = min(lmin, (unsigned int)pu[k]);
                 }
-            } else {
-                my_surv++;
-                lmin = min(lmin, (unsigned int)pu);
             }
         }
         {
@@ -627,46 +744,70 @@ __global__ __launch_bounds__(PEEL_BLK) void k_peel_rounds(PeelArgs a) {
         }
         unsigned long long fb = s_fbase;
         unsigned int lb = s_lbase;
-        for (int base = beg; base < end; base += PEEL_BLK) {
-            const int idx = base + threadIdx.x;
-            int u = -1, d = 0;
-            bool isItem = false, isSurv = false;
-            if (idx < end) {
-                u = (r == 0) ? idx : Lin[idx];
-                const int pu = a.prio[u];
-                if ((long long)pu <= thr) {
-                    a.rnd[u] = r;
-                    d = a.off[u + 1] - a.off[u];
-                    isItem = d > 0;
+        for (int base = beg; base < end; base += TILE) {
+            int u[SEL_U], pu[SEL_U];
+#pragma unroll
+            for (int k = 0; k < SEL_U; k++) {
+                const int idx = base + (int)threadIdx.x * SEL_U + k;
+                u[k] = idx < end ? ((r == 0) ? idx : Lin[idx]) : -1;
+            }
+#pragma unroll
+            for (int k = 0; k < SEL_U; k++) pu[k] = u[k] >= 0 ? a.prio[u[k]] : 0;
+            int o0[SEL_U], o1[SEL_U];
+#pragma unroll
+            for (int k = 0; k < SEL_U; k++) {
+                const bool fr = u[k] >= 0 && (long long)pu[k] <= thr;
+                o0[k] = fr ? a.off[u[k]] : 0;
+                o1[k] = fr ? a.off[u[k] + 1] : 0;
+            }
+            unsigned long long val = 0;
+#pragma unroll
+            for (int k = 0; k < SEL_U; k++) {
+                if (u[k] < 0) continue;
+                if ((long long)pu[k] <= thr) {
+                    a.rnd[u[k]] = r;
+                    const int d = o1[k] - o0[k];
+                    if (d > 0) {
+                        val += (1ull << TITEM_SHIFT) + (unsigned long long)d;
+                        atomicOr(&a.st2[u[k] >> 4], 2u << ((u[k] & 15) * 2));
+                    }
                 } else {
-                    isSurv = true;
+                    val += 1ull << TSURV_SHIFT;
                 }
             }
-            // packed local scan: [edges:32][survivors:11][items:11]
-            unsigned long long val = (isItem ? ((1ull << 43) | (unsigned long long)d) : 0ull) |
-                                     (isSurv ? (1ull << 32) : 0ull);
             unsigned long long tot;
             unsigned long long ex = block_excl_scan<PEEL_BLK>(val, &tot, shs);
-            if (isItem) {
-                const int item = (int)((fb >> FCNT_SHIFT) + (ex >> 43));
-                const long long start = (long long)(fb & FCNT_MASK) + (long long)(ex & 0xFFFFFFFFull);
-                a.iv[item] = u;
-                a.ie[item] = (int)start;
-                for (long long c = (start + PEEL_CH - 1) / PEEL_CH; c * PEEL_CH < start + d; c++)
-                    a.chunk_item[c] = item;
+            unsigned long long it = (fb >> FCNT_SHIFT) + (ex >> TITEM_SHIFT);
+            unsigned long long ed = (fb & FCNT_MASK) + (ex & 0xFFFFFFFFull);
+            unsigned int sv = lb + (unsigned int)((ex >> TSURV_SHIFT) & TCNT_MASK);
+#pragma unroll
+            for (int k = 0; k < SEL_U; k++) {
+                if (u[k] < 0) continue;
+                if ((long long)pu[k] <= thr) {
+                    const int d = o1[k] - o0[k];
+                    if (d > 0) {
+                        ivr[it] = u[k];
+                        a.ie[it] = (int)ed;
+                        a.ir[it] = o0[k] - (int)ed;
+                        mark_chunks<PEEL_CH>((long long)ed, (long long)ed + d, (int)it, a.cfirst, a.clast);
+                        it++;
+                        ed += d;
+                    }
+                } else {
+                    Lout[sv++] = u[k];
+                }
             }
-            if (isSurv) Lout[lb + (unsigned int)((ex >> 32) & 0x7FF)] = u;
-            fb += ((tot >> 43) << FCNT_SHIFT) + (tot & 0xFFFFFFFFull);
-            lb += (unsigned int)((tot >> 32) & 0x7FF);
+            fb += ((tot >> TITEM_SHIFT) << FCNT_SHIFT) + (tot & 0xFFFFFFFFull);
+            lb += (unsigned int)((tot >> TSURV_SHIFT) & TCNT_MASK);
         }
         grid_sync(gs, xid, epoch);
         // ---------------- sweep
         const unsigned long long f = ld_agent_u64(&ctl->fcnt[slot]);
         const int K = (int)(f >> FCNT_SHIFT);
         const long long E = (long long)(f & FCNT_MASK);
-        PeelEdgeOp op{a.rnd, a.prio, r, lmin, ctl, &lds.dec};
-        sweep_chunks<PEEL_BLK, PEEL_CH>(K, E, a.iv, a.ie, a.chunk_item, a.off, a.adj, a.inc, op, lds.sw, blockIdx.x,
-                                        nblocks);
+        PeelEdgeOp op{a.st2, a.prio, r, lmin, ctl, &lds.dec};
+        sweep_chunks<PEEL_BLK, PEEL_CH>(K, E, ivr, a.ie, a.ir, a.cfirst, a.clast, a.adj, a.inc, op, lds.sw,
+                                        blockIdx.x, nblocks, &ctl->cnext[slot], &s_chunk);
         const unsigned int bmin = block_min<PEEL_BLK>(op.lmin, shm);
         if (threadIdx.x == 0 && bmin != 0xFFFFFFFFu) atomicMin(&ctl->mn[nslot], bmin);
         grid_sync(gs, xid, epoch);
@@ -691,8 +832,9 @@ struct SortEdgeOp {
         ctl->err_code = ERR_INTERNAL;
     }
     __device__ __forceinline__ void stage_item(int j, int v) { spos[j] = pos[v]; }
+    __device__ __forceinline__ int gather(int u) const { return pos[u]; }
     // the edge is charged to v when v comes first in the order
-    __device__ __forceinline__ bool edge(int, int u, int j) const { return pos[u] > spos[j]; }
+    __device__ __forceinline__ bool edge(int, int, int pu, int j) const { return pu > spos[j]; }
     __device__ __forceinline__ void flush_chunk() {}
 };
 
@@ -700,8 +842,8 @@ __global__ __launch_bounds__(SORT_BLK) void k_sweep_sort(SweepArgs a) {
     __shared__ SweepLds<SORT_CH> s;
     __shared__ int spos[SORT_CH];
     SortEdgeOp op{a.pos, a.ctl, spos};
-    sweep_chunks<SORT_BLK, SORT_CH>(a.K, a.E, a.iv, a.ie, a.chunk_item, a.off, a.adj, a.inc, op, s, blockIdx.x,
-                                    gridDim.x);
+    sweep_chunks<SORT_BLK, SORT_CH>(a.K, a.E, a.iv, a.ie, a.ir, a.cfirst, a.clast, a.adj, a.inc, op, s, blockIdx.x,
+                                    gridDim.x, nullptr, nullptr);
 }
 
 // =============================================================== SEQ
@@ -954,7 +1096,7 @@ hipError_t launch_build_static_items(const GraphDev& g, hipStream_t s) {
     k_scan_top<<<1, 1024, 0, s>>>(g.tile_sum, ntiles, g.tile_off);
     // tile_off[0] receives the total after the scan of tile_sum in place; the
     // compaction reads the scanned tile_sum as its offsets
-    k_compact_items<<<ntiles, SCAN_BLK, 0, s>>>(g.n, g.off, g.tile_sum, g.siv, g.sie, g.schunk);
+    k_compact_items<<<ntiles, SCAN_BLK, 0, s>>>(g.n, g.off, g.tile_sum, g.siv, g.sie, g.sir, g.scf, g.scl);
     return hipGetLastError();
 }
 
@@ -1009,7 +1151,7 @@ static int bits_for(long long maxval) {
 hipError_t enqueue_iter_peel(const GraphDev& g, int slot, int eps_num, int eps_den, int peel_grid, hipStream_t s,
                              hipEvent_t ev_a, hipEvent_t ev_b) {
     k_iter_begin<<<1, 256, 0, s>>>(g.ctl, g.gsync);
-    k_peel_init<<<grid_for(g.n, 256, 2048), 256, 0, s>>>(g.n, g.off, g.load, g.prio, g.rnd, g.inc, g.ctl);
+    k_peel_init<<<grid_for(g.n, 256, 2048), 256, 0, s>>>(g.n, g.off, g.load, g.prio, g.rnd, g.inc, g.st2, g.ctl);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     PeelArgs a{};
@@ -1023,9 +1165,13 @@ hipError_t enqueue_iter_peel(const GraphDev& g, int slot, int eps_num, int eps_d
     a.inc = g.inc;
     a.L0 = g.L0;
     a.L1 = g.L1;
-    a.iv = g.iv;
+    a.iv0 = g.iv;
+    a.iv1 = g.iv1;
+    a.st2 = g.st2;
     a.ie = g.ie;
-    a.chunk_item = g.chunk;
+    a.ir = g.ir;
+    a.cfirst = g.cfirst;
+    a.clast = g.clast;
     a.ctl = g.ctl;
     a.gs = g.gsync;
     void* args[] = {&a};
@@ -1055,7 +1201,9 @@ hipError_t enqueue_iter_sort(const GraphDev& g, int slot, int key_bits, int sort
     a.E = g.nnz;
     a.iv = g.siv;
     a.ie = g.sie;
-    a.chunk_item = g.schunk;
+    a.ir = g.sir;
+    a.cfirst = g.scf;
+    a.clast = g.scl;
     a.off = g.off;
     a.adj = g.adj;
     a.inc = g.inc;

@@ -111,6 +111,17 @@ def test_rmat_skewed(dsg, ctx, scale):
         g.close()
 
 
+def test_rmat_large_slices(dsg, ctx):
+    """R-MAT scale 20 (1M vertices): each of the 256 round-loop blocks owns more than 4096 alive vertices in the
+    first rounds, so the select phase runs several full tiles per block."""
+    o, a = graphgen.rmat(4, 20, 16 << 20)
+    for variant, eps in [("peel", (1, 10)), ("sort", (0, 1))]:
+        log(f"rmat scale=20 variant={variant}")
+        g, ref = run_both(dsg, ctx, o, a, 3, variant, eps)
+        assert_same(g, ref, f"rmat20/{variant}")
+        g.close()
+
+
 def test_chunglu_small(dsg, ctx):
     """Chung-Lu power law (the shape of the 40M-vertex configuration) at n=200k."""
     o, a = graphgen.chunglu(5, 200_000, 2.1, 30.0, 10_000.0)
