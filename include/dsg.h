@@ -156,6 +156,65 @@ dsg_status dsg_set_kernel_timing(dsg_graph* g, int32_t enable);
  * the number of timed launches (0 when timing is off).  Waits for the work. */
 dsg_status dsg_get_kernel_timing(dsg_graph* g, float* total_ms, int32_t* launches);
 
+/* ------------------------------------------------------------------ batches
+ * Many independent graphs peeled in one persistent launch (DSG_PEEL rule).
+ * Each graph's results are bit-identical to running it alone through
+ * dsg_graph_create + dsg_run with the same T and eps.  Blocks of the
+ * persistent kernel take whole graphs from a device work queue, largest
+ * (by nnz) first, and run all of a graph's iterations with block barriers
+ * only. */
+typedef struct dsg_batch dsg_batch;
+
+typedef struct {
+    const int32_t* d_offsets; /* n + 1 entries, device */
+    const int32_t* d_adj;     /* nnz entries, device */
+    int32_t n;                /* >= 1 */
+    int32_t T;                /* iterations each dsg_batch_run appends (>= 0) */
+    int64_t nnz;              /* [0, 2^31) */
+    int32_t eps_num;          /* eps = eps_num / eps_den, eps_num >= 0 */
+    int32_t eps_den;          /* >= 1 */
+} dsg_batch_graph;
+
+/* Workspace bytes for these graphs with t_cap recorded iterations each. */
+dsg_status dsg_batch_workspace_bytes(const dsg_batch_graph* graphs, int32_t count, int32_t t_cap, int64_t* bytes);
+
+/* Bind count >= 1 graphs (host array of descriptors, copied; the device CSR
+ * arrays must stay alive).  Every CSR gets the offsets and range checks of
+ * dsg_graph_create, and with DSG_VALIDATE the full check.  The first bad
+ * graph gives DSG_EINVAL and its index in the message.  Synchronises the
+ * stream. */
+dsg_status dsg_batch_create(dsg_ctx* ctx, const dsg_batch_graph* graphs, int32_t count, int32_t t_cap,
+                            void* d_workspace, int64_t workspace_bytes, int32_t flags, dsg_batch** out);
+
+/* Schedule of the persistent kernel: cfg 0 = 256 threads per block with
+ * 1024-edge sweep chunks, 1 = 512 / 2048, 2 = 1024 / 4096; blocks_per_cu
+ * caps residency (the occupancy limit applies too).  Chosen by the
+ * autotuner; default (0, 4). */
+dsg_status dsg_batch_set_config(dsg_batch* b, int32_t cfg, int32_t blocks_per_cu);
+
+/* One persistent launch: every graph runs its T more iterations (state
+ * carries over as with dsg_run).  DSG_EINVAL if a graph would exceed t_cap,
+ * DSG_EOVERFLOW under the same load bound as dsg_run.  Asynchronous. */
+dsg_status dsg_batch_run(dsg_batch* b);
+
+/* Every graph back to loads 0, best = its input graph, no history. */
+dsg_status dsg_batch_reset(dsg_batch* b);
+
+/* Per-graph results; i in [0, count).  Same meaning as the dsg_get_*
+ * calls of a single graph.  Each waits for the stream. */
+dsg_status dsg_batch_get_best(dsg_batch* b, int32_t i, int64_t* edges, int64_t* verts, int32_t* iter, int32_t* index);
+dsg_status dsg_batch_get_best_mask(dsg_batch* b, int32_t i, uint8_t* h_mask);
+dsg_status dsg_batch_get_loads(dsg_batch* b, int32_t i, int64_t* h_loads);
+dsg_status dsg_batch_get_iter_densities(dsg_batch* b, int32_t i, int64_t* h_edges, int64_t* h_verts, int32_t* h_index,
+                                        int32_t cap, int32_t* count);
+dsg_status dsg_batch_get_iter_digests(dsg_batch* b, int32_t i, uint64_t* h_digest, int32_t* h_rounds, int32_t cap,
+                                      int32_t* count);
+
+/* Device time of the last dsg_batch_run in milliseconds (waits). */
+dsg_status dsg_batch_last_run_ms(dsg_batch* b, float* ms);
+
+dsg_status dsg_batch_destroy(dsg_batch* b);
+
 /* Message for the calling thread's last failed call ("" if none). */
 const char* dsg_last_error(void);
 

@@ -51,8 +51,28 @@ SIGNATURES = [
     ("dsg_last_run_ms", ctypes.c_int, [_P, _P]),
     ("dsg_set_kernel_timing", ctypes.c_int, [_P, _I32]),
     ("dsg_get_kernel_timing", ctypes.c_int, [_P, _P, _P]),
+    ("dsg_batch_workspace_bytes", ctypes.c_int, [_P, _I32, _I32, _P]),
+    ("dsg_batch_create", ctypes.c_int, [_P, _P, _I32, _I32, _P, _I64, _I32, _P]),
+    ("dsg_batch_set_config", ctypes.c_int, [_P, _I32, _I32]),
+    ("dsg_batch_run", ctypes.c_int, [_P]),
+    ("dsg_batch_reset", ctypes.c_int, [_P]),
+    ("dsg_batch_get_best", ctypes.c_int, [_P, _I32, _P, _P, _P, _P]),
+    ("dsg_batch_get_best_mask", ctypes.c_int, [_P, _I32, _P]),
+    ("dsg_batch_get_loads", ctypes.c_int, [_P, _I32, _P]),
+    ("dsg_batch_get_iter_densities", ctypes.c_int, [_P, _I32, _P, _P, _P, _I32, _P]),
+    ("dsg_batch_get_iter_digests", ctypes.c_int, [_P, _I32, _P, _P, _I32, _P]),
+    ("dsg_batch_last_run_ms", ctypes.c_int, [_P, _P]),
+    ("dsg_batch_destroy", ctypes.c_int, [_P]),
     ("dsg_last_error", ctypes.c_char_p, []),
 ]
+
+
+class _BatchGraph(ctypes.Structure):
+    """dsg_batch_graph of include/dsg.h."""
+
+    _fields_ = [("d_offsets", ctypes.c_void_p), ("d_adj", ctypes.c_void_p), ("n", ctypes.c_int32),
+                ("T", ctypes.c_int32), ("nnz", ctypes.c_int64), ("eps_num", ctypes.c_int32),
+                ("eps_den", ctypes.c_int32)]
 
 
 class DsgError(RuntimeError):
@@ -277,3 +297,145 @@ class Graph:
             self.close()
         except Exception:
             pass
+
+
+class Batch:
+    """Many graphs peeled in one persistent launch (PEEL rule).
+
+    ``graphs`` is a list of (offsets, adj) host CSRs.  They are packed into
+    one offsets tensor and one adjacency tensor on the device, and each
+    graph's pointers are slices of those.  ``T`` and ``eps`` may be scalars
+    or per-graph lists.
+    """
+
+    def __init__(self, ctx: Context, graphs, T=20, eps=(1, 10), t_cap: int = 64, validate: bool = True):
+        import torch
+
+        self.ctx = ctx
+        dev = ctx.torch_device
+        count = len(graphs)
+        Ts = list(T) if isinstance(T, list) else [T] * count
+        epss = list(eps) if isinstance(eps, list) else [eps] * count
+        sizes_o = [len(o) for o, _ in graphs]
+        sizes_a = [len(a) for _, a in graphs]
+        self.n = [s - 1 for s in sizes_o]
+        self.nnz = sizes_a
+        off_all = np.concatenate([np.asarray(o, dtype=np.int32) for o, _ in graphs])
+        adj_all = np.concatenate([np.asarray(a, dtype=np.int32) for _, a in graphs] + [np.zeros(1, np.int32)])
+        self.offsets = torch.from_numpy(off_all).to(dev)
+        self.adj = torch.from_numpy(adj_all).to(dev)
+        arr = (_BatchGraph * count)()
+        po, pa = 0, 0
+        base_o, base_a = self.offsets.data_ptr(), self.adj.data_ptr()
+        for g in range(count):
+            num, den = parse_eps(epss[g])
+            arr[g].d_offsets = base_o + 4 * po
+            arr[g].d_adj = base_a + 4 * pa
+            arr[g].n = sizes_o[g] - 1
+            arr[g].T = int(Ts[g])
+            arr[g].nnz = sizes_a[g]
+            arr[g].eps_num = num
+            arr[g].eps_den = den
+            po += sizes_o[g]
+            pa += sizes_a[g]
+        self._desc = arr
+        self.count = count
+        nbytes = ctypes.c_int64()
+        _check(library().dsg_batch_workspace_bytes(ctypes.addressof(arr), count, t_cap, ctypes.addressof(nbytes)))
+        self.workspace = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=dev)
+        aligned = (self.workspace.data_ptr() + 255) // 256 * 256
+        handle = ctypes.c_void_p()
+        _check(library().dsg_batch_create(ctx.handle, ctypes.addressof(arr), count, t_cap, ctypes.c_void_p(aligned),
+                                          nbytes.value, VALIDATE if validate else 0, ctypes.addressof(handle)))
+        self._h = handle
+
+    def set_config(self, cfg: int, blocks_per_cu: int):
+        _check(library().dsg_batch_set_config(self._h, cfg, blocks_per_cu))
+        return self
+
+    def run(self):
+        _check(library().dsg_batch_run(self._h))
+        return self
+
+    def reset(self):
+        _check(library().dsg_batch_reset(self._h))
+        return self
+
+    def last_run_ms(self) -> float:
+        ms = ctypes.c_float()
+        _check(library().dsg_batch_last_run_ms(self._h, ctypes.addressof(ms)))
+        return ms.value
+
+    def best(self, i: int):
+        e, v = ctypes.c_int64(), ctypes.c_int64()
+        it, idx = ctypes.c_int32(), ctypes.c_int32()
+        _check(library().dsg_batch_get_best(self._h, i, ctypes.addressof(e), ctypes.addressof(v),
+                                            ctypes.addressof(it), ctypes.addressof(idx)))
+        return e.value, v.value, it.value, idx.value
+
+    def best_mask(self, i: int) -> np.ndarray:
+        out = np.zeros(self.n[i], dtype=np.uint8)
+        _check(library().dsg_batch_get_best_mask(self._h, i, out.ctypes.data))
+        return out.astype(bool)
+
+    def loads(self, i: int) -> np.ndarray:
+        out = np.zeros(self.n[i], dtype=np.int64)
+        _check(library().dsg_batch_get_loads(self._h, i, out.ctypes.data))
+        return out
+
+    def iter_densities(self, i: int):
+        cnt = ctypes.c_int32()
+        _check(library().dsg_batch_get_iter_densities(self._h, i, None, None, None, 0, ctypes.addressof(cnt)))
+        k = cnt.value
+        e = np.zeros(max(k, 1), dtype=np.int64)
+        v = np.zeros(max(k, 1), dtype=np.int64)
+        ix = np.zeros(max(k, 1), dtype=np.int32)
+        _check(library().dsg_batch_get_iter_densities(self._h, i, e.ctypes.data, v.ctypes.data, ix.ctypes.data, k,
+                                                      ctypes.addressof(cnt)))
+        return [(int(e[t]), int(v[t]), int(ix[t])) for t in range(k)]
+
+    def digests(self, i: int):
+        cnt = ctypes.c_int32()
+        _check(library().dsg_batch_get_iter_digests(self._h, i, None, None, 0, ctypes.addressof(cnt)))
+        k = cnt.value
+        d = np.zeros(max(k, 1), dtype=np.uint64)
+        r = np.zeros(max(k, 1), dtype=np.int32)
+        _check(library().dsg_batch_get_iter_digests(self._h, i, d.ctypes.data, r.ctypes.data, k,
+                                                    ctypes.addressof(cnt)))
+        return [int(x) for x in d[:k]], [int(x) for x in r[:k]]
+
+    def view(self, i: int) -> "BatchGraphView":
+        return BatchGraphView(self, i)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            library().dsg_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class BatchGraphView:
+    """Graph i of a Batch, with the result accessors of Graph."""
+
+    def __init__(self, batch: Batch, i: int):
+        self.batch, self.i = batch, i
+
+    def loads(self):
+        return self.batch.loads(self.i)
+
+    def best(self):
+        return self.batch.best(self.i)
+
+    def best_mask(self):
+        return self.batch.best_mask(self.i)
+
+    def iter_densities(self):
+        return self.batch.iter_densities(self.i)
+
+    def digests(self):
+        return self.batch.digests(self.i)

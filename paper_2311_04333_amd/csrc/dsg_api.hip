@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <algorithm>
 #include <new>
 #include <string>
 #include <vector>
@@ -41,6 +42,24 @@ struct dsg_graph {
     bool ktime;                    // per-launch timing of the dominant kernel
     std::vector<hipEvent_t> kev;   // 2 events per timed launch
     int klaunches;                 // timed launches of the last dsg_run
+};
+
+struct dsg_batch {
+    dsg_ctx* ctx;
+    int count;
+    int t_cap;
+    std::vector<dsg::BatchDesc> hdesc;  // host copy of the descriptors
+    std::vector<int> max_deg;
+    std::vector<int> iters;             // iterations done per graph (host mirror)
+    dsg::BatchDesc* ddesc;
+    int* dorder;
+    unsigned int* dqueue;
+    int* derr;
+    dsg::Ctl* dctl;                     // scratch control block for the CSR checks
+    int cfg;
+    int blocks_per_cu;
+    hipEvent_t ev0, ev1;
+    bool timed;
 };
 
 namespace {
@@ -475,6 +494,323 @@ dsg_status dsg_graph_destroy(dsg_graph* g) {
     (void)hipEventDestroy(g->ev0);
     (void)hipEventDestroy(g->ev1);
     delete g;
+    return DSG_OK;
+}
+
+
+}  // extern "C"
+
+namespace {
+
+long long al256(long long x) { return (x + 255) / 256 * 256; }
+
+// Lays out the batch workspace: shared control data first, then each
+// graph's arrays.  With base != nullptr the descriptors get real pointers.
+long long carve_batch(const dsg_batch_graph* gr, int count, int t_cap, char* base, std::vector<dsg::BatchDesc>* out) {
+    long long at = 0;
+    const long long o_desc = at;
+    at += al256(sizeof(dsg::BatchDesc) * (long long)count);
+    const long long o_order = at;
+    at += al256(4LL * count);
+    const long long o_q = at;
+    at += 256;
+    const long long o_err = at;
+    at += 256;
+    const long long o_ctl = at;
+    at += al256(sizeof(dsg::Ctl));
+    if (out) out->resize(count);
+    for (int g = 0; g < count; g++) {
+        const long long n = gr[g].n, nch = gr[g].nnz / dsg::BATCH_MIN_CH + 2;
+        dsg::BatchDesc d{};
+        auto take = [&](long long bytes) {
+            char* p = base ? base + at : nullptr;
+            at += al256(bytes);
+            return p;
+        };
+        d.load = (int*)take(4 * n);
+        d.prio = (int*)take(4 * n);
+        d.rnd = (int*)take(4 * n);
+        d.inc = (int*)take(4 * n);
+        d.pos = (int*)take(4 * n);
+        d.L0 = (int*)take(4 * n);
+        d.L1 = (int*)take(4 * n);
+        d.iv = (int*)take(4 * n);
+        d.ie = (int*)take(4 * n);
+        d.ir = (int*)take(4 * n);
+        d.A = (int*)take(4 * n);
+        d.best_pos = (int*)take(4 * n);
+        d.cfirst = (int*)take(4 * nch);
+        d.clast = (int*)take(4 * nch);
+        d.hist_e = (long long*)take(8LL * t_cap);
+        d.hist_v = (long long*)take(8LL * t_cap);
+        d.hist_i = (int*)take(4LL * t_cap);
+        d.rounds = (int*)take(4LL * t_cap);
+        d.digest = (unsigned long long*)take(8LL * t_cap);
+        d.best = (long long*)take(32);
+        d.state = (int*)take(32);
+        d.n = gr[g].n;
+        d.T = gr[g].T;
+        d.eps_num = gr[g].eps_num;
+        d.eps_den = gr[g].eps_den;
+        d.nnz = gr[g].nnz;
+        d.off = gr[g].d_offsets;
+        d.adj = gr[g].d_adj;
+        d.t_cap = t_cap;
+        if (out) (*out)[g] = d;
+    }
+    (void)o_desc;
+    (void)o_order;
+    (void)o_q;
+    (void)o_err;
+    (void)o_ctl;
+    return at;
+}
+
+dsg_status batch_index(dsg_batch* b, int i) {
+    if (!b) return fail(DSG_EINVAL, "batch is NULL");
+    if (i < 0 || i >= b->count) return fail(DSG_EINVAL, "graph index out of range");
+    return DSG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+dsg_status dsg_batch_workspace_bytes(const dsg_batch_graph* graphs, int32_t count, int32_t t_cap, int64_t* bytes) {
+    if (!graphs || !bytes || count < 1) return fail(DSG_EINVAL, "need graphs, count >= 1 and bytes");
+    if (t_cap < 1) return fail(DSG_EINVAL, "t_cap must be >= 1");
+    for (int g = 0; g < count; g++)
+        if (graphs[g].n < 1 || graphs[g].nnz < 0 || graphs[g].nnz >= (1LL << 31))
+            return fail(DSG_EINVAL, "graph " + std::to_string(g) + ": bad n or nnz");
+    *bytes = carve_batch(graphs, count, t_cap, nullptr, nullptr);
+    return DSG_OK;
+}
+
+dsg_status dsg_batch_create(dsg_ctx* ctx, const dsg_batch_graph* graphs, int32_t count, int32_t t_cap,
+                            void* d_workspace, int64_t workspace_bytes, int32_t flags, dsg_batch** out) {
+    if (!ctx || !graphs || !out || !d_workspace || count < 1) return fail(DSG_EINVAL, "NULL argument or count < 1");
+    *out = nullptr;
+    if (t_cap < 1) return fail(DSG_EINVAL, "t_cap must be >= 1");
+    if (reinterpret_cast<uintptr_t>(d_workspace) % 256 != 0) return fail(DSG_EINVAL, "workspace not 256-byte aligned");
+    for (int g = 0; g < count; g++) {
+        const dsg_batch_graph& x = graphs[g];
+        if (x.n < 1 || x.nnz < 0 || x.nnz >= (1LL << 31) || !x.d_offsets || (x.nnz > 0 && !x.d_adj))
+            return fail(DSG_EINVAL, "graph " + std::to_string(g) + ": bad n, nnz or pointers");
+        if (x.T < 0 || x.eps_num < 0 || x.eps_den < 1)
+            return fail(DSG_EINVAL, "graph " + std::to_string(g) + ": bad T or eps");
+        if (x.n >= dsg::PEEL_MAX_N) return fail(DSG_EINVAL, "graph " + std::to_string(g) + ": n too large");
+    }
+    const long long need = carve_batch(graphs, count, t_cap, nullptr, nullptr);
+    if (workspace_bytes < need) return fail(DSG_ENOMEM, "workspace smaller than dsg_batch_workspace_bytes()");
+    DSG_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    dsg_batch* b = new (std::nothrow) dsg_batch();
+    if (!b) return fail(DSG_ENOMEM, "host allocation failed");
+    b->ctx = ctx;
+    b->count = count;
+    b->t_cap = t_cap;
+    b->cfg = 0;
+    b->blocks_per_cu = 4;
+    char* base = static_cast<char*>(d_workspace);
+    carve_batch(graphs, count, t_cap, base, &b->hdesc);
+    b->ddesc = reinterpret_cast<dsg::BatchDesc*>(base);
+    long long at = al256(sizeof(dsg::BatchDesc) * (long long)count);
+    b->dorder = reinterpret_cast<int*>(base + at);
+    at += al256(4LL * count);
+    b->dqueue = reinterpret_cast<unsigned int*>(base + at);
+    at += 256;
+    b->derr = reinterpret_cast<int*>(base + at);
+    at += 256;
+    b->dctl = reinterpret_cast<dsg::Ctl*>(base + at);
+    hipStream_t s = ctx->stream;
+    auto bail = [&](dsg_status st) {
+        delete b;
+        return st;
+    };
+    // per-graph CSR checks, reusing the single-graph check kernels
+    b->max_deg.assign(count, 0);
+    b->iters.assign(count, 0);
+    for (int g = 0; g < count; g++) {
+        GraphDev gd{};
+        gd.n = graphs[g].n;
+        gd.nnz = graphs[g].nnz;
+        gd.off = graphs[g].d_offsets;
+        gd.adj = graphs[g].d_adj;
+        gd.ctl = b->dctl;
+        hipError_t e;
+        if ((e = dsg::launch_zero_ctl(gd, s)) != hipSuccess) return bail(hip_fail(e, "zero ctl"));
+        if ((e = dsg::launch_check_offsets(gd, s)) != hipSuccess) return bail(hip_fail(e, "check offsets"));
+        dsg::Ctl c;
+        if ((e = hipMemcpyAsync(&c, b->dctl, sizeof c, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+            (e = hipStreamSynchronize(s)) != hipSuccess)
+            return bail(hip_fail(e, "read checks"));
+        if (c.err_count)
+            return bail(fail(DSG_EINVAL, "graph " + std::to_string(g) + ": invalid CSR offsets"));
+        if ((e = dsg::launch_check_range(gd, s)) != hipSuccess) return bail(hip_fail(e, "check range"));
+        if ((flags & DSG_VALIDATE) && (e = dsg::launch_check_rows(gd, s)) != hipSuccess)
+            return bail(hip_fail(e, "check rows"));
+        if ((e = hipMemcpyAsync(&c, b->dctl, sizeof c, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+            (e = hipStreamSynchronize(s)) != hipSuccess)
+            return bail(hip_fail(e, "read checks"));
+        if (c.err_count)
+            return bail(fail(DSG_EINVAL, "graph " + std::to_string(g) + ": invalid CSR (" + err_name(c.err_code) + ")"));
+        b->max_deg[g] = c.max_deg;
+    }
+    // largest first (longest-processing-time order), ties by index
+    std::vector<int> order(count);
+    for (int g = 0; g < count; g++) order[g] = g;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return graphs[x].nnz > graphs[y].nnz; });
+    hipError_t e;
+    if ((e = hipMemcpyAsync(b->ddesc, b->hdesc.data(), sizeof(dsg::BatchDesc) * count, hipMemcpyHostToDevice, s)) !=
+            hipSuccess ||
+        (e = hipMemcpyAsync(b->dorder, order.data(), 4LL * count, hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return bail(hip_fail(e, "upload descriptors"));
+    if ((e = dsg::launch_batch_reset(b->ddesc, count, s)) != hipSuccess) return bail(hip_fail(e, "batch reset"));
+    if ((e = dsg::launch_fill(b->derr, 0, 1, s)) != hipSuccess) return bail(hip_fail(e, "clear error flag"));
+    if ((e = hipEventCreate(&b->ev0)) != hipSuccess) return bail(hip_fail(e, "hipEventCreate"));
+    if ((e = hipEventCreate(&b->ev1)) != hipSuccess) {
+        (void)hipEventDestroy(b->ev0);
+        return bail(hip_fail(e, "hipEventCreate"));
+    }
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) {
+        (void)hipEventDestroy(b->ev0);
+        (void)hipEventDestroy(b->ev1);
+        return bail(hip_fail(e, "hipStreamSynchronize"));
+    }
+    *out = b;
+    return DSG_OK;
+}
+
+dsg_status dsg_batch_set_config(dsg_batch* b, int32_t cfg, int32_t blocks_per_cu) {
+    if (!b) return fail(DSG_EINVAL, "batch is NULL");
+    if (cfg < 0 || cfg > 2 || blocks_per_cu < 1) return fail(DSG_EINVAL, "cfg must be 0..2 and blocks_per_cu >= 1");
+    b->cfg = cfg;
+    b->blocks_per_cu = blocks_per_cu;
+    return DSG_OK;
+}
+
+dsg_status dsg_batch_run(dsg_batch* b) {
+    if (!b) return fail(DSG_EINVAL, "batch is NULL");
+    for (int g = 0; g < b->count; g++) {
+        const dsg::BatchDesc& d = b->hdesc[g];
+        if (b->iters[g] + d.T > b->t_cap)
+            return fail(DSG_EINVAL, "graph " + std::to_string(g) + ": T exceeds the history capacity t_cap");
+        if (((long long)b->iters[g] + d.T + 1) * (long long)b->max_deg[g] >= (1LL << 31))
+            return fail(DSG_EOVERFLOW, "graph " + std::to_string(g) + ": loads could exceed 31 bits");
+    }
+    DSG_HIP(hipSetDevice(b->ctx->device), "hipSetDevice");
+    hipStream_t s = b->ctx->stream;
+    DSG_HIP(hipEventRecord(b->ev0, s), "hipEventRecord");
+    hipError_t e = dsg::launch_batch(b->ddesc, b->dorder, b->count, b->dqueue, b->derr, b->cfg, b->blocks_per_cu,
+                                     b->ctx->num_cu, s);
+    if (e != hipSuccess) return hip_fail(e, "batch launch");
+    DSG_HIP(hipEventRecord(b->ev1, s), "hipEventRecord");
+    b->timed = true;
+    for (int g = 0; g < b->count; g++) b->iters[g] += b->hdesc[g].T;
+    return DSG_OK;
+}
+
+dsg_status dsg_batch_reset(dsg_batch* b) {
+    if (!b) return fail(DSG_EINVAL, "batch is NULL");
+    hipError_t e = dsg::launch_batch_reset(b->ddesc, b->count, b->ctx->stream);
+    if (e != hipSuccess) return hip_fail(e, "batch reset");
+    for (int g = 0; g < b->count; g++) b->iters[g] = 0;
+    b->timed = false;
+    return DSG_OK;
+}
+
+dsg_status dsg_batch_last_run_ms(dsg_batch* b, float* ms) {
+    if (!b || !ms) return fail(DSG_EINVAL, "NULL argument");
+    if (!b->timed) return fail(DSG_ESTATE, "no run recorded");
+    DSG_HIP(hipEventSynchronize(b->ev1), "hipEventSynchronize");
+    DSG_HIP(hipEventElapsedTime(ms, b->ev0, b->ev1), "hipEventElapsedTime");
+    int err = 0;
+    DSG_HIP(hipMemcpy(&err, b->derr, sizeof err, hipMemcpyDeviceToHost), "hipMemcpy(err)");
+    if (err) return fail(DSG_EDEVICE, "a batch kernel consistency check failed");
+    return DSG_OK;
+}
+
+dsg_status dsg_batch_get_best(dsg_batch* b, int32_t i, int64_t* edges, int64_t* verts, int32_t* iter, int32_t* index) {
+    dsg_status st = batch_index(b, i);
+    if (st != DSG_OK) return st;
+    DSG_HIP(hipStreamSynchronize(b->ctx->stream), "hipStreamSynchronize");
+    long long bs[4];
+    DSG_HIP(hipMemcpy(bs, b->hdesc[i].best, sizeof bs, hipMemcpyDeviceToHost), "hipMemcpy(best)");
+    if (edges) *edges = bs[0];
+    if (verts) *verts = bs[1];
+    if (iter) *iter = (int32_t)bs[2];
+    if (index) *index = (int32_t)bs[3];
+    return DSG_OK;
+}
+
+dsg_status dsg_batch_get_best_mask(dsg_batch* b, int32_t i, uint8_t* h_mask) {
+    dsg_status st = batch_index(b, i);
+    if (st != DSG_OK) return st;
+    if (!h_mask) return fail(DSG_EINVAL, "mask is NULL");
+    DSG_HIP(hipStreamSynchronize(b->ctx->stream), "hipStreamSynchronize");
+    const dsg::BatchDesc& d = b->hdesc[i];
+    long long bs[4];
+    DSG_HIP(hipMemcpy(bs, d.best, sizeof bs, hipMemcpyDeviceToHost), "hipMemcpy(best)");
+    if (bs[2] == 0) {
+        memset(h_mask, 1, (size_t)d.n);
+        return DSG_OK;
+    }
+    std::vector<int32_t> pos((size_t)d.n);
+    DSG_HIP(hipMemcpy(pos.data(), d.best_pos, 4 * (size_t)d.n, hipMemcpyDeviceToHost), "hipMemcpy(best pos)");
+    for (int v = 0; v < d.n; v++) h_mask[v] = pos[(size_t)v] >= bs[3] ? 1 : 0;
+    return DSG_OK;
+}
+
+dsg_status dsg_batch_get_loads(dsg_batch* b, int32_t i, int64_t* h_loads) {
+    dsg_status st = batch_index(b, i);
+    if (st != DSG_OK) return st;
+    if (!h_loads) return fail(DSG_EINVAL, "loads is NULL");
+    DSG_HIP(hipStreamSynchronize(b->ctx->stream), "hipStreamSynchronize");
+    const dsg::BatchDesc& d = b->hdesc[i];
+    std::vector<int32_t> tmp((size_t)d.n);
+    DSG_HIP(hipMemcpy(tmp.data(), d.load, 4 * (size_t)d.n, hipMemcpyDeviceToHost), "hipMemcpy(loads)");
+    for (int v = 0; v < d.n; v++) h_loads[v] = tmp[(size_t)v];
+    return DSG_OK;
+}
+
+dsg_status dsg_batch_get_iter_densities(dsg_batch* b, int32_t i, int64_t* h_edges, int64_t* h_verts, int32_t* h_index,
+                                        int32_t cap, int32_t* count) {
+    dsg_status st = batch_index(b, i);
+    if (st != DSG_OK) return st;
+    DSG_HIP(hipStreamSynchronize(b->ctx->stream), "hipStreamSynchronize");
+    const dsg::BatchDesc& d = b->hdesc[i];
+    const int rec = b->iters[i];
+    const int k = cap < rec ? cap : rec;
+    if (k > 0) {
+        if (h_edges) DSG_HIP(hipMemcpy(h_edges, d.hist_e, 8 * (size_t)k, hipMemcpyDeviceToHost), "hipMemcpy(hist)");
+        if (h_verts) DSG_HIP(hipMemcpy(h_verts, d.hist_v, 8 * (size_t)k, hipMemcpyDeviceToHost), "hipMemcpy(hist)");
+        if (h_index) DSG_HIP(hipMemcpy(h_index, d.hist_i, 4 * (size_t)k, hipMemcpyDeviceToHost), "hipMemcpy(hist)");
+    }
+    if (count) *count = rec;
+    return DSG_OK;
+}
+
+dsg_status dsg_batch_get_iter_digests(dsg_batch* b, int32_t i, uint64_t* h_digest, int32_t* h_rounds, int32_t cap,
+                                      int32_t* count) {
+    dsg_status st = batch_index(b, i);
+    if (st != DSG_OK) return st;
+    DSG_HIP(hipStreamSynchronize(b->ctx->stream), "hipStreamSynchronize");
+    const dsg::BatchDesc& d = b->hdesc[i];
+    const int rec = b->iters[i];
+    const int k = cap < rec ? cap : rec;
+    if (k > 0) {
+        if (h_digest) DSG_HIP(hipMemcpy(h_digest, d.digest, 8 * (size_t)k, hipMemcpyDeviceToHost), "hipMemcpy(digest)");
+        if (h_rounds) DSG_HIP(hipMemcpy(h_rounds, d.rounds, 4 * (size_t)k, hipMemcpyDeviceToHost), "hipMemcpy(rounds)");
+    }
+    if (count) *count = rec;
+    return DSG_OK;
+}
+
+dsg_status dsg_batch_destroy(dsg_batch* b) {
+    if (!b) return DSG_OK;
+    (void)hipEventDestroy(b->ev0);
+    (void)hipEventDestroy(b->ev1);
+    delete b;
     return DSG_OK;
 }
 

@@ -121,6 +121,49 @@ hipError_t enqueue_iter_sort(const GraphDev& g, int slot, int key_bits, int sort
                              hipEvent_t ev_b);
 hipError_t enqueue_iter_seq(const GraphDev& g, int slot, hipStream_t s, hipEvent_t ev_a, hipEvent_t ev_b);
 
+// One graph of a batch: its CSR and every per-graph array, carved from the
+// batch workspace by the host.  state[4] = history slots used, state[5] =
+// iterations done before the history was last cleared (always 0 here).
+struct BatchDesc {
+    int n;
+    int T;
+    int eps_num;
+    int eps_den;
+    long long nnz;
+    const int* off;
+    const int* adj;
+    int* load;
+    int* prio;
+    int* rnd;
+    int* inc;
+    int* pos;
+    int* L0;
+    int* L1;
+    int* iv;
+    int* ie;
+    int* ir;
+    int* A;
+    int* best_pos;
+    int* cfirst;
+    int* clast;
+    long long* hist_e;
+    long long* hist_v;
+    int* hist_i;
+    int* rounds;
+    unsigned long long* digest;
+    long long* best;  // edges, vertices, iteration, index
+    int* state;       // [4] history slots used, [5] reserved
+    int t_cap;
+    int pad;
+};
+
+// cfg: 0 = 256 threads / 1024-edge chunks, 1 = 512 / 2048, 2 = 1024 / 4096
+hipError_t launch_batch(const BatchDesc* descs, const int* order, int count, unsigned int* queue, int* err, int cfg,
+                        int blocks_per_cu, int num_cu, hipStream_t s);
+hipError_t launch_batch_reset(BatchDesc* descs, int count, hipStream_t s);
+hipError_t launch_fill(int* p, int v, long long cnt, hipStream_t s);
+constexpr int BATCH_MIN_CH = 1024;
+
 int peel_blocks_per_cu();
 int ctl_bytes();
 

@@ -1047,6 +1047,288 @@ __global__ __launch_bounds__(256) void k_finalize(int n, int* __restrict__ load,
     if (threadIdx.x == 0) atomicAdd(digest_slot, h);
 }
 
+// =============================================================== BATCH
+// Many independent graphs in one persistent launch.  Each block takes whole
+// graphs from a work queue (largest first) and runs all of a graph's PEEL
+// iterations with block barriers only.  The grid-wide round loop is for one
+// large graph.  The per-round rule, same-round edge ownership and
+// Algorithm 3 bookkeeping are the same as in the grid-wide path.  Because
+// one block owns a graph, the alive list can be compacted in id order, so
+// each round's frontier comes out in ascending id and positions are assigned
+// directly: no sort by round is needed.
+template <int SLOTS>
+struct DecTableT {
+    int key[SLOTS];
+    int cnt[SLOTS];
+};
+
+template <int CH>
+struct BatchLds {
+    SweepLds<CH> sw;
+    DecTableT<2 * CH> dec;
+};
+
+template <int BLK, int SLOTS>
+struct BatchPeelOp {
+    const int* rnd;
+    int* prio;
+    int r;
+    unsigned int lmin;
+    int* err;
+    DecTableT<SLOTS>* dec;
+    __device__ void flag_error() { atomicAdd(err, 1); }
+    __device__ __forceinline__ void stage_item(int, int) {}
+    __device__ __forceinline__ int gather(int u) const { return rnd[u]; }
+    __device__ __forceinline__ bool edge(int v, int u, int ru, int) {
+        if (ru < 0) {
+            unsigned int h = ((unsigned int)u * 0x9E3779B1u) >> (32 - __builtin_ctz(SLOTS));
+#pragma unroll 1
+            for (int probe = 0; probe < 64; probe++) {
+                const int k = atomicCAS(&dec->key[h], DEC_EMPTY, u);
+                if (k == DEC_EMPTY || k == u) {
+                    atomicAdd(&dec->cnt[h], 1);
+                    return true;
+                }
+                h = (h + 1) & (SLOTS - 1);
+            }
+            const int old = atomicSub(&prio[u], 1);
+            lmin = min(lmin, (unsigned int)(old - 1));
+            return true;
+        }
+        return ru == r && u > v;
+    }
+    __device__ __forceinline__ void flush_chunk() {
+        constexpr int PER = SLOTS / BLK;
+        lds_barrier();
+        int key[PER], c[PER], old[PER];
+#pragma unroll
+        for (int k = 0; k < PER; k++) {
+            key[k] = dec->key[threadIdx.x + k * BLK];
+            c[k] = dec->cnt[threadIdx.x + k * BLK];
+        }
+#pragma unroll
+        for (int k = 0; k < PER; k++)
+            if (key[k] != DEC_EMPTY) old[k] = atomicSub(&prio[key[k]], c[k]);
+#pragma unroll
+        for (int k = 0; k < PER; k++) {
+            if (key[k] != DEC_EMPTY) {
+                lmin = min(lmin, (unsigned int)(old[k] - c[k]));
+                dec->key[threadIdx.x + k * BLK] = DEC_EMPTY;
+                dec->cnt[threadIdx.x + k * BLK] = 0;
+            }
+        }
+    }
+};
+
+// One PEEL iteration of one graph by one block.
+template <int BLK, int CH>
+__device__ void batch_iteration(const BatchDesc& d, BatchLds<CH>& lds, int* err, const int slot) {
+    constexpr int U = 4;
+    constexpr int TILE = BLK * U;
+    __shared__ unsigned long long sh64[BLK / WAVE];
+    __shared__ unsigned int sh32[BLK / WAVE];
+    __shared__ Cand shc[BLK / WAVE];
+    __shared__ int s_improved;
+    const int n = d.n;
+    const long long q = d.eps_den, p = d.eps_num;
+    // ---- init
+    unsigned int lmin = 0xFFFFFFFFu;
+    for (int v = threadIdx.x; v < n; v += BLK) {
+        const int pv = d.load[v] + (d.off[v + 1] - d.off[v]);
+        d.prio[v] = pv;
+        d.rnd[v] = -1;
+        d.inc[v] = 0;
+        lmin = min(lmin, (unsigned int)pv);
+    }
+    unsigned int mn = block_min<BLK>(lmin, sh32);
+    int Lc = n, next = 0, r = 0;
+    // ---- rounds
+    while (Lc > 0) {
+        const int* __restrict__ Lin = (r & 1) ? d.L1 : d.L0;
+        int* __restrict__ Lout = (r & 1) ? d.L0 : d.L1;
+        const long long thr = ((q + p) * (long long)mn) / q;
+        unsigned int smin = 0xFFFFFFFFu;
+        int nfr = 0, nitem = 0, nsurv = 0;
+        long long nedge = 0;
+        for (int base = 0; base < Lc; base += TILE) {
+            int u[U], pu[U], o0[U], o1[U];
+#pragma unroll
+            for (int k = 0; k < U; k++) {
+                const int idx = base + (int)threadIdx.x * U + k;
+                u[k] = idx < Lc ? ((r == 0) ? idx : Lin[idx]) : -1;
+            }
+#pragma unroll
+            for (int k = 0; k < U; k++) pu[k] = u[k] >= 0 ? d.prio[u[k]] : 0;
+#pragma unroll
+            for (int k = 0; k < U; k++) {
+                const bool fr = u[k] >= 0 && (long long)pu[k] <= thr;
+                o0[k] = fr ? d.off[u[k]] : 0;
+                o1[k] = fr ? d.off[u[k] + 1] : 0;
+            }
+            // counts [frontier:16][items:16][survivors:16] and edges
+            unsigned long long cnt = 0, edg = 0;
+#pragma unroll
+            for (int k = 0; k < U; k++) {
+                if (u[k] < 0) continue;
+                if ((long long)pu[k] <= thr) {
+                    cnt += 1ull;
+                    if (o1[k] > o0[k]) {
+                        cnt += 1ull << 16;
+                        edg += (unsigned long long)(o1[k] - o0[k]);
+                    }
+                } else {
+                    cnt += 1ull << 32;
+                }
+            }
+            unsigned long long ctot, etot;
+            unsigned long long cex = block_excl_scan<BLK>(cnt, &ctot, sh64);
+            unsigned long long eex = block_excl_scan<BLK>(edg, &etot, sh64);
+            int f = nfr + (int)(cex & 0xFFFF);
+            int it = nitem + (int)((cex >> 16) & 0xFFFF);
+            int sv = nsurv + (int)((cex >> 32) & 0xFFFF);
+            long long ed = nedge + (long long)eex;
+#pragma unroll
+            for (int k = 0; k < U; k++) {
+                if (u[k] < 0) continue;
+                if ((long long)pu[k] <= thr) {
+                    d.pos[u[k]] = next + f++;
+                    d.rnd[u[k]] = r;
+                    const int dg = o1[k] - o0[k];
+                    if (dg > 0) {
+                        d.iv[it] = u[k];
+                        d.ie[it] = (int)ed;
+                        d.ir[it] = o0[k] - (int)ed;
+                        mark_chunks<CH>(ed, ed + dg, it, d.cfirst, d.clast);
+                        it++;
+                        ed += dg;
+                    }
+                } else {
+                    Lout[sv++] = u[k];
+                    smin = min(smin, (unsigned int)pu[k]);
+                }
+            }
+            nfr += (int)(ctot & 0xFFFF);
+            nitem += (int)((ctot >> 16) & 0xFFFF);
+            nsurv += (int)((ctot >> 32) & 0xFFFF);
+            nedge += (long long)etot;
+        }
+        __syncthreads();
+        BatchPeelOp<BLK, 2 * CH> op{d.rnd, d.prio, r, smin, err, &lds.dec};
+        sweep_chunks<BLK, CH>(nitem, nedge, d.iv, d.ie, d.ir, d.cfirst, d.clast, d.adj, d.inc, op, lds.sw, 0, 1,
+                              nullptr, nullptr);
+        __syncthreads();
+        mn = block_min<BLK>(op.lmin, sh32);
+        if (nsurv >= Lc) {  // every round peels the minimum vertex
+            if (threadIdx.x == 0) atomicAdd(err, 1);
+            break;
+        }
+        next += nfr;
+        Lc = nsurv;
+        r++;
+    }
+    // ---- Algorithm 3: A[pos] = charge, densest suffix (ties to the smallest index)
+    for (int v = threadIdx.x; v < n; v += BLK) d.A[d.pos[v]] = d.inc[v];
+    __syncthreads();
+    long long carry = 0;
+    Cand best{-1, 1, 0x7FFFFFFFFFFFFFFFll};
+    for (int t0 = ((n - 1) / TILE) * TILE; t0 >= 0; t0 -= TILE) {
+        const int b0 = t0 + (int)threadIdx.x * U;
+        int x[U];
+        long long mine = 0;
+#pragma unroll
+        for (int k = 0; k < U; k++) {
+            x[k] = b0 + k < n ? d.A[b0 + k] : 0;
+            mine += x[k];
+        }
+        long long tot;
+        const long long ex = block_excl_scan<BLK>(mine, &tot, (long long*)sh64);
+        long long run = carry + (tot - ex - mine);
+        Cand c{-1, 1, 0x7FFFFFFFFFFFFFFFll};
+#pragma unroll
+        for (int k = U - 1; k >= 0; k--) {
+            const int i = b0 + k;
+            run += x[k];
+            if (i < n) {
+                Cand cc{run, (long long)(n - i), (long long)i};
+                if (c.e < 0 || cand_better(cc, c)) c = cc;
+            }
+        }
+        c = block_best<BLK>(c, shc);
+        if (c.e >= 0 && (best.e < 0 || cand_better(c, best))) best = c;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) {
+        d.hist_e[slot] = best.e;
+        d.hist_v[slot] = best.v;
+        d.hist_i[slot] = (int)best.i;
+        d.rounds[slot] = r;
+        long long* bs = d.best;
+        const int improved = best.e * bs[1] > bs[0] * best.v;
+        if (improved) {
+            bs[0] = best.e;
+            bs[1] = best.v;
+            bs[2] = slot + 1;
+            bs[3] = best.i;
+        }
+        s_improved = improved;
+    }
+    __syncthreads();
+    const bool improved = s_improved != 0;
+    unsigned long long h = 0;
+    for (int v = threadIdx.x; v < n; v += BLK) {
+        d.load[v] += d.inc[v];
+        h += mix64(((unsigned long long)(unsigned int)v << 32) | (unsigned long long)(unsigned int)d.rnd[v]);
+        if (improved) d.best_pos[v] = d.pos[v];
+    }
+    h = block_sum<BLK>(h, sh64);
+    if (threadIdx.x == 0) {
+        d.digest[slot] = h;
+        d.state[4] = slot + 1;
+    }
+    __syncthreads();
+}
+
+template <int BLK, int CH>
+__global__ __launch_bounds__(BLK) void k_batch_peel(const BatchDesc* __restrict__ descs, const int* __restrict__ order,
+                                                    int count, unsigned int* queue, int* err) {
+    __shared__ BatchLds<CH> lds;
+    __shared__ int s_g;
+    for (int i = threadIdx.x; i < 2 * CH; i += BLK) {
+        lds.dec.key[i] = DEC_EMPTY;
+        lds.dec.cnt[i] = 0;
+    }
+    while (true) {
+        if (threadIdx.x == 0) s_g = (int)atomicAdd(queue, 1u);
+        __syncthreads();
+        const int gi = s_g;
+        __syncthreads();
+        if (gi >= count) break;
+        const BatchDesc d = descs[order[gi]];
+        const int s0 = d.state[4];
+        if (s0 + d.T > d.t_cap) {  // the host checks this; never index past the history
+            if (threadIdx.x == 0) atomicAdd(err, 1);
+            continue;
+        }
+        for (int t = 0; t < d.T; t++) batch_iteration<BLK, CH>(d, lds, err, s0 + t);
+    }
+}
+
+__global__ void k_batch_reset(BatchDesc* descs, int count) {
+    // loads 0, best = the input graph, history empty
+    for (int g = blockIdx.x; g < count; g += gridDim.x) {
+        const BatchDesc d = descs[g];
+        for (int v = threadIdx.x; v < d.n; v += blockDim.x) d.load[v] = 0;
+        if (threadIdx.x == 0) {
+            d.best[0] = d.nnz / 2;
+            d.best[1] = d.n;
+            d.best[2] = 0;
+            d.best[3] = 0;
+            d.state[4] = 0;
+            d.state[5] = 0;
+        }
+    }
+}
+
 // ================================================================= launchers
 namespace {
 inline int grid_for(long long n, int blk, int cap = 4096) {
@@ -1228,6 +1510,43 @@ hipError_t enqueue_iter_seq(const GraphDev& g, int slot, hipStream_t s, hipEvent
     if (e != hipSuccess) return e;
     if (ev_b && (e = hipEventRecord(ev_b, s)) != hipSuccess) return e;
     return enqueue_alg3(g, slot, g.n, s);
+}
+
+
+template <int BLK, int CH>
+static hipError_t launch_batch_cfg(const BatchDesc* descs, const int* order, int count, unsigned int* queue, int* err,
+                                   int blocks_per_cu, int num_cu, hipStream_t s) {
+    int occ = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(k_batch_peel<BLK, CH>),
+                                                                BLK, 0);
+    if (e != hipSuccess) return e;
+    if (occ < 1) occ = 1;
+    int per = blocks_per_cu < occ ? blocks_per_cu : occ;
+    if (per < 1) per = 1;
+    int grid = num_cu * per;
+    if (grid > count) grid = count > 0 ? count : 1;
+    k_batch_peel<BLK, CH><<<grid, BLK, 0, s>>>(descs, order, count, queue, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch(const BatchDesc* descs, const int* order, int count, unsigned int* queue, int* err,
+                        int cfg, int blocks_per_cu, int num_cu, hipStream_t s) {
+    k_fill_i32<<<1, 64, 0, s>>>(reinterpret_cast<int*>(queue), 0, 1);
+    switch (cfg) {
+        case 0: return launch_batch_cfg<256, 1024>(descs, order, count, queue, err, blocks_per_cu, num_cu, s);
+        case 1: return launch_batch_cfg<512, 2048>(descs, order, count, queue, err, blocks_per_cu, num_cu, s);
+        default: return launch_batch_cfg<1024, 4096>(descs, order, count, queue, err, blocks_per_cu, num_cu, s);
+    }
+}
+
+hipError_t launch_fill(int* p, int v, long long cnt, hipStream_t s) {
+    k_fill_i32<<<grid_for(cnt, 256), 256, 0, s>>>(p, v, cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_reset(BatchDesc* descs, int count, hipStream_t s) {
+    k_batch_reset<<<count < 2048 ? (count > 0 ? count : 1) : 2048, 256, 0, s>>>(descs, count);
+    return hipGetLastError();
 }
 
 }  // namespace dsg

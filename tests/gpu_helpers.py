@@ -18,7 +18,7 @@ def sha(arr) -> str:
     return hashlib.sha256(np.ascontiguousarray(arr).tobytes()).hexdigest()
 
 
-def assert_same(g, ref: oracle.State, what: str = ""):
+def assert_same(g, ref: oracle.State, what: str = "", check_order: bool = True):
     """Bit-exact comparison of every output of the GPU graph with the oracle state."""
     loads = g.loads()
     assert np.array_equal(loads, ref.loads), f"{what}: loads differ at {np.flatnonzero(loads != ref.loads)[:10]}"
@@ -30,7 +30,7 @@ def assert_same(g, ref: oracle.State, what: str = ""):
     digests, rounds = g.digests()
     assert rounds == ref.rounds, f"{what}: rounds {rounds} vs {ref.rounds}"
     assert digests == ref.digests, f"{what}: order digests differ"
-    if ref.last_round is not None:
+    if check_order and ref.last_round is not None:
         rnd, pos, nr = g.order()
         assert np.array_equal(rnd, ref.last_round), f"{what}: last-iteration rounds differ"
         assert np.array_equal(pos, ref.last_pos), f"{what}: last-iteration positions differ"
