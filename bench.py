@@ -68,7 +68,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="rmat22", choices=["rmat22", "batch"],
+                    help="rmat22: one R-MAT scale-22 graph (default); batch: the 4096-graph batched mix")
     ap.add_argument("--variant", default="peel", choices=["peel", "sort"])
+    ap.add_argument("--count", type=int, default=4096, help="graphs in the batched mix")
+    ap.add_argument("--plain-sample", type=int, default=256, help="graphs of the mix timed on the plain path")
     ap.add_argument("--T", type=int, default=20)
     ap.add_argument("--scale", type=int, default=22)
     ap.add_argument("--cpu-iters", type=int, default=2, help="oracle iterations timed for cpu_baseline (0 = skip)")
@@ -80,6 +84,9 @@ def main():
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU sharding is a design, not an implementation", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "batch":
+        return bench_batch(args)
 
     import numpy as np
     import torch
@@ -191,6 +198,111 @@ def main():
                      "avg_launch_ms": kern_ms / max(launches, 1), "alg_bytes_per_launch": alg_bytes},
         "cpu_baseline": cpu,
         "check": check,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_batch(args):
+    """The batched workload: --count graphs of the mix (n log-uniform 100..200k, mean degree 4..64; ER, R-MAT,
+    ER + planted block), PEEL eps=1/10, T=20, in one persistent launch.  This is compared with the plain path
+    (one dsg_run per graph, back to back) on a systematic sample of the same graphs."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import numpy as np
+    import torch
+
+    import graphgen
+    import paper_2311_04333_amd as dsg
+    from paper_2311_04333_amd import autotune
+
+    T, eps = args.T, (1, 10)
+    t0 = time.time()
+    workers = min(16, os.cpu_count() or 1)
+    with ThreadPoolExecutor(workers) as ex:
+        graphs = list(ex.map(lambda i: graphgen.mix_graph(1, i), range(args.count)))
+    n_tot = sum(len(o) - 1 for o, _ in graphs)
+    m_tot = sum(len(a) // 2 for _, a in graphs)
+    log(f"generated {args.count} graphs (n={n_tot}, m={m_tot}) in {time.time() - t0:.1f}s with {workers} threads")
+    ctx = dsg.Context(0)
+    cfg, bpc, timings = autotune.tune_batch(ctx, graphs, T=2, eps=eps, log=log)
+    log(f"autotuned schedule: cfg={cfg} blocks/CU={bpc}")
+    t1 = time.time()
+    b = dsg.Batch(ctx, graphs, T=T, eps=eps, t_cap=T, validate=False).set_config(cfg, bpc)
+    torch.cuda.synchronize()
+    log(f"batch resident in HBM in {time.time() - t1:.1f}s")
+    for w in range(args.warmup):
+        b.reset().run()
+        log(f"warmup {w + 1}: {b.last_run_ms():.1f} ms")
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    for _ in range(args.steps):
+        b.reset().run()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - ts
+    kern_ms = b.last_run_ms()
+    graphs_per_s = args.count * args.steps / elapsed
+    ev_per_s = 2.0 * m_tot * T * args.steps / elapsed
+    alg_bytes = sum(16.0 * (len(a) // 2) + 16.0 * (len(o) - 1) for o, a in graphs) * T
+    achieved = alg_bytes / (kern_ms / 1e3) / 1e9
+    log(f"batched: {elapsed / args.steps * 1e3:.1f} ms/step, {graphs_per_s:.1f} graphs/s, {ev_per_s / 1e9:.2f} G edge-visits/s")
+
+    # plain path on a systematic sample: one dsg_run per graph, enqueued back to back
+    step = max(1, args.count // args.plain_sample)
+    idx = list(range(0, args.count, step))[:args.plain_sample]
+    plain = [dsg.Graph(ctx, *graphs[i], t_cap=T, validate=False) for i in idx]
+    for g in plain[:4]:
+        g.reset().run(T, eps, "peel")
+    torch.cuda.synchronize()
+    tp = time.perf_counter()
+    for g in plain:
+        g.reset().run(T, eps, "peel")
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - tp
+    m_samp = sum(len(graphs[i][1]) // 2 for i in idx)
+    plain_gps = len(idx) / plain_s
+    plain_evs = 2.0 * m_samp * T / plain_s
+    # bit-equality of batched and alone results on the sample
+    same = all(np.array_equal(b.loads(i), g.loads()) and b.best(i) == g.best() and b.digests(i) == g.digests()
+               for i, g in zip(idx[:32], plain[:32]))
+    log(f"plain: {len(idx)} graphs in {plain_s:.2f}s = {plain_gps:.1f} graphs/s; batched/plain = "
+        f"{graphs_per_s / plain_gps:.1f}x; alone == batched on {min(32, len(idx))} graphs: {same}")
+
+    cpu = None
+    if args.cpu_iters > 0:
+        import oracle
+
+        cs = idx[:: max(1, len(idx) // 8)][:8]
+        tc = time.perf_counter()
+        for i in cs:
+            oracle.run(*graphs[i], args.cpu_iters, "peel", eps)
+        cpu_s = time.perf_counter() - tc
+        m_c = sum(len(graphs[i][1]) // 2 for i in cs)
+        cpu = {"value": 2.0 * m_c * args.cpu_iters / cpu_s, "unit": "edge-visits/s", "cores": 1, "kind": "oracle",
+               "sample": f"{len(cs)} graphs of the mix x {args.cpu_iters} iterations ({cpu_s:.1f} s); "
+                         f"graphs/s at T={T} extrapolates to {len(cs) * args.cpu_iters / T / cpu_s:.3f}"}
+    line = {
+        "metric": "graphs/s, batched persistent launch (edge-visits/s beside it); batched vs plain",
+        "value": graphs_per_s,
+        "unit": "graphs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.count} mixed graphs (n={n_tot}, m={m_tot}), PEEL eps=1/10, T={T}",
+                   "schedule": {"cfg": cfg, "blocks_per_cu": bpc, "autotune_ms": timings}},
+        "edge_visits_per_s": ev_per_s,
+        "plain": {"graphs_per_s": plain_gps, "edge_visits_per_s": plain_evs, "sample_graphs": len(idx)},
+        "batched_over_plain": graphs_per_s / plain_gps,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_batch_peel",
+                     "avg_launch_ms": kern_ms, "alg_bytes_per_launch": alg_bytes},
+        "cpu_baseline": cpu,
+        "check": {"alone_equals_batched": bool(same)},
     }
     print(json.dumps(line), flush=True)
 
