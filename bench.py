@@ -68,8 +68,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="rmat22", choices=["rmat22", "batch"],
-                    help="rmat22: one R-MAT scale-22 graph (default); batch: the 4096-graph batched mix")
+    ap.add_argument("--workload", default="rmat22", choices=["rmat22", "batch", "serve"],
+                    help="rmat22: one R-MAT scale-22 graph (default); batch: the 4096-graph batched mix; "
+                         "serve: Poisson request stream through the continuous-batching server")
+    ap.add_argument("--rates", default="100,200,500,1000,2000,5000", help="serve: offered request rates (req/s)")
+    ap.add_argument("--requests", type=int, default=1000, help="serve: requests per rate")
     ap.add_argument("--variant", default="peel", choices=["peel", "sort"])
     ap.add_argument("--count", type=int, default=4096, help="graphs in the batched mix")
     ap.add_argument("--plain-sample", type=int, default=256, help="graphs of the mix timed on the plain path")
@@ -87,6 +90,8 @@ def main():
 
     if args.workload == "batch":
         return bench_batch(args)
+    if args.workload == "serve":
+        return bench_serve(args)
 
     import numpy as np
     import torch
@@ -303,6 +308,115 @@ def bench_batch(args):
                      "avg_launch_ms": kern_ms, "alg_bytes_per_launch": alg_bytes},
         "cpu_baseline": cpu,
         "check": {"alone_equals_batched": bool(same)},
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_serve(args):
+    """Serving: Poisson arrivals at each offered rate.  98% of requests draw a graph from the batched mix (a pool of
+    256 resident graphs) and 2% draw an R-MAT scale-20 graph.  T ~ U{5..50} and eps is 1/20 or 1/10 with equal
+    probability.  Requests are admitted under the HBM budget (min(200 GB, 80% of free HBM)).  The output is p50/p99
+    latency (arrival to result fetched on the host) and the sustained graphs/s at each rate.  The plain baseline
+    runs the same request list one at a time through the single-graph path."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import numpy as np
+    import torch
+
+    import graphgen
+    import paper_2311_04333_amd as dsg
+
+    rng = np.random.default_rng(2026)
+    workers = min(16, os.cpu_count() or 1)
+    t0 = time.time()
+    with ThreadPoolExecutor(workers) as ex:
+        mix = list(ex.map(lambda i: graphgen.mix_graph(7, i), range(256)))
+        big = list(ex.map(lambda i: graphgen.rmat(100 + i, 20, 16 << 20), range(4)))
+    log(f"request pool: 256 mix graphs + 4 R-MAT scale-20 graphs in {time.time() - t0:.1f}s")
+    ctx = dsg.Context(0)
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(min(200e9, 0.8 * free))
+    srv = dsg.Server(ctx, budget, ring_size=16384)
+    gids_mix = [srv.register(o, a, validate=False) for o, a in mix]
+    gids_big = [srv.register(o, a, validate=False) for o, a in big]
+    graphs = {g: ga for g, ga in zip(gids_mix + gids_big, mix + big)}
+    srv.start(cfg=1, blocks_per_cu=1, idle_seconds=60, max_seconds=1100)
+    results = []
+    served_sample = {}
+    try:
+        for rate in [float(r) for r in args.rates.split(",")]:
+            N = args.requests
+            arrivals = np.cumsum(rng.exponential(1.0 / rate, N))
+            plan = [((gids_big[rng.integers(4)] if rng.random() < 0.02 else gids_mix[rng.integers(256)]),
+                     int(rng.integers(5, 51)), (1, 20) if rng.random() < 0.5 else (1, 10)) for _ in range(N)]
+            lat = np.zeros(N)
+            ticket_of = {}
+            start = time.perf_counter()
+            i, done_cnt, last_done = 0, 0, 0.0
+            while done_cnt < N:
+                now = time.perf_counter() - start
+                while i < N and arrivals[i] <= now:
+                    t = srv.submit_registered(*plan[i])
+                    if t is None:
+                        break  # pool or ring full: retry once results are released
+                    ticket_of[t] = i
+                    i += 1
+                for t in srv.poll():
+                    j = ticket_of.pop(t)
+                    res = srv.fetch(t)
+                    srv.release(t)
+                    last_done = time.perf_counter() - start
+                    lat[j] = last_done - arrivals[j]
+                    done_cnt += 1
+                    if len(served_sample) < 48 and plan[j] not in served_sample:
+                        served_sample[plan[j]] = res
+                if time.perf_counter() - start > 240:
+                    raise RuntimeError(f"rate {rate}: stream did not drain in 240 s ({done_cnt}/{N} done)")
+            thr = N / last_done
+            rec = {"rate": rate, "requests": N, "graphs_per_s": thr, "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                   "p99_ms": float(np.percentile(lat, 99) * 1e3),
+                   "p99_small_ms": float(np.percentile(lat[[p[0] not in gids_big for p in plan]], 99) * 1e3)}
+            results.append(rec)
+            log(f"rate {rate:6.0f}/s: {thr:8.1f} graphs/s, p50 {rec['p50_ms']:.1f} ms, p99 {rec['p99_ms']:.1f} ms "
+                f"(p99 without the R-MAT-20 requests {rec['p99_small_ms']:.1f} ms)")
+    finally:
+        srv.stop()
+    # plain: the same kind of requests one at a time through the single-graph path
+    plan = list(served_sample.keys())
+    tp = time.perf_counter()
+    same = True
+    for gid, T, eps in plan:
+        o, a = graphs[gid]
+        g = dsg.Graph(ctx, o, a, t_cap=T, validate=False).run(T, eps, "peel")
+        dens = g.iter_densities()
+        res = served_sample[(gid, T, eps)]
+        same = same and g.best() == res["best"] and [(e, v) for e, v, _ in dens] == res["hist"] and \
+            g.digests()[0] == res["digests"]
+        g.close()
+    plain_s = time.perf_counter() - tp
+    plain_gps = len(plan) / plain_s
+    best = max(results, key=lambda r: r["graphs_per_s"])
+    log(f"plain: {len(plan)} requests in {plain_s:.2f}s = {plain_gps:.1f} graphs/s; served/plain = "
+        f"{best['graphs_per_s'] / plain_gps:.1f}x; alone == served: {same}")
+    line = {
+        "metric": "served graphs/s under a Poisson request stream (continuous batching), p50/p99 latency",
+        "value": best["graphs_per_s"],
+        "unit": "graphs/s",
+        "n_gpus": 1,
+        "steps": len(results),
+        "warmup": 0,
+        "ms_per_step": None,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": f"Poisson stream: 98% batched-mix graphs, 2% R-MAT scale 20; T~U{{5..50}}, "
+                               f"eps in {{1/20, 1/10}}; HBM budget {budget / 1e9:.0f} GB"},
+        "rates": results,
+        "plain": {"graphs_per_s": plain_gps, "requests": len(plan)},
+        "served_over_plain": best["graphs_per_s"] / plain_gps,
+        "check": {"alone_equals_served": bool(same)},
     }
     print(json.dumps(line), flush=True)
 

@@ -215,6 +215,69 @@ dsg_status dsg_batch_last_run_ms(dsg_batch* b, float* ms);
 
 dsg_status dsg_batch_destroy(dsg_batch* b);
 
+/* ------------------------------------------------------------------ serving
+ * Continuous batching of a request stream (DSG_PEEL rule).  One persistent
+ * kernel runs on a stream of its own.  Each request (a host CSR plus T and
+ * eps) is admitted if its HBM footprint fits the caller-provided pool and a
+ * ring slot is free; otherwise DSG_EBUSY.  It is copied to the device,
+ * published to a request ring in pinned host memory, and claimed by the
+ * first idle block.  So requests that arrive while others run start as soon
+ * as a block frees up.  Results equal those of the same graph run alone
+ * with dsg_run.  The CSR's offsets and entry range are checked on the host
+ * at submit. */
+typedef struct dsg_server dsg_server;
+
+/* d_pool: caller-owned device memory (256-byte aligned) that the server
+ * sub-allocates (first fit) for admitted requests.  ring_size >= 1 bounds
+ * the requests in flight.  Allocates the pinned ring (host memory) and two
+ * streams (kernel, copies), both at the default priority. */
+dsg_status dsg_server_create(dsg_ctx* ctx, void* d_pool, int64_t pool_bytes, int32_t ring_size, dsg_server** out);
+
+/* Bytes one request (with its CSR copy) occupies in the pool. */
+dsg_status dsg_server_footprint(int32_t n, int64_t nnz, int32_t T, int64_t* bytes);
+
+/* Launch the persistent kernel (cfg 0 = 256 threads / 1024-edge chunks,
+ * 1 = 512 / 2048; blocks_per_cu >= 1).  It exits on dsg_server_stop, after
+ * idle_seconds with nothing to do, or after max_seconds in total. */
+dsg_status dsg_server_start(dsg_server* s, int32_t cfg, int32_t blocks_per_cu, double idle_seconds,
+                            double max_seconds);
+
+/* Admit one request; copies the host CSR (h_offsets[n+1], h_adj[nnz]) to
+ * the pool before returning.  T >= 1, (T + 1) * max_degree < 2^31.
+ * DSG_EBUSY when the pool or the ring is full (retry after releasing
+ * results); DSG_ESTATE if the kernel is not running. */
+dsg_status dsg_server_submit(dsg_server* s, const int32_t* h_offsets, const int32_t* h_adj, int32_t n, int64_t nnz,
+                             int32_t T, int32_t eps_num, int32_t eps_den, uint64_t* ticket);
+
+/* Resident graphs: register a CSR that stays on the device (caller-owned,
+ * alive until dsg_server_destroy), checked like dsg_graph_create (flags:
+ * DSG_VALIDATE).  Only before dsg_server_start.  Requests against it need
+ * no copy and no host-side check, so admission is O(1) host work. */
+dsg_status dsg_server_register(dsg_server* s, const int32_t* d_offsets, const int32_t* d_adj, int32_t n, int64_t nnz,
+                               int32_t flags, int32_t* graph_id);
+
+/* Admit one request against a registered graph (errors as dsg_server_submit). */
+dsg_status dsg_server_submit_registered(dsg_server* s, int32_t graph_id, int32_t T, int32_t eps_num, int32_t eps_den,
+                                        uint64_t* ticket);
+
+/* Tickets whose results are ready (up to cap); each is reported once. */
+dsg_status dsg_server_poll(dsg_server* s, uint64_t* h_tickets, int32_t cap, int32_t* count);
+
+/* Copy a finished request's results: best[4] = (edges, vertices, iteration,
+ * index); per-iteration arrays of length T (any may be NULL); h_loads
+ * (n int64, may be NULL). */
+dsg_status dsg_server_fetch(dsg_server* s, uint64_t ticket, int64_t* best, int64_t* h_edges, int64_t* h_verts,
+                            int32_t* h_index, uint64_t* h_digest, int32_t* h_rounds, int64_t* h_loads);
+
+/* Free a finished request's pool memory and ring slot. */
+dsg_status dsg_server_release(dsg_server* s, uint64_t ticket);
+
+/* Ask the kernel to finish the queue and exit; waits for it. */
+dsg_status dsg_server_stop(dsg_server* s);
+
+/* Stops the kernel if running, frees the pinned ring and streams. */
+dsg_status dsg_server_destroy(dsg_server* s);
+
 /* Message for the calling thread's last failed call ("" if none). */
 const char* dsg_last_error(void);
 

@@ -63,6 +63,17 @@ SIGNATURES = [
     ("dsg_batch_get_iter_digests", ctypes.c_int, [_P, _I32, _P, _P, _I32, _P]),
     ("dsg_batch_last_run_ms", ctypes.c_int, [_P, _P]),
     ("dsg_batch_destroy", ctypes.c_int, [_P]),
+    ("dsg_server_create", ctypes.c_int, [_P, _P, _I64, _I32, _P]),
+    ("dsg_server_footprint", ctypes.c_int, [_I32, _I64, _I32, _P]),
+    ("dsg_server_start", ctypes.c_int, [_P, _I32, _I32, ctypes.c_double, ctypes.c_double]),
+    ("dsg_server_submit", ctypes.c_int, [_P, _P, _P, _I32, _I64, _I32, _I32, _I32, _P]),
+    ("dsg_server_register", ctypes.c_int, [_P, _P, _P, _I32, _I64, _I32, _P]),
+    ("dsg_server_submit_registered", ctypes.c_int, [_P, _I32, _I32, _I32, _I32, _P]),
+    ("dsg_server_poll", ctypes.c_int, [_P, _P, _I32, _P]),
+    ("dsg_server_fetch", ctypes.c_int, [_P, ctypes.c_uint64, _P, _P, _P, _P, _P, _P, _P]),
+    ("dsg_server_release", ctypes.c_int, [_P, ctypes.c_uint64]),
+    ("dsg_server_stop", ctypes.c_int, [_P]),
+    ("dsg_server_destroy", ctypes.c_int, [_P]),
     ("dsg_last_error", ctypes.c_char_p, []),
 ]
 
@@ -439,3 +450,114 @@ class BatchGraphView:
 
     def digests(self):
         return self.batch.digests(self.i)
+
+
+class Server:
+    """Continuous-batching server (persistent kernel + pinned request ring).
+
+    ``pool_bytes`` of device memory (a torch tensor owned here) holds the
+    admitted requests.  ``submit`` returns a ticket, or None when the pool
+    or the ring is full (DSG_EBUSY).
+    """
+
+    def __init__(self, ctx: Context, pool_bytes: int, ring_size: int = 8192):
+        import torch
+
+        self.ctx = ctx
+        self.pool = torch.empty(pool_bytes + 256, dtype=torch.uint8, device=ctx.torch_device)
+        aligned = (self.pool.data_ptr() + 255) // 256 * 256
+        handle = ctypes.c_void_p()
+        _check(library().dsg_server_create(ctx.handle, ctypes.c_void_p(aligned), pool_bytes, ring_size,
+                                           ctypes.addressof(handle)))
+        self._h = handle
+        self.meta = {}
+
+    @staticmethod
+    def footprint(n: int, nnz: int, T: int) -> int:
+        out = ctypes.c_int64()
+        _check(library().dsg_server_footprint(n, nnz, T, ctypes.addressof(out)))
+        return out.value
+
+    def start(self, cfg: int = 1, blocks_per_cu: int = 1, idle_seconds: float = 60.0, max_seconds: float = 900.0):
+        _check(library().dsg_server_start(self._h, cfg, blocks_per_cu, idle_seconds, max_seconds))
+        return self
+
+    def submit(self, offsets, adj, T: int, eps=(1, 10)):
+        o = np.ascontiguousarray(offsets, dtype=np.int32)
+        a = np.ascontiguousarray(adj, dtype=np.int32)
+        if a.size == 0:
+            a = np.zeros(1, dtype=np.int32)
+        num, den = parse_eps(eps)
+        t = ctypes.c_uint64()
+        st = library().dsg_server_submit(self._h, o.ctypes.data, a.ctypes.data, len(o) - 1, len(adj), T, num, den,
+                                         ctypes.addressof(t))
+        if st == -6:
+            return None
+        _check(st)
+        self.meta[t.value] = (len(o) - 1, T)
+        return t.value
+
+    def register(self, offsets, adj, validate: bool = True) -> int:
+        """Keep a CSR resident on the device for repeated requests; returns its graph id."""
+        import torch
+
+        dev = self.ctx.torch_device
+        o = torch.from_numpy(np.ascontiguousarray(offsets, dtype=np.int32)).to(dev)
+        a = torch.from_numpy(np.ascontiguousarray(adj, dtype=np.int32) if len(adj) else np.zeros(1, np.int32)).to(dev)
+        gid = ctypes.c_int32()
+        _check(library().dsg_server_register(self._h, ctypes.c_void_p(o.data_ptr()), ctypes.c_void_p(a.data_ptr()),
+                                             len(o) - 1, len(adj), VALIDATE if validate else 0,
+                                             ctypes.addressof(gid)))
+        self.resident = getattr(self, "resident", [])
+        self.resident.append((o, a, len(o) - 1))
+        return gid.value
+
+    def submit_registered(self, graph_id: int, T: int, eps=(1, 10)):
+        num, den = parse_eps(eps)
+        t = ctypes.c_uint64()
+        st = library().dsg_server_submit_registered(self._h, graph_id, T, num, den, ctypes.addressof(t))
+        if st == -6:
+            return None
+        _check(st)
+        self.meta[t.value] = (self.resident[graph_id][2], T)
+        return t.value
+
+    def poll(self, cap: int = 4096):
+        out = np.zeros(cap, dtype=np.uint64)
+        cnt = ctypes.c_int32()
+        _check(library().dsg_server_poll(self._h, out.ctypes.data, cap, ctypes.addressof(cnt)))
+        return [int(x) for x in out[:cnt.value]]
+
+    def fetch(self, ticket: int, loads: bool = False):
+        n, T = self.meta[ticket]
+        best = np.zeros(4, dtype=np.int64)
+        e = np.zeros(T, dtype=np.int64)
+        v = np.zeros(T, dtype=np.int64)
+        ix = np.zeros(T, dtype=np.int32)
+        dg = np.zeros(T, dtype=np.uint64)
+        rd = np.zeros(T, dtype=np.int32)
+        ld = np.zeros(n, dtype=np.int64) if loads else None
+        _check(library().dsg_server_fetch(self._h, ticket, best.ctypes.data, e.ctypes.data, v.ctypes.data,
+                                          ix.ctypes.data, dg.ctypes.data, rd.ctypes.data,
+                                          ld.ctypes.data if loads else None))
+        return {"best": tuple(int(x) for x in best), "hist": [(int(e[t]), int(v[t])) for t in range(T)],
+                "hist_idx": [int(x) for x in ix], "digests": [int(x) for x in dg], "rounds": [int(x) for x in rd],
+                "loads": ld}
+
+    def release(self, ticket: int):
+        _check(library().dsg_server_release(self._h, ticket))
+        self.meta.pop(ticket, None)
+
+    def stop(self):
+        _check(library().dsg_server_stop(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            library().dsg_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -815,3 +815,401 @@ dsg_status dsg_batch_destroy(dsg_batch* b) {
 }
 
 }  // extern "C"
+
+// ----------------------------------------------------------------- serving
+namespace {
+
+struct PoolAlloc {
+    // first-fit free list over [0, size): offset -> length
+    std::vector<std::pair<long long, long long>> free_list;
+    void init(long long size) { free_list.assign(1, {0, size}); }
+    long long alloc(long long bytes) {
+        bytes = al256(bytes);
+        for (size_t i = 0; i < free_list.size(); i++) {
+            if (free_list[i].second >= bytes) {
+                long long at = free_list[i].first;
+                free_list[i].first += bytes;
+                free_list[i].second -= bytes;
+                if (free_list[i].second == 0) free_list.erase(free_list.begin() + (long)i);
+                return at;
+            }
+        }
+        return -1;
+    }
+    void release(long long at, long long bytes) {
+        bytes = al256(bytes);
+        auto it = std::lower_bound(free_list.begin(), free_list.end(), std::make_pair(at, 0LL));
+        it = free_list.insert(it, {at, bytes});
+        // merge with neighbours
+        size_t i = (size_t)(it - free_list.begin());
+        if (i + 1 < free_list.size() && free_list[i].first + free_list[i].second == free_list[i + 1].first) {
+            free_list[i].second += free_list[i + 1].second;
+            free_list.erase(free_list.begin() + (long)i + 1);
+        }
+        if (i > 0 && free_list[i - 1].first + free_list[i - 1].second == free_list[i].first) {
+            free_list[i - 1].second += free_list[i].second;
+            free_list.erase(free_list.begin() + (long)i);
+        }
+    }
+};
+
+struct ServeReq {
+    uint64_t ticket;
+    long long at, bytes;  // the request's arrays in the pool
+    dsg::BatchDesc d;
+    bool reported;
+    long long csr_at, csr_bytes;  // its CSR copy in the pool (0 bytes for a registered graph)
+};
+
+long long serve_footprint(int n, long long nnz, int T) {
+    dsg_batch_graph g{};
+    g.n = n;
+    g.nnz = nnz;
+    g.T = T;
+    std::vector<dsg::BatchDesc> tmp;
+    // the batch layout of one graph minus its shared header, plus the CSR
+    const long long header = al256(sizeof(dsg::BatchDesc)) + 256 + 256 + 256 + al256(sizeof(dsg::Ctl));
+    return carve_batch(&g, 1, T, nullptr, nullptr) - header + al256(4LL * (n + 1)) + al256(4LL * (nnz > 0 ? nnz : 1));
+}
+
+}  // namespace
+
+struct dsg_server {
+    dsg_ctx* ctx;
+    char* pool;
+    long long pool_bytes;
+    int ring_size;
+    dsg::ServeHostCtl* hctl;      // host view of the pinned control block
+    dsg::ServeSlot* ring;         // host view of the pinned ring
+    dsg::ServeHostCtl* hctl_dev;  // the same memory as the device addresses it
+    dsg::ServeSlot* ring_dev;
+    unsigned long long* dhead;
+    int* derr;
+    hipStream_t kstream, cstream;
+    bool running;
+    PoolAlloc alloc;
+    uint64_t next_ticket;
+    std::vector<ServeReq> reqs;  // in flight (admitted, not released)
+    std::vector<char> slot_busy; // ring slot held by an unreleased request
+    struct Reg {
+        const int32_t* off;
+        const int32_t* adj;
+        int n;
+        long long nnz;
+        int max_deg;
+    };
+    std::vector<Reg> regs;       // resident graphs (caller-owned device CSR)
+};
+
+extern "C" {
+
+dsg_status dsg_server_footprint(int32_t n, int64_t nnz, int32_t T, int64_t* bytes) {
+    if (!bytes || n < 1 || nnz < 0 || nnz >= (1LL << 31) || T < 1) return fail(DSG_EINVAL, "bad arguments");
+    *bytes = serve_footprint(n, nnz, T);
+    return DSG_OK;
+}
+
+dsg_status dsg_server_create(dsg_ctx* ctx, void* d_pool, int64_t pool_bytes, int32_t ring_size, dsg_server** out) {
+    if (!ctx || !d_pool || !out || ring_size < 1 || pool_bytes < 4096) return fail(DSG_EINVAL, "bad arguments");
+    *out = nullptr;
+    if (reinterpret_cast<uintptr_t>(d_pool) % 256 != 0) return fail(DSG_EINVAL, "pool not 256-byte aligned");
+    DSG_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    dsg_server* s = new (std::nothrow) dsg_server();
+    if (!s) return fail(DSG_ENOMEM, "host allocation failed");
+    s->ctx = ctx;
+    s->pool = static_cast<char*>(d_pool);
+    s->pool_bytes = pool_bytes;
+    s->ring_size = ring_size;
+    // the first 512 bytes of the pool: claim counter and error flag
+    s->dhead = reinterpret_cast<unsigned long long*>(s->pool);
+    s->derr = reinterpret_cast<int*>(s->pool + 256);
+    s->alloc.init(pool_bytes - 512);
+    hipError_t e;
+    void* hp = nullptr;
+    if ((e = hipHostMalloc(&hp, sizeof(dsg::ServeHostCtl), hipHostMallocCoherent | hipHostMallocMapped)) != hipSuccess) {
+        delete s;
+        return hip_fail(e, "hipHostMalloc(ctl)");
+    }
+    s->hctl = static_cast<dsg::ServeHostCtl*>(hp);
+    memset(s->hctl, 0, sizeof(dsg::ServeHostCtl));
+    if ((e = hipHostMalloc(&hp, sizeof(dsg::ServeSlot) * (size_t)ring_size, hipHostMallocCoherent | hipHostMallocMapped)) !=
+        hipSuccess) {
+        (void)hipHostFree(s->hctl);
+        delete s;
+        return hip_fail(e, "hipHostMalloc(ring)");
+    }
+    s->ring = static_cast<dsg::ServeSlot*>(hp);
+    memset(s->ring, 0, sizeof(dsg::ServeSlot) * (size_t)ring_size);
+    s->slot_busy.assign((size_t)ring_size, 0);
+    void* dp = nullptr;
+    if ((e = hipHostGetDevicePointer(&dp, s->hctl, 0)) != hipSuccess) {
+        (void)hipHostFree(s->ring);
+        (void)hipHostFree(s->hctl);
+        delete s;
+        return hip_fail(e, "hipHostGetDevicePointer(ctl)");
+    }
+    s->hctl_dev = static_cast<dsg::ServeHostCtl*>(dp);
+    if ((e = hipHostGetDevicePointer(&dp, s->ring, 0)) != hipSuccess) {
+        (void)hipHostFree(s->ring);
+        (void)hipHostFree(s->hctl);
+        delete s;
+        return hip_fail(e, "hipHostGetDevicePointer(ring)");
+    }
+    s->ring_dev = static_cast<dsg::ServeSlot*>(dp);
+    if ((e = hipStreamCreateWithFlags(&s->kstream, hipStreamNonBlocking)) != hipSuccess ||
+        (e = hipStreamCreateWithFlags(&s->cstream, hipStreamNonBlocking)) != hipSuccess) {
+        (void)hipHostFree(s->ring);
+        (void)hipHostFree(s->hctl);
+        delete s;
+        return hip_fail(e, "hipStreamCreate");
+    }
+    *out = s;
+    return DSG_OK;
+}
+
+dsg_status dsg_server_start(dsg_server* s, int32_t cfg, int32_t blocks_per_cu, double idle_seconds, double max_seconds) {
+    if (!s) return fail(DSG_EINVAL, "server is NULL");
+    if (s->running) return fail(DSG_ESTATE, "already running");
+    if (cfg < 0 || cfg > 1 || blocks_per_cu < 1 || !(idle_seconds > 0) || !(max_seconds > 0))
+        return fail(DSG_EINVAL, "bad schedule or time limits");
+    DSG_HIP(hipSetDevice(s->ctx->device), "hipSetDevice");
+    __atomic_store_n(&s->hctl->shutdown, 0u, __ATOMIC_RELEASE);
+    hipError_t e = dsg::launch_fill(s->derr, 0, 1, s->kstream);
+    if (e != hipSuccess) return hip_fail(e, "clear error flag");
+    const unsigned long long idle = (unsigned long long)(idle_seconds * 1e8);  // 100 MHz wall clock
+    const unsigned long long maxt = (unsigned long long)(max_seconds * 1e8);
+    // requests published before a restart are never replayed: the claim
+    // counter restarts at the current tail
+    const unsigned long long tail = __atomic_load_n(&s->hctl->tail, __ATOMIC_ACQUIRE);
+    e = dsg::launch_serve(s->hctl_dev, s->ring_dev, s->ring_size, s->dhead, tail, s->derr, cfg, blocks_per_cu,
+                          s->ctx->num_cu, idle, maxt, s->kstream);
+    if (e != hipSuccess) return hip_fail(e, "serve launch");
+    s->running = true;
+    return DSG_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Admit one request whose CSR is at d_off/d_adj on the device (copied by the
+// caller of this function if it came from the host): reserve its arrays in
+// the pool, fill its ring slot and publish it.  extra_bytes/extra_at: a
+// pool region already reserved for the CSR copy (freed with the request).
+dsg_status serve_publish(dsg_server* s, const int32_t* d_off, const int32_t* d_adj, int n, long long nnz, int T,
+                         int eps_num, int eps_den, long long extra_at, long long extra_bytes, uint64_t* ticket) {
+    const long long header = al256(sizeof(dsg::BatchDesc)) + 256 + 256 + 256 + al256(sizeof(dsg::Ctl));
+    dsg_batch_graph g{};
+    g.d_offsets = d_off;
+    g.d_adj = d_adj;
+    g.n = n;
+    g.nnz = nnz;
+    g.T = T;
+    g.eps_num = eps_num;
+    g.eps_den = eps_den;
+    const long long bytes = carve_batch(&g, 1, T, nullptr, nullptr) - header;
+    const long long at = s->alloc.alloc(bytes);
+    if (at < 0) {
+        if (extra_bytes) s->alloc.release(extra_at, extra_bytes);
+        return fail(DSG_EBUSY, "HBM pool full");
+    }
+    std::vector<dsg::BatchDesc> desc;
+    carve_batch(&g, 1, T, s->pool + 512 + at - header, &desc);
+    const uint64_t t = s->next_ticket++;
+    dsg::ServeSlot* sl = &s->ring[t % (uint64_t)s->ring_size];
+    sl->d = desc[0];
+    __atomic_store_n(&sl->done, 0ull, __ATOMIC_RELAXED);
+    __atomic_store_n(&s->hctl->tail, (unsigned long long)(t + 1), __ATOMIC_RELEASE);
+    s->reqs.push_back(ServeReq{t, at, bytes, desc[0], false, extra_at, extra_bytes});
+    s->slot_busy[(size_t)(t % (uint64_t)s->ring_size)] = 1;
+    *ticket = t;
+    return DSG_OK;
+}
+
+dsg_status serve_precheck(dsg_server* s, int T, int eps_num, int eps_den, int maxdeg) {
+    if (T < 1 || eps_num < 0 || eps_den < 1) return fail(DSG_EINVAL, "bad T or eps");
+    if (!s->running || hipStreamQuery(s->kstream) == hipSuccess) {
+        s->running = false;
+        return fail(DSG_ESTATE, "server kernel is not running");
+    }
+    if (((long long)T + 1) * (long long)maxdeg >= (1LL << 31)) return fail(DSG_EOVERFLOW, "loads could exceed 31 bits");
+    // ticket t lives in ring slot t % ring_size: that slot must be free
+    if (s->slot_busy[(size_t)(s->next_ticket % (uint64_t)s->ring_size)])
+        return fail(DSG_EBUSY, "the next ring slot is still held by an unreleased request");
+    return DSG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+dsg_status dsg_server_submit(dsg_server* s, const int32_t* h_off, const int32_t* h_adj, int32_t n, int64_t nnz,
+                             int32_t T, int32_t eps_num, int32_t eps_den, uint64_t* ticket) {
+    if (!s || !h_off || !ticket || (nnz > 0 && !h_adj)) return fail(DSG_EINVAL, "NULL argument");
+    if (n < 1 || nnz < 0 || nnz >= (1LL << 31)) return fail(DSG_EINVAL, "bad n or nnz");
+    if (n >= dsg::PEEL_MAX_N) return fail(DSG_EINVAL, "n too large");
+    // memory-safety checks of the CSR on the host: offsets and entry range
+    if (h_off[0] != 0 || (long long)h_off[n] != nnz) return fail(DSG_EINVAL, "offsets[0] != 0 or offsets[n] != nnz");
+    int maxdeg = 0;
+    for (int v = 0; v < n; v++) {
+        const int d = h_off[v + 1] - h_off[v];
+        if (d < 0) return fail(DSG_EINVAL, "offsets decrease");
+        if (d > maxdeg) maxdeg = d;
+    }
+    for (long long e = 0; e < nnz; e++)
+        if (h_adj[e] < 0 || h_adj[e] >= n) return fail(DSG_EINVAL, "adjacency entry outside [0, n)");
+    dsg_status st = serve_precheck(s, T, eps_num, eps_den, maxdeg);
+    if (st != DSG_OK) return st;
+    const long long csr_bytes = al256(4LL * (n + 1)) + al256(4LL * (nnz > 0 ? nnz : 1));
+    const long long cat = s->alloc.alloc(csr_bytes);
+    if (cat < 0) return fail(DSG_EBUSY, "HBM pool full");
+    int32_t* d_off = reinterpret_cast<int32_t*>(s->pool + 512 + cat);
+    int32_t* d_adj = reinterpret_cast<int32_t*>(s->pool + 512 + cat + al256(4LL * (n + 1)));
+    hipError_t e = hipMemcpyAsync(d_off, h_off, 4LL * (n + 1), hipMemcpyHostToDevice, s->cstream);
+    if (e == hipSuccess && nnz > 0) e = hipMemcpyAsync(d_adj, h_adj, 4LL * nnz, hipMemcpyHostToDevice, s->cstream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->cstream);
+    if (e != hipSuccess) {
+        s->alloc.release(cat, csr_bytes);
+        return hip_fail(e, "copy request CSR");
+    }
+    return serve_publish(s, d_off, d_adj, n, nnz, T, eps_num, eps_den, cat, csr_bytes, ticket);
+}
+
+dsg_status dsg_server_register(dsg_server* s, const int32_t* d_offsets, const int32_t* d_adj, int32_t n, int64_t nnz,
+                               int32_t flags, int32_t* graph_id) {
+    if (!s || !d_offsets || !graph_id || (nnz > 0 && !d_adj)) return fail(DSG_EINVAL, "NULL argument");
+    if (n < 1 || nnz < 0 || nnz >= (1LL << 31) || n >= dsg::PEEL_MAX_N) return fail(DSG_EINVAL, "bad n or nnz");
+    if (s->running) return fail(DSG_ESTATE, "register graphs before dsg_server_start");
+    // device checks with the single-graph check kernels, on the copy stream;
+    // the control block sits in the pool's reserved header
+    GraphDev gd{};
+    gd.n = n;
+    gd.nnz = nnz;
+    gd.off = d_offsets;
+    gd.adj = d_adj;
+    // borrow a pool region for a control block
+    const long long cat = s->alloc.alloc(sizeof(dsg::Ctl));
+    if (cat < 0) return fail(DSG_EBUSY, "HBM pool full");
+    gd.ctl = reinterpret_cast<dsg::Ctl*>(s->pool + 512 + cat);
+    hipStream_t c = s->cstream;
+    dsg::Ctl ctl;
+    hipError_t e = dsg::launch_zero_ctl(gd, c);
+    if (e == hipSuccess) e = dsg::launch_check_offsets(gd, c);
+    if (e == hipSuccess) e = hipMemcpyAsync(&ctl, gd.ctl, sizeof ctl, hipMemcpyDeviceToHost, c);
+    if (e == hipSuccess) e = hipStreamSynchronize(c);
+    if (e == hipSuccess && ctl.err_count == 0) {
+        e = dsg::launch_check_range(gd, c);
+        if (e == hipSuccess && (flags & DSG_VALIDATE)) e = dsg::launch_check_rows(gd, c);
+        if (e == hipSuccess) e = hipMemcpyAsync(&ctl, gd.ctl, sizeof ctl, hipMemcpyDeviceToHost, c);
+        if (e == hipSuccess) e = hipStreamSynchronize(c);
+    }
+    s->alloc.release(cat, sizeof(dsg::Ctl));
+    if (e != hipSuccess) return hip_fail(e, "check registered graph");
+    if (ctl.err_count) return fail(DSG_EINVAL, std::string("invalid CSR (") + err_name(ctl.err_code) + ")");
+    s->regs.push_back(dsg_server::Reg{d_offsets, d_adj, n, nnz, ctl.max_deg});
+    *graph_id = (int32_t)s->regs.size() - 1;
+    return DSG_OK;
+}
+
+dsg_status dsg_server_submit_registered(dsg_server* s, int32_t graph_id, int32_t T, int32_t eps_num, int32_t eps_den,
+                                        uint64_t* ticket) {
+    if (!s || !ticket) return fail(DSG_EINVAL, "NULL argument");
+    if (graph_id < 0 || graph_id >= (int)s->regs.size()) return fail(DSG_EINVAL, "unknown graph id");
+    const dsg_server::Reg& r = s->regs[(size_t)graph_id];
+    dsg_status st = serve_precheck(s, T, eps_num, eps_den, r.max_deg);
+    if (st != DSG_OK) return st;
+    return serve_publish(s, r.off, r.adj, r.n, r.nnz, T, eps_num, eps_den, 0, 0, ticket);
+}
+
+dsg_status dsg_server_poll(dsg_server* s, uint64_t* h_tickets, int32_t cap, int32_t* count) {
+    if (!s || !count) return fail(DSG_EINVAL, "NULL argument");
+    int k = 0;
+    for (ServeReq& r : s->reqs) {
+        if (k >= cap) break;
+        if (r.reported) continue;
+        const dsg::ServeSlot* sl = &s->ring[r.ticket % (uint64_t)s->ring_size];
+        if (__atomic_load_n(&sl->done, __ATOMIC_ACQUIRE) == r.ticket + 1) {
+            r.reported = true;
+            if (h_tickets) h_tickets[k] = r.ticket;
+            k++;
+        }
+    }
+    *count = k;
+    return DSG_OK;
+}
+
+dsg_status dsg_server_fetch(dsg_server* s, uint64_t ticket, int64_t* best, int64_t* h_edges, int64_t* h_verts,
+                            int32_t* h_index, uint64_t* h_digest, int32_t* h_rounds, int64_t* h_loads) {
+    if (!s) return fail(DSG_EINVAL, "server is NULL");
+    ServeReq* r = nullptr;
+    for (ServeReq& x : s->reqs)
+        if (x.ticket == ticket) r = &x;
+    if (!r) return fail(DSG_EINVAL, "unknown ticket");
+    const dsg::ServeSlot* sl = &s->ring[ticket % (uint64_t)s->ring_size];
+    if (__atomic_load_n(&sl->done, __ATOMIC_ACQUIRE) != ticket + 1) return fail(DSG_ESTATE, "request not finished");
+    const dsg::BatchDesc& d = r->d;
+    const int T = d.T;
+    hipStream_t c = s->cstream;
+    long long bs[4];
+    std::vector<int32_t> loads32;
+    hipError_t e = hipMemcpyAsync(bs, d.best, sizeof bs, hipMemcpyDeviceToHost, c);
+    if (e == hipSuccess && h_edges) e = hipMemcpyAsync(h_edges, d.hist_e, 8LL * T, hipMemcpyDeviceToHost, c);
+    if (e == hipSuccess && h_verts) e = hipMemcpyAsync(h_verts, d.hist_v, 8LL * T, hipMemcpyDeviceToHost, c);
+    if (e == hipSuccess && h_index) e = hipMemcpyAsync(h_index, d.hist_i, 4LL * T, hipMemcpyDeviceToHost, c);
+    if (e == hipSuccess && h_digest) e = hipMemcpyAsync(h_digest, d.digest, 8LL * T, hipMemcpyDeviceToHost, c);
+    if (e == hipSuccess && h_rounds) e = hipMemcpyAsync(h_rounds, d.rounds, 4LL * T, hipMemcpyDeviceToHost, c);
+    if (e == hipSuccess && h_loads) {
+        loads32.resize((size_t)d.n);
+        e = hipMemcpyAsync(loads32.data(), d.load, 4LL * d.n, hipMemcpyDeviceToHost, c);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(c);
+    if (e != hipSuccess) return hip_fail(e, "fetch results");
+    if (best)
+        for (int i = 0; i < 4; i++) best[i] = bs[i];
+    if (h_loads)
+        for (int v = 0; v < d.n; v++) h_loads[v] = loads32[(size_t)v];
+    return DSG_OK;
+}
+
+dsg_status dsg_server_release(dsg_server* s, uint64_t ticket) {
+    if (!s) return fail(DSG_EINVAL, "server is NULL");
+    for (size_t i = 0; i < s->reqs.size(); i++) {
+        if (s->reqs[i].ticket != ticket) continue;
+        const dsg::ServeSlot* sl = &s->ring[ticket % (uint64_t)s->ring_size];
+        if (__atomic_load_n(&sl->done, __ATOMIC_ACQUIRE) != ticket + 1)
+            return fail(DSG_ESTATE, "request not finished");
+        s->alloc.release(s->reqs[i].at, s->reqs[i].bytes);
+        if (s->reqs[i].csr_bytes) s->alloc.release(s->reqs[i].csr_at, s->reqs[i].csr_bytes);
+        s->slot_busy[(size_t)(ticket % (uint64_t)s->ring_size)] = 0;
+        s->reqs.erase(s->reqs.begin() + (long)i);
+        return DSG_OK;
+    }
+    return fail(DSG_EINVAL, "unknown ticket");
+}
+
+dsg_status dsg_server_stop(dsg_server* s) {
+    if (!s) return fail(DSG_EINVAL, "server is NULL");
+    __atomic_store_n(&s->hctl->shutdown, 1u, __ATOMIC_RELEASE);
+    DSG_HIP(hipStreamSynchronize(s->kstream), "hipStreamSynchronize(server)");
+    s->running = false;
+    int err = 0;
+    DSG_HIP(hipMemcpy(&err, s->derr, sizeof err, hipMemcpyDeviceToHost), "hipMemcpy(err)");
+    if (err) return fail(DSG_EDEVICE, "a serving kernel consistency check failed");
+    return DSG_OK;
+}
+
+dsg_status dsg_server_destroy(dsg_server* s) {
+    if (!s) return DSG_OK;
+    if (s->running) {
+        __atomic_store_n(&s->hctl->shutdown, 1u, __ATOMIC_RELEASE);
+        (void)hipStreamSynchronize(s->kstream);
+    }
+    (void)hipStreamDestroy(s->kstream);
+    (void)hipStreamDestroy(s->cstream);
+    (void)hipHostFree(s->ring);
+    (void)hipHostFree(s->hctl);
+    delete s;
+    return DSG_OK;
+}
+
+}  // extern "C"

@@ -162,6 +162,25 @@ hipError_t launch_batch(const BatchDesc* descs, const int* order, int count, uns
                         int blocks_per_cu, int num_cu, hipStream_t s);
 hipError_t launch_batch_reset(BatchDesc* descs, int count, hipStream_t s);
 hipError_t launch_fill(int* p, int v, long long cnt, hipStream_t s);
+
+// Serving: control block and request ring in pinned host memory.
+struct ServeHostCtl {
+    unsigned long long tail;  // requests published by the host
+    unsigned long long pad0[7];
+    unsigned int shutdown;    // host sets 1: blocks leave once the queue is drained
+    unsigned int pad1[15];
+};
+
+struct ServeSlot {
+    BatchDesc d;
+    unsigned long long done;  // ticket + 1 once the result is in device memory
+    unsigned long long pad[7];
+};
+
+// cfg 0 = 256 threads / 1024-edge chunks, otherwise 512 / 2048
+hipError_t launch_serve(ServeHostCtl* hc, ServeSlot* ring, int ring_size, unsigned long long* dhead,
+                        unsigned long long head0, int* err, int cfg, int blocks_per_cu, int num_cu,
+                        unsigned long long idle_ticks, unsigned long long max_ticks, hipStream_t s);
 constexpr int BATCH_MIN_CH = 1024;
 
 int peel_blocks_per_cu();

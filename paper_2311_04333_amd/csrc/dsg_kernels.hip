@@ -1329,6 +1329,86 @@ __global__ void k_batch_reset(BatchDesc* descs, int count) {
     }
 }
 
+// =============================================================== SERVE
+// Continuous batching: one persistent kernel serves a request stream.  The
+// host publishes request descriptors into a ring in pinned host memory and
+// raises `tail`.  An idle block claims the next request with a CAS on a
+// device counter and runs all of its iterations (the same per-graph
+// iteration as the batch kernel, so results equal those of a lone run).
+// It then signals completion through the slot's `done` word.  Requests that
+// arrive while others run start as soon as a block is free.  Every block
+// leaves once the host raises `shutdown` and the queue is drained, after
+// `idle_ticks` of waiting with nothing to claim, or after `max_ticks` in
+// total (wall clock at 100 MHz), so the grid always drains.
+template <int BLK, int CH>
+__global__ __launch_bounds__(BLK) void k_serve(ServeHostCtl* hc, ServeSlot* ring, int ring_size,
+                                               unsigned long long* dhead, int* err, unsigned long long idle_ticks,
+                                               unsigned long long max_ticks) {
+    __shared__ BatchLds<CH> lds;
+    __shared__ long long s_claim;
+    __shared__ BatchDesc s_desc;
+    for (int i = threadIdx.x; i < 2 * CH; i += BLK) {
+        lds.dec.key[i] = DEC_EMPTY;
+        lds.dec.cnt[i] = 0;
+    }
+    const unsigned long long t_start = wall_clock64();
+    while (true) {
+        if (threadIdx.x == 0) {
+            long long claim = -1;
+            const unsigned long long idle_from = wall_clock64();
+            while (true) {
+                const unsigned long long tail =
+                    __hip_atomic_load(&hc->tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+                const unsigned long long h = __hip_atomic_load(dhead, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (h < tail) {
+                    if (atomicCAS(dhead, h, h + 1) == h) {
+                        claim = (long long)h;
+                        break;
+                    }
+                    continue;
+                }
+                if (__hip_atomic_load(&hc->shutdown, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) break;
+                const unsigned long long now = wall_clock64();
+                if (now - idle_from > idle_ticks || now - t_start > max_ticks) break;
+                __builtin_amdgcn_s_sleep(127);
+            }
+            s_claim = claim;
+        }
+        __syncthreads();
+        const long long claim = s_claim;
+        if (claim < 0) break;
+        ServeSlot* sl = &ring[claim % ring_size];
+        {
+            // the descriptor sits in host memory: read it once, into LDS
+            const int* src = reinterpret_cast<const int*>(&sl->d);
+            int* dst = reinterpret_cast<int*>(&s_desc);
+            for (int w = threadIdx.x; w < (int)(sizeof(BatchDesc) / 4); w += BLK)
+                dst[w] = __hip_atomic_load(src + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+        __syncthreads();
+        const BatchDesc d = s_desc;
+        for (int v = threadIdx.x; v < d.n; v += BLK) d.load[v] = 0;
+        if (threadIdx.x == 0) {
+            d.best[0] = d.nnz / 2;
+            d.best[1] = d.n;
+            d.best[2] = 0;
+            d.best[3] = 0;
+            d.state[4] = 0;
+        }
+        __syncthreads();
+        const int T = d.T < d.t_cap ? d.T : d.t_cap;
+        for (int t = 0; t < T; t++) batch_iteration<BLK, CH>(d, lds, err, t);
+        if (threadIdx.x == 0) {
+            d.state[4] = T;
+            // results are in device memory: write the L2 back before the host
+            // sees the flag and copies them out
+            __threadfence_system();
+            __hip_atomic_store(&sl->done, (unsigned long long)claim + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+        __syncthreads();
+    }
+}
+
 // ================================================================= launchers
 namespace {
 inline int grid_for(long long n, int blk, int cap = 4096) {
@@ -1546,6 +1626,29 @@ hipError_t launch_fill(int* p, int v, long long cnt, hipStream_t s) {
 
 hipError_t launch_batch_reset(BatchDesc* descs, int count, hipStream_t s) {
     k_batch_reset<<<count < 2048 ? (count > 0 ? count : 1) : 2048, 256, 0, s>>>(descs, count);
+    return hipGetLastError();
+}
+
+
+__global__ void k_set_u64(unsigned long long* p, unsigned long long v) {
+    if (threadIdx.x == 0) *p = v;
+}
+
+hipError_t launch_serve(ServeHostCtl* hc, ServeSlot* ring, int ring_size, unsigned long long* dhead,
+                        unsigned long long head0, int* err, int cfg, int blocks_per_cu, int num_cu,
+                        unsigned long long idle_ticks, unsigned long long max_ticks, hipStream_t s) {
+    // the claim counter starts at the first unpublished ticket, in stream order
+    // before the kernel
+    k_set_u64<<<1, 64, 0, s>>>(dhead, head0);
+    int grid = num_cu * (blocks_per_cu < 1 ? 1 : blocks_per_cu);
+    switch (cfg) {
+        case 0:
+            k_serve<256, 1024><<<grid, 256, 0, s>>>(hc, ring, ring_size, dhead, err, idle_ticks, max_ticks);
+            break;
+        default:
+            k_serve<512, 2048><<<grid, 512, 0, s>>>(hc, ring, ring_size, dhead, err, idle_ticks, max_ticks);
+            break;
+    }
     return hipGetLastError();
 }
 
