@@ -146,6 +146,23 @@ dsg_status dsg_graph_destroy(dsg_graph* g);
  * the work to finish. */
 dsg_status dsg_last_run_ms(dsg_graph* g, float* ms);
 
+/* Tuning of the PEEL round loop; results do not depend on it.  Both
+ * thresholds count the adjacency entries of a round's frontier, and -1
+ * selects the default.
+ *  - bucket_min_edges: from this size on, a round applies its neighbour-degree
+ *    decrements through owner buckets.  The buckets cover contiguous ranges of
+ *    up to 16384 vertex ids, and each range is summed by one block in a dense
+ *    LDS histogram after an extra grid barrier.  Smaller rounds apply the
+ *    decrements with per-chunk aggregated device atomics.  Default 2^20;
+ *    0 buckets every round.  Graphs with more than 1024 * 16384 vertices always
+ *    take the atomic path.
+ *  - coarse_min_edges: from this size on, a round sweeps 4096-edge chunks;
+ *    smaller rounds sweep 1024-edge chunks, so that more blocks share them.
+ *    Default 2^20; 0 = always coarse.
+ * The setting is kept across dsg_reset.  Returns DSG_EINVAL for a value below
+ * -1 or a NULL graph. */
+dsg_status dsg_set_peel_tuning(dsg_graph* g, int64_t bucket_min_edges, int64_t coarse_min_edges);
+
 /* Optional per-launch timing of each iteration's dominant kernel (the PEEL
  * round loop, the SORT sweep, the SEQ peel): HIP events are recorded on the
  * graph's stream right before and after every such launch of later dsg_run

@@ -49,6 +49,7 @@ SIGNATURES = [
     ("dsg_get_iter_digests", ctypes.c_int, [_P, _P, _P, _I32, _P]),
     ("dsg_graph_destroy", ctypes.c_int, [_P]),
     ("dsg_last_run_ms", ctypes.c_int, [_P, _P]),
+    ("dsg_set_peel_tuning", ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int64]),
     ("dsg_set_kernel_timing", ctypes.c_int, [_P, _I32]),
     ("dsg_get_kernel_timing", ctypes.c_int, [_P, _P, _P]),
     ("dsg_batch_workspace_bytes", ctypes.c_int, [_P, _I32, _I32, _P]),
@@ -237,6 +238,12 @@ class Graph:
         ms = ctypes.c_float()
         _check(library().dsg_last_run_ms(self._h, ctypes.addressof(ms)))
         return ms.value
+
+    def set_peel_tuning(self, bucket_min_edges: int = -1, coarse_min_edges: int = -1):
+        """PEEL round-loop tuning (results do not depend on it): frontier sizes (adjacency entries) from which a
+        round applies decrements through owner buckets, and from which it sweeps coarse chunks; -1 = default."""
+        _check(library().dsg_set_peel_tuning(self._h, int(bucket_min_edges), int(coarse_min_edges)))
+        return self
 
     def set_kernel_timing(self, enable: bool = True):
         _check(library().dsg_set_kernel_timing(self._h, 1 if enable else 0))

@@ -42,6 +42,8 @@ struct dsg_graph {
     bool ktime;                    // per-launch timing of the dominant kernel
     std::vector<hipEvent_t> kev;   // 2 events per timed launch
     int klaunches;                 // timed launches of the last dsg_run
+    long long bkt_min_e;           // PEEL rounds with at least this many frontier edges use owner buckets
+    long long coarse_min_e;        // ... and coarse sweep chunks; -1 = default
 };
 
 struct dsg_batch {
@@ -82,7 +84,7 @@ dsg_status hip_fail(hipError_t e, const char* where) {
     } while (0)
 
 struct Layout {
-    long long off[40];
+    long long off[48];
     int count = 0;
     long long total = 0;
     long long add(long long bytes) {
@@ -113,7 +115,13 @@ long long carve(int n, long long nnz, int t_cap, char* base, GraphDev* g) {
     long long o_rh = L.add(4 * 256 * rtiles);
     long long o_he = L.add(8LL * t_cap), o_hv = L.add(8LL * t_cap), o_hi = L.add(4LL * t_cap);
     long long o_rd = L.add(4LL * t_cap), o_dg = L.add(8LL * t_cap);
+    const int rshift = dsg::bucket_shift(N);
+    long long o_bkt = L.add(rshift >= 0 ? 4 * nnz : 0), o_bf = L.add(4 * dsg::BKT_MAX_NR);
     if (base && g) {
+        g->rshift = rshift >= 0 ? rshift : 0;
+        g->nr = rshift >= 0 ? (int)((N + (1LL << rshift) - 1) >> rshift) : 0;
+        g->bkt = reinterpret_cast<int*>(base + o_bkt);
+        g->bfill = reinterpret_cast<unsigned int*>(base + o_bf);
         g->ctl = reinterpret_cast<dsg::Ctl*>(base + o_ctl);
         g->gsync = reinterpret_cast<dsg::GridSync*>(base + o_gs);
         g->load = reinterpret_cast<int*>(base + o_load);
@@ -209,10 +217,10 @@ dsg_status dsg_ctx_create(int device, void* hip_stream, dsg_ctx** out) {
     c->stream = reinterpret_cast<hipStream_t>(hip_stream);
     c->num_cu = prop.multiProcessorCount;
     int per_cu = dsg::peel_blocks_per_cu();
-    // one block per CU: the round loop's grid syncs cost grow with the
-    // number of blocks, and 1024 threads per CU keep enough loads in flight
+    // one block per CU: the round loop's grid syncs cost more with more
+    // blocks, and 1024 threads per CU keep enough loads in flight
     if (per_cu < 1) return fail(DSG_EDEVICE, "round kernel cannot be resident");
-    c->peel_grid = c->num_cu;
+    c->peel_grid = c->num_cu * (per_cu < dsg::PEEL_BLOCKS_PER_CU ? per_cu : dsg::PEEL_BLOCKS_PER_CU);
     c->sort_grid = c->num_cu * 8;
     *out = c;
     return DSG_OK;
@@ -252,6 +260,8 @@ dsg_status dsg_graph_create(dsg_ctx* ctx, int32_t n, int64_t nnz, const int32_t*
     g->ws_bytes = workspace_bytes;
     g->t_cap = t_cap;
     g->last_variant = -1;
+    g->bkt_min_e = dsg::BKT_DEFAULT_MIN_E;
+    g->coarse_min_e = -1;
     g->d.n = n;
     g->d.nnz = nnz;
     g->d.off = d_offsets;
@@ -327,7 +337,9 @@ dsg_status dsg_run(dsg_graph* g, int32_t T, int32_t eps_num, int32_t eps_den, ds
         hipEvent_t eb = g->ktime ? g->kev[2 * t + 1] : nullptr;
         hipError_t e;
         if (variant == DSG_PEEL) {
-            e = dsg::enqueue_iter_peel(g->d, slot, eps_num, eps_den, g->ctx->peel_grid, s, ea, eb);
+            e = dsg::enqueue_iter_peel(g->d, slot, eps_num, eps_den, g->ctx->peel_grid, g->bkt_min_e,
+                                       g->coarse_min_e >= 0 ? g->coarse_min_e : dsg::PEEL_DEFAULT_COARSE_MIN_E,
+                                       s, ea, eb);
         } else if (variant == DSG_SORT) {
             long long bound = (long long)(g->iters_done + t) * (long long)g->d.max_deg;
             int bits = 0;
@@ -373,6 +385,14 @@ dsg_status dsg_last_run_ms(dsg_graph* g, float* ms) {
     if (!g->timed) return fail(DSG_ESTATE, "no run recorded");
     DSG_HIP(hipEventSynchronize(g->ev1), "hipEventSynchronize");
     DSG_HIP(hipEventElapsedTime(ms, g->ev0, g->ev1), "hipEventElapsedTime");
+    return DSG_OK;
+}
+
+dsg_status dsg_set_peel_tuning(dsg_graph* g, int64_t bucket_min_edges, int64_t coarse_min_edges) {
+    if (!g) return fail(DSG_EINVAL, "graph is NULL");
+    if (bucket_min_edges < -1 || coarse_min_edges < -1) return fail(DSG_EINVAL, "thresholds must be >= -1");
+    g->bkt_min_e = bucket_min_edges >= 0 ? bucket_min_edges : dsg::BKT_DEFAULT_MIN_E;
+    g->coarse_min_e = coarse_min_edges;
     return DSG_OK;
 }
 

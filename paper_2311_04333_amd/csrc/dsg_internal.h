@@ -10,14 +10,38 @@ namespace dsg {
 struct Ctl;
 struct GridSync;
 
-constexpr int PEEL_BLK = 1024;     // threads per block of the persistent round kernel (one block per CU)
-constexpr int PEEL_CH = 4096;      // edges per PEEL sweep chunk (items per chunk <= this)
+constexpr int PEEL_BLK = 1024;     // threads per block of the persistent round kernel
+constexpr int PEEL_BLOCKS_PER_CU = 1;  // measured: two 512-thread blocks per CU are slower (more grid-sync arrivals)
+constexpr int PEEL_CH = 4096;      // edges per coarse PEEL sweep chunk (items per chunk <= this)
+constexpr int PEEL_MARK = 1024;    // PEEL chunk markers are written per 1024 edges; fine chunks are one marker,
+                                   // coarse chunks PEEL_CH / PEEL_MARK markers
+// a round sweeps coarse chunks when its frontier has at least this many edges (measured on R-MAT scale 22:
+// about one coarse chunk per block of the grid)
+constexpr long long PEEL_DEFAULT_COARSE_MIN_E = 1LL << 20;
 constexpr int SORT_BLK = 512;      // threads per block of the SORT sweep
 constexpr int SORT_CH = 4096;      // edges per SORT sweep chunk
-constexpr int MIN_CH = PEEL_CH < SORT_CH ? PEEL_CH : SORT_CH;
+constexpr int MIN_CH = PEEL_MARK < SORT_CH ? PEEL_MARK : SORT_CH;  // finest chunk-marker granularity
 constexpr int SEQ_BLK = 1024;      // threads of the single SEQ block
 constexpr int SEQ_MAX_N = 16000;   // SEQ keeps n priorities in LDS (< 64 KB)
 constexpr int PEEL_MAX_N = 1 << 26;  // frontier item counter has 26 bits
+// Owner-bucketed decrements of the PEEL round loop: vertex ids are split into
+// ranges of 2^shift ids (shift <= BKT_MAX_SHIFT, so a range's counters fit a
+// dense LDS histogram), at most BKT_MAX_NR ranges.  Larger graphs keep the
+// direct path.  Rounds whose frontier has at least the threshold's edges
+// take the bucketed path.
+constexpr int BKT_MAX_SHIFT = 14;
+constexpr int BKT_MAX_NR = 1024;
+constexpr int BKT_CNT_BITS = 12;  // bucket entry = local id << 12 | (count - 1); count <= PEEL_CH
+constexpr long long BKT_DEFAULT_MIN_E = 1LL << 20;
+static_assert((1 << BKT_CNT_BITS) >= 4096, "chunk-local counts must fit the entry's count field");
+// Range shift for n vertices, or -1 when the graph is too large for the
+// bucketed path: the smallest shift >= 8 giving at most 256 ranges, capped
+// at BKT_MAX_SHIFT.
+inline int bucket_shift(long long n) {
+    int s = 8;
+    while (s < BKT_MAX_SHIFT && ((n + (1LL << s) - 1) >> s) > 256) s++;
+    return ((n + (1LL << s) - 1) >> s) <= BKT_MAX_NR ? s : -1;
+}
 
 struct PeelArgs {
     int n;
@@ -40,6 +64,12 @@ struct PeelArgs {
     int* clast;
     Ctl* ctl;
     GridSync* gs;
+    int* bkt;              // owner buckets (nnz entries; range j starts at off[j << rshift])
+    unsigned int* bfill;   // per-range fill counters, zero between bucketed rounds
+    int rshift;
+    int nr;                // ranges; 0 = bucketed path off
+    long long bkt_min_e;   // frontier edges from which a round is bucketed
+    long long coarse_min_e;  // frontier edges from which a round sweeps coarse chunks
 };
 
 struct SweepArgs {
@@ -100,6 +130,10 @@ struct GraphDev {
     int* hist_i;
     int* rounds;
     unsigned long long* digest;
+    int* bkt;
+    unsigned int* bfill;
+    int rshift;
+    int nr;
     int n_items;  // vertices with degree > 0
     int max_deg;
 };
@@ -115,8 +149,9 @@ hipError_t launch_zero_ctl(const GraphDev& g, hipStream_t s);
 // One iteration; `slot` is the history index written by this iteration.
 // ev_a / ev_b (may be null) are recorded on `s` right before and after the
 // iteration's dominant kernel (PEEL round loop, SORT sweep, SEQ peel).
-hipError_t enqueue_iter_peel(const GraphDev& g, int slot, int eps_num, int eps_den, int peel_grid, hipStream_t s,
-                             hipEvent_t ev_a, hipEvent_t ev_b);
+hipError_t enqueue_iter_peel(const GraphDev& g, int slot, int eps_num, int eps_den, int peel_grid,
+                             long long bkt_min_e, long long coarse_min_e, hipStream_t s, hipEvent_t ev_a,
+                             hipEvent_t ev_b);
 hipError_t enqueue_iter_sort(const GraphDev& g, int slot, int key_bits, int sort_grid, hipStream_t s, hipEvent_t ev_a,
                              hipEvent_t ev_b);
 hipError_t enqueue_iter_seq(const GraphDev& g, int slot, hipStream_t s, hipEvent_t ev_a, hipEvent_t ev_b);

@@ -390,15 +390,18 @@ struct SweepLds {
 // Chunks are handed out by an atomic counter (`cnext`, zero at the start)
 // when it is given, else statically (b, b + grid, ...).  The block
 // barriers inside a chunk order LDS only, so the chunk's global atomics
-// (charges, aggregated decrements) overlap the next chunk's loads.
-template <int BLK, int CH, class Op>
+// (charges, aggregated decrements) overlap the next chunk's loads.  The
+// markers may be finer than the chunk: MS markers per chunk, so chunk c
+// starts at item cfirst[c * MS] and ends at item clast[c * MS + MS - 1].
+template <int BLK, int CH, int MS, class Op, class Lds>
 __device__ __forceinline__ void sweep_chunks(int K, long long E, const int* __restrict__ iv, const int* __restrict__ ie,
                                              const int* __restrict__ ir, const int* __restrict__ cfirst,
                                              const int* __restrict__ clast, const int* __restrict__ adj,
-                                             int* __restrict__ inc, Op& op, SweepLds<CH>& s, int block, int nblocks,
+                                             int* __restrict__ inc, Op& op, Lds& s, int block, int nblocks,
                                              unsigned int* cnext, int* s_chunk) {
     constexpr int EPT = CH / BLK;
     static_assert(EPT * BLK == CH, "chunk must be a multiple of the block");
+    static_assert(sizeof(s.fe) >= sizeof(int) * CH, "LDS item arrays must hold a chunk's items");
     const long long nchunks = (E + CH - 1) / CH;
     long long c = block;
     if (cnext) {
@@ -410,8 +413,8 @@ __device__ __forceinline__ void sweep_chunks(int K, long long E, const int* __re
     for (; c < nchunks;) {
         const long long x0 = c * CH;
         const long long x1 = min(E, x0 + CH);
-        const int k0 = cfirst[c];
-        const int k1 = (c + 1 < nchunks) ? clast[c] : K - 1;
+        const int k0 = cfirst[c * MS];
+        const int k1 = (c + 1 < nchunks) ? clast[c * MS + MS - 1] : K - 1;
         const int nitems = k1 - k0 + 1;
         if (nitems < 1 || nitems > CH) {
             // impossible when every item has an edge in the chunk; refuse to
@@ -458,9 +461,30 @@ __device__ __forceinline__ void sweep_chunks(int K, long long E, const int* __re
         }
 #pragma unroll
         for (int e = 0; e < EPT; e++) st[e] = jj[e] >= 0 ? op.gather(uu[e]) : 0;
+        bool hit[EPT];
 #pragma unroll
-        for (int e = 0; e < EPT; e++)
-            if (jj[e] >= 0 && op.edge(s.v[jj[e]], uu[e], st[e], jj[e])) atomicAdd(&s.cnt[jj[e]], 1);
+        for (int e = 0; e < EPT; e++) hit[e] = jj[e] >= 0 && op.edge(s.v[jj[e]], uu[e], st[e], jj[e]);
+        // Per-item counts.  Same-address LDS atomics serialise, and in a hub
+        // row every edge of the chunk has the same item, so the counts are
+        // summed first: over runs of one item within the thread's consecutive
+        // edges, then over the wave when all its lanes end on one item.
+        int rj = jj[0], rc = 0;
+#pragma unroll
+        for (int e = 0; e < EPT; e++) {
+            if (jj[e] != rj) {
+                if (rc) atomicAdd(&s.cnt[rj], rc);
+                rj = jj[e];
+                rc = 0;
+            }
+            rc += hit[e] ? 1 : 0;
+        }
+        const int j0 = __builtin_amdgcn_readfirstlane(rj);
+        if (__all(rj == j0)) {
+            const int tot = wave_sum(rc);
+            if ((threadIdx.x & (WAVE - 1)) == 0 && tot) atomicAdd(&s.cnt[j0], tot);
+        } else if (rc) {
+            atomicAdd(&s.cnt[rj], rc);
+        }
         lds_barrier();
         for (int j = threadIdx.x; j < nitems; j += BLK)
             if (s.cnt[j]) atomicAdd(&inc[s.v[j]], s.cnt[j]);
@@ -498,8 +522,10 @@ __global__ __launch_bounds__(256) void k_peel_init(int n, const int* __restrict_
     if (threadIdx.x == 0) atomicMin(&ctl->mn[0], lmin);
 }
 
-// Clears the per-iteration control fields and the grid-barrier state.
-__global__ void k_iter_begin(Ctl* ctl, GridSync* gs) {
+// Clears the per-iteration control fields, the grid-barrier state and the
+// owner-bucket fill counters.
+__global__ void k_iter_begin(Ctl* ctl, GridSync* gs, unsigned int* bfill, int nr) {
+    for (int j = threadIdx.x; j < nr; j += blockDim.x) bfill[j] = 0;
     if (threadIdx.x < 4) {
         ctl->mn[threadIdx.x] = 0xFFFFFFFFu;
         ctl->lcnt[threadIdx.x] = 0;
@@ -530,10 +556,19 @@ struct DecTable {
     int cnt[DEC_SLOTS];
 };
 
-struct PeelLds {
+struct PeelSweepLds {
     SweepLds<PEEL_CH> sw;
     DecTable dec;
 };
+struct PeelLds {
+    union {
+        PeelSweepLds m;                     // the sweep
+        int dense[1 << BKT_MAX_SHIFT];      // the bucketed apply step (after the sweep)
+    };
+    int bcnt[BKT_MAX_NR];   // per-range entries of the chunk being flushed
+    int bbase[BKT_MAX_NR];  // their reserved start in the range's bucket
+};
+static_assert(sizeof(PeelSweepLds) >= sizeof(int) * (1 << BKT_MAX_SHIFT), "dense histogram aliases the sweep");
 
 // What an edge (v, u) of a frontier vertex v does in round r:
 //   u alive after the round (round[u] == -1): v is charged the edge, and
@@ -558,6 +593,17 @@ struct PeelEdgeOp {
     unsigned int lmin;
     Ctl* ctl;
     DecTable* dec;
+    // bucketed rounds: the chunk's aggregated (target, count) pairs go to
+    // the owner range's bucket instead of one atomicSub per target
+    bool bucket;
+    int rshift;
+    int nr;
+    int n;
+    const int* off;
+    int* bkt;
+    unsigned int* bfill;
+    int* bcnt;
+    int* bbase;
     __device__ void flag_error() {
         atomicAdd(&ctl->err_count, 1);
         ctl->err_code = ERR_INTERNAL;
@@ -583,6 +629,10 @@ struct PeelEdgeOp {
         return su == 3 && u > v;
     }
     __device__ __forceinline__ void flush_chunk() {
+        if (bucket) {
+            flush_to_buckets();
+            return;
+        }
         constexpr int PER = DEC_SLOTS / PEEL_BLK;
         static_assert(PER * PEEL_BLK == DEC_SLOTS, "slots must be a multiple of the block");
         lds_barrier();
@@ -600,6 +650,51 @@ struct PeelEdgeOp {
         for (int k = 0; k < PER; k++) {
             if (key[k] != DEC_EMPTY) {
                 lmin = min(lmin, (unsigned int)(old[k] - c[k]));
+                const int slot = threadIdx.x + k * PEEL_BLK;
+                dec->key[slot] = DEC_EMPTY;
+                dec->cnt[slot] = 0;
+            }
+        }
+    }
+    // Ranks each aggregated target within its owner range (LDS counters),
+    // reserves the chunk's share of every touched range's bucket with one
+    // global atomic per range, then writes the entries.  A range's bucket
+    // holds at most one entry per decrement of its vertices in a round, so
+    // its capacity is the range's degree sum: it starts at off[j << rshift].
+    __device__ __forceinline__ void flush_to_buckets() {
+        constexpr int PER = DEC_SLOTS / PEEL_BLK;
+        lds_barrier();
+        int key[PER], c[PER], rk[PER];
+#pragma unroll
+        for (int k = 0; k < PER; k++) {
+            const int slot = threadIdx.x + k * PEEL_BLK;
+            key[k] = dec->key[slot];
+            c[k] = dec->cnt[slot];
+            rk[k] = key[k] != DEC_EMPTY ? atomicAdd(&bcnt[key[k] >> rshift], 1) : 0;
+        }
+        lds_barrier();
+        for (int j = threadIdx.x; j < nr; j += PEEL_BLK) {
+            const int cj = bcnt[j];
+            if (cj) {
+                const int lo = off[j << rshift];
+                const int hi = off[min(n, (j + 1) << rshift)];
+                const int b = lo + (int)atomicAdd(&bfill[j], (unsigned int)cj);
+                if (b + cj > hi) {  // impossible by the capacity argument; never write past the range
+                    flag_error();
+                    bbase[j] = -1;
+                } else {
+                    bbase[j] = b;
+                }
+                bcnt[j] = 0;
+            }
+        }
+        lds_barrier();
+#pragma unroll
+        for (int k = 0; k < PER; k++) {
+            if (key[k] != DEC_EMPTY) {
+                const int j = key[k] >> rshift;
+                const int b = bbase[j];
+                if (b >= 0) bkt[b + rk[k]] = ((key[k] - (j << rshift)) << BKT_CNT_BITS) | (c[k] - 1);
                 const int slot = threadIdx.x + k * PEEL_BLK;
                 dec->key[slot] = DEC_EMPTY;
                 dec->cnt[slot] = 0;
@@ -630,11 +725,15 @@ static_assert(PEEL_BLK * SEL_U <= (int)TCNT_MASK, "tile counts must fit their pa
 //     the item list (vertex, edge start, row base, chunk markers) and the
 //     survivors to L_{r+1}.  Survivors bid their priority for ring.mn[r+1].
 //   grid sync
-//   sweep: edge-balanced over the round's items (PeelEdgeOp).
+//   sweep: edge-balanced over the round's items (PeelEdgeOp).  In rounds
+//     with many frontier edges the aggregated decrements go to owner-range
+//     buckets, and after one more grid sync each block applies its ranges'
+//     buckets (global atomics run at about 27 G/s on random targets, which
+//     bounded those rounds).
 //   grid sync
 // L_0 is implicit (all vertices).  The loop ends when L_r is empty.  Every
 // block reads the same counters after a grid sync, so all leave together.
-__global__ __launch_bounds__(PEEL_BLK) void k_peel_rounds(PeelArgs a) {
+__global__ __launch_bounds__(PEEL_BLK, PEEL_BLOCKS_PER_CU) void k_peel_rounds(PeelArgs a) {
     __shared__ PeelLds lds;
     __shared__ unsigned long long shs[PEEL_BLK / WAVE];
     __shared__ unsigned int shm[PEEL_BLK / WAVE];
@@ -648,9 +747,10 @@ __global__ __launch_bounds__(PEEL_BLK) void k_peel_rounds(PeelArgs a) {
     unsigned int epoch = 0;
     const long long q = a.eps_den, p = a.eps_num;
     for (int slot = threadIdx.x; slot < DEC_SLOTS; slot += PEEL_BLK) {
-        lds.dec.key[slot] = DEC_EMPTY;
-        lds.dec.cnt[slot] = 0;
+        lds.m.dec.key[slot] = DEC_EMPTY;
+        lds.m.dec.cnt[slot] = 0;
     }
+    for (int j = threadIdx.x; j < BKT_MAX_NR; j += PEEL_BLK) lds.bcnt[j] = 0;
     grid_sync_init(gs, nblocks, xid);
     int prevLc = a.n + 1;
     for (int r = 0;; r++) {
@@ -701,8 +801,10 @@ __global__ __launch_bounds__(PEEL_BLK) void k_peel_rounds(PeelArgs a) {
         constexpr int TILE = PEEL_BLK * SEL_U;
         unsigned int lmin = 0xFFFFFFFFu;
         unsigned long long my_items = 0, my_edges = 0, my_surv = 0;
+        // a slice of one tile stays in registers for the writing pass
+        const bool one_tile = end - beg <= TILE;
+        int u[SEL_U], pu[SEL_U], o0[SEL_U], o1[SEL_U];
         for (int base = beg; base < end; base += TILE) {
-            int u[SEL_U], pu[SEL_U];
 #pragma unroll
             for (int k = 0; k < SEL_U; k++) {
                 const int idx = base + (int)threadIdx.x * SEL_U + k;
@@ -710,7 +812,6 @@ __global__ __launch_bounds__(PEEL_BLK) void k_peel_rounds(PeelArgs a) {
             }
 #pragma unroll
             for (int k = 0; k < SEL_U; k++) pu[k] = u[k] >= 0 ? a.prio[u[k]] : 0;
-            int o0[SEL_U], o1[SEL_U];
 #pragma unroll
             for (int k = 0; k < SEL_U; k++) {
                 const bool fr = u[k] >= 0 && (long long)pu[k] <= thr;
@@ -745,20 +846,20 @@ __global__ __launch_bounds__(PEEL_BLK) void k_peel_rounds(PeelArgs a) {
         unsigned long long fb = s_fbase;
         unsigned int lb = s_lbase;
         for (int base = beg; base < end; base += TILE) {
-            int u[SEL_U], pu[SEL_U];
+            if (!one_tile) {
 #pragma unroll
-            for (int k = 0; k < SEL_U; k++) {
-                const int idx = base + (int)threadIdx.x * SEL_U + k;
-                u[k] = idx < end ? ((r == 0) ? idx : Lin[idx]) : -1;
-            }
+                for (int k = 0; k < SEL_U; k++) {
+                    const int idx = base + (int)threadIdx.x * SEL_U + k;
+                    u[k] = idx < end ? ((r == 0) ? idx : Lin[idx]) : -1;
+                }
 #pragma unroll
-            for (int k = 0; k < SEL_U; k++) pu[k] = u[k] >= 0 ? a.prio[u[k]] : 0;
-            int o0[SEL_U], o1[SEL_U];
+                for (int k = 0; k < SEL_U; k++) pu[k] = u[k] >= 0 ? a.prio[u[k]] : 0;
 #pragma unroll
-            for (int k = 0; k < SEL_U; k++) {
-                const bool fr = u[k] >= 0 && (long long)pu[k] <= thr;
-                o0[k] = fr ? a.off[u[k]] : 0;
-                o1[k] = fr ? a.off[u[k] + 1] : 0;
+                for (int k = 0; k < SEL_U; k++) {
+                    const bool fr = u[k] >= 0 && (long long)pu[k] <= thr;
+                    o0[k] = fr ? a.off[u[k]] : 0;
+                    o1[k] = fr ? a.off[u[k] + 1] : 0;
+                }
             }
             unsigned long long val = 0;
 #pragma unroll
@@ -789,7 +890,7 @@ __global__ __launch_bounds__(PEEL_BLK) void k_peel_rounds(PeelArgs a) {
                         ivr[it] = u[k];
                         a.ie[it] = (int)ed;
                         a.ir[it] = o0[k] - (int)ed;
-                        mark_chunks<PEEL_CH>((long long)ed, (long long)ed + d, (int)it, a.cfirst, a.clast);
+                        mark_chunks<PEEL_MARK>((long long)ed, (long long)ed + d, (int)it, a.cfirst, a.clast);
                         it++;
                         ed += d;
                     }
@@ -805,10 +906,59 @@ __global__ __launch_bounds__(PEEL_BLK) void k_peel_rounds(PeelArgs a) {
         const unsigned long long f = ld_agent_u64(&ctl->fcnt[slot]);
         const int K = (int)(f >> FCNT_SHIFT);
         const long long E = (long long)(f & FCNT_MASK);
-        PeelEdgeOp op{a.st2, a.prio, r, lmin, ctl, &lds.dec};
-        sweep_chunks<PEEL_BLK, PEEL_CH>(K, E, ivr, a.ie, a.ir, a.cfirst, a.clast, a.adj, a.inc, op, lds.sw,
-                                        blockIdx.x, nblocks, &ctl->cnext[slot], &s_chunk);
-        const unsigned int bmin = block_min<PEEL_BLK>(op.lmin, shm);
+        const bool bucket = a.nr > 0 && E >= a.bkt_min_e;
+        PeelEdgeOp op{a.st2, a.prio, r, lmin, ctl, &lds.m.dec, bucket, a.rshift, a.nr, a.n, a.off, a.bkt, a.bfill,
+                      lds.bcnt, lds.bbase};
+        if (E >= a.coarse_min_e)
+            sweep_chunks<PEEL_BLK, PEEL_CH, PEEL_CH / PEEL_MARK>(K, E, ivr, a.ie, a.ir, a.cfirst, a.clast, a.adj,
+                                                                 a.inc, op, lds.m.sw, blockIdx.x, nblocks,
+                                                                 &ctl->cnext[slot], &s_chunk);
+        else
+            sweep_chunks<PEEL_BLK, PEEL_MARK, 1>(K, E, ivr, a.ie, a.ir, a.cfirst, a.clast, a.adj, a.inc, op,
+                                                 lds.m.sw, blockIdx.x, nblocks, &ctl->cnext[slot], &s_chunk);
+        unsigned int rmin = op.lmin;
+        if (bucket) {
+            grid_sync(gs, xid, epoch);
+            // apply: block b owns ranges b, b + grid, ...  It sums its
+            // ranges' bucket entries in a dense LDS histogram and lowers the
+            // priorities with plain read-modify-writes (no other block
+            // touches them until the next grid sync).
+            const int R = 1 << a.rshift;
+            for (int j = blockIdx.x; j < a.nr; j += nblocks) {
+                for (int i = threadIdx.x; i < R; i += PEEL_BLK) lds.dense[i] = 0;
+                const int v0 = j << a.rshift;
+                const int v1 = min(a.n, v0 + R);
+                const int lo = a.off[v0];
+                // a reservation past the range's capacity was refused (and
+                // flagged) but still counted: never read past the range
+                const int cnt = min((int)ld_agent(&a.bfill[j]), a.off[v1] - lo);
+                lds_barrier();
+                for (int i = threadIdx.x; i < cnt; i += PEEL_BLK) {
+                    const unsigned int e = (unsigned int)a.bkt[lo + i];
+                    const unsigned int li = e >> BKT_CNT_BITS;
+                    if (li < (unsigned int)R) atomicAdd(&lds.dense[li], (int)(e & ((1u << BKT_CNT_BITS) - 1)) + 1);
+                }
+                lds_barrier();
+                for (int u = v0 + (int)threadIdx.x; u < v1; u += PEEL_BLK) {
+                    const int c = lds.dense[u - v0];
+                    if (c) {
+                        const int pu = a.prio[u] - c;
+                        a.prio[u] = pu;
+                        rmin = min(rmin, (unsigned int)pu);
+                    }
+                }
+                if (threadIdx.x == 0) a.bfill[j] = 0;  // empty for the next bucketed round
+                lds_barrier();
+            }
+            if ((int)blockIdx.x < a.nr) {
+                // the histogram overwrote the decrement table
+                for (int t = threadIdx.x; t < DEC_SLOTS; t += PEEL_BLK) {
+                    lds.m.dec.key[t] = DEC_EMPTY;
+                    lds.m.dec.cnt[t] = 0;
+                }
+            }
+        }
+        const unsigned int bmin = block_min<PEEL_BLK>(rmin, shm);
         if (threadIdx.x == 0 && bmin != 0xFFFFFFFFu) atomicMin(&ctl->mn[nslot], bmin);
         grid_sync(gs, xid, epoch);
     }
@@ -842,7 +992,7 @@ __global__ __launch_bounds__(SORT_BLK) void k_sweep_sort(SweepArgs a) {
     __shared__ SweepLds<SORT_CH> s;
     __shared__ int spos[SORT_CH];
     SortEdgeOp op{a.pos, a.ctl, spos};
-    sweep_chunks<SORT_BLK, SORT_CH>(a.K, a.E, a.iv, a.ie, a.ir, a.cfirst, a.clast, a.adj, a.inc, op, s, blockIdx.x,
+    sweep_chunks<SORT_BLK, SORT_CH, 1>(a.K, a.E, a.iv, a.ie, a.ir, a.cfirst, a.clast, a.adj, a.inc, op, s, blockIdx.x,
                                     gridDim.x, nullptr, nullptr);
 }
 
@@ -1214,7 +1364,7 @@ __device__ void batch_iteration(const BatchDesc& d, BatchLds<CH>& lds, int* err,
         }
         __syncthreads();
         BatchPeelOp<BLK, 2 * CH> op{d.rnd, d.prio, r, smin, err, &lds.dec};
-        sweep_chunks<BLK, CH>(nitem, nedge, d.iv, d.ie, d.ir, d.cfirst, d.clast, d.adj, d.inc, op, lds.sw, 0, 1,
+        sweep_chunks<BLK, CH, 1>(nitem, nedge, d.iv, d.ie, d.ir, d.cfirst, d.clast, d.adj, d.inc, op, lds.sw, 0, 1,
                               nullptr, nullptr);
         __syncthreads();
         mn = block_min<BLK>(op.lmin, sh32);
@@ -1510,9 +1660,10 @@ static int bits_for(long long maxval) {
     return b;
 }
 
-hipError_t enqueue_iter_peel(const GraphDev& g, int slot, int eps_num, int eps_den, int peel_grid, hipStream_t s,
-                             hipEvent_t ev_a, hipEvent_t ev_b) {
-    k_iter_begin<<<1, 256, 0, s>>>(g.ctl, g.gsync);
+hipError_t enqueue_iter_peel(const GraphDev& g, int slot, int eps_num, int eps_den, int peel_grid,
+                             long long bkt_min_e, long long coarse_min_e, hipStream_t s, hipEvent_t ev_a,
+                             hipEvent_t ev_b) {
+    k_iter_begin<<<1, 256, 0, s>>>(g.ctl, g.gsync, g.bfill, g.nr);
     k_peel_init<<<grid_for(g.n, 256, 2048), 256, 0, s>>>(g.n, g.off, g.load, g.prio, g.rnd, g.inc, g.st2, g.ctl);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -1536,6 +1687,12 @@ hipError_t enqueue_iter_peel(const GraphDev& g, int slot, int eps_num, int eps_d
     a.clast = g.clast;
     a.ctl = g.ctl;
     a.gs = g.gsync;
+    a.bkt = g.bkt;
+    a.bfill = g.bfill;
+    a.rshift = g.rshift;
+    a.nr = g.nr;
+    a.bkt_min_e = bkt_min_e;
+    a.coarse_min_e = coarse_min_e;
     void* args[] = {&a};
     if (ev_a && (e = hipEventRecord(ev_a, s)) != hipSuccess) return e;
     e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_peel_rounds), dim3(peel_grid), dim3(PEEL_BLK), args,
@@ -1552,7 +1709,7 @@ hipError_t enqueue_iter_peel(const GraphDev& g, int slot, int eps_num, int eps_d
 
 hipError_t enqueue_iter_sort(const GraphDev& g, int slot, int key_bits, int sort_grid, hipStream_t s, hipEvent_t ev_a,
                              hipEvent_t ev_b) {
-    k_iter_begin<<<1, 64, 0, s>>>(g.ctl, nullptr);
+    k_iter_begin<<<1, 64, 0, s>>>(g.ctl, nullptr, nullptr, 0);
     int passes = (key_bits + 7) / 8;
     if (passes < 1) passes = 1;
     hipError_t e = enqueue_radix(g, g.load, passes, 0, s);
@@ -1581,7 +1738,7 @@ hipError_t enqueue_iter_sort(const GraphDev& g, int slot, int key_bits, int sort
 }
 
 hipError_t enqueue_iter_seq(const GraphDev& g, int slot, hipStream_t s, hipEvent_t ev_a, hipEvent_t ev_b) {
-    k_iter_begin<<<1, 64, 0, s>>>(g.ctl, nullptr);
+    k_iter_begin<<<1, 64, 0, s>>>(g.ctl, nullptr, nullptr, 0);
     hipError_t e;
     if (ev_a && (e = hipEventRecord(ev_a, s)) != hipSuccess) return e;
     k_seq_order<<<1, SEQ_BLK, sizeof(unsigned int) * (size_t)g.n, s>>>(g.n, g.off, g.adj, g.load, g.order, g.rnd,

@@ -48,8 +48,12 @@ def test_workspace_bytes_host_logic(lib):
     big = dsg.workspace_bytes(4194304, 128312518, 64)
     assert 0 < small < big
     assert big % 256 == 0
-    # state grows linearly in n and nnz: about 18 int32 arrays of n plus chunk maps
-    assert 4194304 * 4 * 16 < big < 4194304 * 4 * 24 + 128312518
+    # state grows linearly in n and nnz: about 18 int32 arrays of n, chunk maps, and the PEEL owner buckets
+    # (one int32 per adjacency entry while n <= 1024 * 16384)
+    assert 4194304 * 4 * 16 + 4 * 128312518 < big < 4194304 * 4 * 24 + 5 * 128312518
+    # beyond 1024 ranges of 16384 ids the bucketed path is off and takes no space
+    huge_n = 1024 * 16384 + 1
+    assert dsg.workspace_bytes(huge_n, 1000, 4) < huge_n * 4 * 24
     with pytest.raises(dsg.DsgError):
         dsg.workspace_bytes(0, 0, 1)
     with pytest.raises(dsg.DsgError):

@@ -197,3 +197,41 @@ def test_guards(dsg, ctx):
     small.run(2, (0, 1), "sort")
     with pytest.raises(dsg.DsgError):
         small.run(1, (0, 1), "sort")
+
+
+def _bucket_cases():
+    ec = edge_cases()
+    cases = {k: ec[k] for k in ["single_vertex", "no_edges_n7", "triangle", "K40", "star_3000", "isolated_mix"]}
+    cases["config1"] = graphgen.config1(6)
+    cases["ragged_4097"] = graphgen.er_planted(11, 4097, 30000, 60, 1, 2)
+    cases["rmat16"] = graphgen.rmat(12, 16, 16 << 16)
+    cases["chunglu_200k"] = graphgen.chunglu(13, 200_000, 2.1, 30.0, 10_000.0)
+    return cases
+
+
+@pytest.mark.parametrize("name", list(_bucket_cases().keys()))
+def test_peel_bucket_paths(dsg, ctx, name):
+    """PEEL round-loop paths against the oracle: owner buckets in every round or in none, and coarse (4096-edge) or
+    fine (1024-edge) sweep chunks in every round.  Covers partial last ranges, empty rounds and isolated vertices."""
+    o, a = _bucket_cases()[name]
+    for eps in [(1, 10), (0, 1)]:
+        ref = oracle.run(o, a, 4, "peel", eps)
+        for bkt, coarse in [(0, 0), (0, 1 << 62), (1 << 62, 0), (1 << 62, 1 << 62)]:
+            log(f"bucket case={name} eps={eps} bucket_min={bkt} coarse_min={coarse}")
+            g = dsg.Graph(ctx, o, a, t_cap=8).set_peel_tuning(bkt, coarse)
+            g.run(4, eps, "peel")
+            assert_same(g, ref, f"bucket/{name}/{eps}/{bkt}/{coarse}")
+            g.close()
+
+
+def test_peel_bucket_more_ranges_than_blocks(dsg, ctx):
+    """n = 5M vertices: 16384-id ranges number 306, more than the round loop's blocks, so blocks apply several
+    ranges per bucketed round."""
+    o, a = graphgen.er_planted(14, 5_000_000, 6_000_000, 60, 1, 2)
+    ref = oracle.run(o, a, 2, "peel", (1, 10))
+    for thr in [0, 1 << 62]:
+        log(f"bucket n=5M threshold={thr}")
+        g = dsg.Graph(ctx, o, a, t_cap=4).set_peel_tuning(thr, thr)
+        g.run(2, (1, 10), "peel")
+        assert_same(g, ref, f"bucket5M/{thr}")
+        g.close()
