@@ -166,8 +166,9 @@ struct alignas(256) GridSync {
     unsigned int pad1[63];
     unsigned int gsize[8];
     unsigned int pad2[56];
+    unsigned int gcnt;           // XCD releases (monotonic)
+    unsigned int pad3[63];
     unsigned int xcnt[8][64];    // arrivals per XCD (monotonic)
-    unsigned int xflag[8][64];   // epoch whose XCD data has been released
 };
 
 __device__ __forceinline__ unsigned int ld_agent(const unsigned int* p) {
@@ -180,48 +181,58 @@ __device__ __forceinline__ void st_agent(unsigned int* p, unsigned int v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Per-block handle of the grid barrier.  Only thread 0 of a block runs the
+// protocol, so only its copy of the counts is meaningful.
+struct GridBarrier {
+    GridSync* gs;
+    unsigned int xid;    // this block's XCD
+    unsigned int gsz;    // blocks of the launch on this XCD
+    unsigned int nx;     // XCDs holding blocks of the launch
+    unsigned int epoch;  // barriers passed in this launch
+};
+
 // Called once at kernel start by every block: count the blocks of each XCD
-// in this launch (the block-to-XCD placement is the hardware's choice).
-__device__ __forceinline__ void grid_sync_init(GridSync* gs, unsigned int nblocks, unsigned int xid) {
+// in this launch (the block-to-XCD placement is the hardware's choice), wait
+// until every block has counted, then keep the counts in registers.
+__device__ __forceinline__ GridBarrier grid_sync_init(GridSync* gs, unsigned int nblocks, unsigned int xid) {
+    GridBarrier b{gs, xid, 0u, 0u, 0u};
     if (threadIdx.x == 0) {
         __hip_atomic_fetch_add(&gs->gsize[xid], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_fetch_add(&gs->started, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         while (ld_agent(&gs->started) < nblocks) __builtin_amdgcn_s_sleep(1);
+        b.gsz = ld_agent(&gs->gsize[xid]);
+        for (int x = 0; x < 8; x++) b.nx += ld_agent(&gs->gsize[x]) != 0u ? 1u : 0u;
     }
     __syncthreads();
+    return b;
 }
 
 // Grid barrier with one L2 write-back per XCD instead of one per block
 // (per-block agent-scope releases dominate the cost of a barrier at 256
 // blocks).  Blocks of an XCD arrive on that XCD's counter after their own
 // stores have completed into the shared L2.  The last arrival of an XCD
-// issues the agent-scope release that writes that L2 back.  It waits for the
-// write-back to finish, then raises the XCD flag.  Block 0 waits for every
-// XCD flag and publishes the epoch.  Every block then performs its own
-// agent-scope acquire (L1 and L2 invalidate, waited for).  `epoch` counts
-// the block's barriers in this launch.
-__device__ __forceinline__ void grid_sync(GridSync* gs, unsigned int xid, unsigned int& epoch) {
+// issues the agent-scope release that writes that L2 back, waits for it,
+// then arrives on the global counter; the arrival that completes the global
+// count publishes the epoch.  Every block then performs its own agent-scope
+// acquire (L1 and L2 invalidate, waited for).
+__device__ __forceinline__ void grid_sync(GridBarrier& b) {
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    epoch++;
+    b.epoch++;
     if (threadIdx.x == 0) {
+        GridSync* gs = b.gs;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __builtin_amdgcn_s_waitcnt(0);
-        const unsigned int gsz = ld_agent(&gs->gsize[xid]);
         const unsigned int a =
-            __hip_atomic_fetch_add(&gs->xcnt[xid][0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (a == epoch * gsz - 1) {
+            __hip_atomic_fetch_add(&gs->xcnt[b.xid][0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (a == b.epoch * b.gsz - 1) {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-            st_agent(&gs->xflag[xid][0], epoch);
+            const unsigned int g =
+                __hip_atomic_fetch_add(&gs->gcnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (g == b.epoch * b.nx - 1) st_agent(&gs->gen, b.epoch);
         }
-        if (blockIdx.x == 0) {
-            for (int x = 0; x < 8; x++)
-                if (ld_agent(&gs->gsize[x]))
-                    while (ld_agent(&gs->xflag[x][0]) < epoch) __builtin_amdgcn_s_sleep(1);
-            st_agent(&gs->gen, epoch);
-        }
-        while (ld_agent(&gs->gen) < epoch) __builtin_amdgcn_s_sleep(1);
+        while (ld_agent(&gs->gen) < b.epoch) __builtin_amdgcn_s_sleep(1);
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     }

@@ -743,15 +743,13 @@ __global__ __launch_bounds__(PEEL_BLK, PEEL_BLOCKS_PER_CU) void k_peel_rounds(Pe
     Ctl* ctl = a.ctl;
     GridSync* gs = a.gs;
     const unsigned int nblocks = gridDim.x;
-    const unsigned int xid = xcd_id();
-    unsigned int epoch = 0;
     const long long q = a.eps_den, p = a.eps_num;
     for (int slot = threadIdx.x; slot < DEC_SLOTS; slot += PEEL_BLK) {
         lds.m.dec.key[slot] = DEC_EMPTY;
         lds.m.dec.cnt[slot] = 0;
     }
     for (int j = threadIdx.x; j < BKT_MAX_NR; j += PEEL_BLK) lds.bcnt[j] = 0;
-    grid_sync_init(gs, nblocks, xid);
+    GridBarrier bar = grid_sync_init(gs, nblocks, xcd_id());
     int prevLc = a.n + 1;
     for (int r = 0;; r++) {
         const int slot = r & 3, nslot = (r + 1) & 3;
@@ -901,7 +899,7 @@ __global__ __launch_bounds__(PEEL_BLK, PEEL_BLOCKS_PER_CU) void k_peel_rounds(Pe
             fb += ((tot >> TITEM_SHIFT) << FCNT_SHIFT) + (tot & 0xFFFFFFFFull);
             lb += (unsigned int)((tot >> TSURV_SHIFT) & TCNT_MASK);
         }
-        grid_sync(gs, xid, epoch);
+        grid_sync(bar);
         // ---------------- sweep
         const unsigned long long f = ld_agent_u64(&ctl->fcnt[slot]);
         const int K = (int)(f >> FCNT_SHIFT);
@@ -918,7 +916,7 @@ __global__ __launch_bounds__(PEEL_BLK, PEEL_BLOCKS_PER_CU) void k_peel_rounds(Pe
                                                  lds.m.sw, blockIdx.x, nblocks, &ctl->cnext[slot], &s_chunk);
         unsigned int rmin = op.lmin;
         if (bucket) {
-            grid_sync(gs, xid, epoch);
+            grid_sync(bar);
             // apply: block b owns ranges b, b + grid, ...  It sums its
             // ranges' bucket entries in a dense LDS histogram and lowers the
             // priorities with plain read-modify-writes (no other block
@@ -960,7 +958,7 @@ __global__ __launch_bounds__(PEEL_BLK, PEEL_BLOCKS_PER_CU) void k_peel_rounds(Pe
         }
         const unsigned int bmin = block_min<PEEL_BLK>(rmin, shm);
         if (threadIdx.x == 0 && bmin != 0xFFFFFFFFu) atomicMin(&ctl->mn[nslot], bmin);
-        grid_sync(gs, xid, epoch);
+        grid_sync(bar);
     }
 }
 
