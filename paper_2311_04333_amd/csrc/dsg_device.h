@@ -14,15 +14,14 @@ constexpr int WAVE = 64;
 // two rounds ahead of its use, so no round reads a slot that another round
 // is still writing.
 struct alignas(256) Ctl {
-    unsigned int pad0[4];
-    // per-round ring: minimum priority, survivor count, packed frontier
-    // counter (items << 38 | edges)
-    unsigned int mn[4];
-    unsigned int lcnt[4];
-    unsigned long long fcnt[4];
-    unsigned int cnext[4];  // next sweep chunk to hand out, per round
+    // per-round rings (slot = round mod 4), each counter array on its own
+    // cache line: every block updates them with atomics
+    alignas(128) unsigned int mn[4];          // minimum priority bid for the round
+    alignas(128) unsigned int lcnt[4];        // survivor count
+    alignas(128) unsigned long long fcnt[4];  // frontier items << 38 | frontier edges
+    alignas(128) unsigned int cnext[4];       // next sweep chunk to hand out
     // results of the current iteration
-    int nrounds;
+    alignas(128) int nrounds;
     int improved;
     int iters_done;
     int best_iter;
