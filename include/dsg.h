@@ -79,7 +79,7 @@ dsg_status dsg_ctx_destroy(dsg_ctx* ctx);
 
 /* Bytes of workspace a graph of n vertices and nnz CSR entries needs, with
  * room for t_cap recorded iterations (per-iteration densities and digests).
- * n >= 1, 0 <= nnz < 2^31, t_cap >= 1. */
+ * n >= 1, 0 <= nnz <= 2^31 - 2^16 (int32 edge positions with a chunk of headroom), t_cap >= 1. */
 dsg_status dsg_workspace_bytes(int32_t n, int64_t nnz, int32_t t_cap, int64_t* bytes);
 
 /* Bind a CSR already resident on the device.  d_workspace must be 256-byte
@@ -187,7 +187,7 @@ typedef struct {
     const int32_t* d_adj;     /* nnz entries, device */
     int32_t n;                /* >= 1 */
     int32_t T;                /* iterations each dsg_batch_run appends (>= 0) */
-    int64_t nnz;              /* [0, 2^31) */
+    int64_t nnz;              /* [0, 2^31 - 2^16] */
     int32_t eps_num;          /* eps = eps_num / eps_den, eps_num >= 0 */
     int32_t eps_den;          /* >= 1 */
 } dsg_batch_graph;

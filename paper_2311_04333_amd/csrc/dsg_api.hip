@@ -234,7 +234,7 @@ dsg_status dsg_ctx_destroy(dsg_ctx* ctx) {
 dsg_status dsg_workspace_bytes(int32_t n, int64_t nnz, int32_t t_cap, int64_t* bytes) {
     if (!bytes) return fail(DSG_EINVAL, "bytes is NULL");
     if (n < 1) return fail(DSG_EINVAL, "n must be >= 1");
-    if (nnz < 0 || nnz >= (1LL << 31)) return fail(DSG_EINVAL, "nnz must be in [0, 2^31)");
+    if (nnz < 0 || nnz > dsg::MAX_NNZ) return fail(DSG_EINVAL, "nnz must be in [0, 2^31 - 2^16]");
     if (t_cap < 1) return fail(DSG_EINVAL, "t_cap must be >= 1");
     *bytes = carve(n, nnz, t_cap, nullptr, nullptr);
     return DSG_OK;
@@ -246,7 +246,7 @@ dsg_status dsg_graph_create(dsg_ctx* ctx, int32_t n, int64_t nnz, const int32_t*
     if (!ctx || !out || !d_offsets || !d_workspace) return fail(DSG_EINVAL, "NULL argument");
     *out = nullptr;
     if (n < 1) return fail(DSG_EINVAL, "n must be >= 1");
-    if (nnz < 0 || nnz >= (1LL << 31)) return fail(DSG_EINVAL, "nnz must be in [0, 2^31)");
+    if (nnz < 0 || nnz > dsg::MAX_NNZ) return fail(DSG_EINVAL, "nnz must be in [0, 2^31 - 2^16]");
     if (nnz > 0 && !d_adj) return fail(DSG_EINVAL, "adj is NULL");
     if (t_cap < 1) return fail(DSG_EINVAL, "t_cap must be >= 1");
     if (reinterpret_cast<uintptr_t>(d_workspace) % 256 != 0) return fail(DSG_EINVAL, "workspace not 256-byte aligned");
@@ -280,11 +280,8 @@ dsg_status dsg_graph_create(dsg_ctx* ctx, int32_t n, int64_t nnz, const int32_t*
     if ((e = dsg::launch_check_range(g->d, s)) != hipSuccess) return bail(hip_fail(e, "check range"));
     st = check_errors(g, "entries");
     if (st != DSG_OK) return bail(st);
-    if (flags & DSG_VALIDATE) {
-        if ((e = dsg::launch_check_rows(g->d, s)) != hipSuccess) return bail(hip_fail(e, "check rows"));
-        st = check_errors(g, "rows");
-        if (st != DSG_OK) return bail(st);
-    }
+    // offsets and entries are in range now, so the static item list (which
+    // the row check walks) can be built
     if ((e = dsg::launch_build_static_items(g->d, s)) != hipSuccess) return bail(hip_fail(e, "static items"));
     dsg::Ctl c;
     st = read_ctl(g, &c);
@@ -294,6 +291,11 @@ dsg_status dsg_graph_create(dsg_ctx* ctx, int32_t n, int64_t nnz, const int32_t*
         return bail(hip_fail(e, "hipMemcpy(items)"));
     g->d.n_items = (int)items;
     g->d.max_deg = c.max_deg;
+    if (flags & DSG_VALIDATE) {
+        if ((e = dsg::launch_check_rows(g->d, s)) != hipSuccess) return bail(hip_fail(e, "check rows"));
+        st = check_errors(g, "rows");
+        if (st != DSG_OK) return bail(st);
+    }
     if ((e = dsg::launch_reset_state(g->d, s)) != hipSuccess) return bail(hip_fail(e, "reset"));
     if ((e = hipEventCreate(&g->ev0)) != hipSuccess) return bail(hip_fail(e, "hipEventCreate"));
     if ((e = hipEventCreate(&g->ev1)) != hipSuccess) {
@@ -600,7 +602,7 @@ dsg_status dsg_batch_workspace_bytes(const dsg_batch_graph* graphs, int32_t coun
     if (!graphs || !bytes || count < 1) return fail(DSG_EINVAL, "need graphs, count >= 1 and bytes");
     if (t_cap < 1) return fail(DSG_EINVAL, "t_cap must be >= 1");
     for (int g = 0; g < count; g++)
-        if (graphs[g].n < 1 || graphs[g].nnz < 0 || graphs[g].nnz >= (1LL << 31))
+        if (graphs[g].n < 1 || graphs[g].nnz < 0 || graphs[g].nnz > dsg::MAX_NNZ)
             return fail(DSG_EINVAL, "graph " + std::to_string(g) + ": bad n or nnz");
     *bytes = carve_batch(graphs, count, t_cap, nullptr, nullptr);
     return DSG_OK;
@@ -614,7 +616,7 @@ dsg_status dsg_batch_create(dsg_ctx* ctx, const dsg_batch_graph* graphs, int32_t
     if (reinterpret_cast<uintptr_t>(d_workspace) % 256 != 0) return fail(DSG_EINVAL, "workspace not 256-byte aligned");
     for (int g = 0; g < count; g++) {
         const dsg_batch_graph& x = graphs[g];
-        if (x.n < 1 || x.nnz < 0 || x.nnz >= (1LL << 31) || !x.d_offsets || (x.nnz > 0 && !x.d_adj))
+        if (x.n < 1 || x.nnz < 0 || x.nnz > dsg::MAX_NNZ || !x.d_offsets || (x.nnz > 0 && !x.d_adj))
             return fail(DSG_EINVAL, "graph " + std::to_string(g) + ": bad n, nnz or pointers");
         if (x.T < 0 || x.eps_num < 0 || x.eps_den < 1)
             return fail(DSG_EINVAL, "graph " + std::to_string(g) + ": bad T or eps");
@@ -924,7 +926,7 @@ struct dsg_server {
 extern "C" {
 
 dsg_status dsg_server_footprint(int32_t n, int64_t nnz, int32_t T, int64_t* bytes) {
-    if (!bytes || n < 1 || nnz < 0 || nnz >= (1LL << 31) || T < 1) return fail(DSG_EINVAL, "bad arguments");
+    if (!bytes || n < 1 || nnz < 0 || nnz > dsg::MAX_NNZ || T < 1) return fail(DSG_EINVAL, "bad arguments");
     *bytes = serve_footprint(n, nnz, T);
     return DSG_OK;
 }
@@ -1066,7 +1068,7 @@ extern "C" {
 dsg_status dsg_server_submit(dsg_server* s, const int32_t* h_off, const int32_t* h_adj, int32_t n, int64_t nnz,
                              int32_t T, int32_t eps_num, int32_t eps_den, uint64_t* ticket) {
     if (!s || !h_off || !ticket || (nnz > 0 && !h_adj)) return fail(DSG_EINVAL, "NULL argument");
-    if (n < 1 || nnz < 0 || nnz >= (1LL << 31)) return fail(DSG_EINVAL, "bad n or nnz");
+    if (n < 1 || nnz < 0 || nnz > dsg::MAX_NNZ) return fail(DSG_EINVAL, "bad n or nnz");
     if (n >= dsg::PEEL_MAX_N) return fail(DSG_EINVAL, "n too large");
     // memory-safety checks of the CSR on the host: offsets and entry range
     if (h_off[0] != 0 || (long long)h_off[n] != nnz) return fail(DSG_EINVAL, "offsets[0] != 0 or offsets[n] != nnz");
@@ -1098,7 +1100,7 @@ dsg_status dsg_server_submit(dsg_server* s, const int32_t* h_off, const int32_t*
 dsg_status dsg_server_register(dsg_server* s, const int32_t* d_offsets, const int32_t* d_adj, int32_t n, int64_t nnz,
                                int32_t flags, int32_t* graph_id) {
     if (!s || !d_offsets || !graph_id || (nnz > 0 && !d_adj)) return fail(DSG_EINVAL, "NULL argument");
-    if (n < 1 || nnz < 0 || nnz >= (1LL << 31) || n >= dsg::PEEL_MAX_N) return fail(DSG_EINVAL, "bad n or nnz");
+    if (n < 1 || nnz < 0 || nnz > dsg::MAX_NNZ || n >= dsg::PEEL_MAX_N) return fail(DSG_EINVAL, "bad n or nnz");
     if (s->running) return fail(DSG_ESTATE, "register graphs before dsg_server_start");
     // device checks with the single-graph check kernels, on the copy stream;
     // the control block sits in the pool's reserved header

@@ -24,6 +24,9 @@ constexpr int MIN_CH = PEEL_MARK < SORT_CH ? PEEL_MARK : SORT_CH;  // finest chu
 constexpr int SEQ_BLK = 1024;      // threads of the single SEQ block
 constexpr int SEQ_MAX_N = 16000;   // SEQ keeps n priorities in LDS (< 64 KB)
 constexpr int PEEL_MAX_N = 1 << 26;  // frontier item counter has 26 bits
+// Adjacency entries are indexed with int32, and a sweep chunk's edge
+// positions (start + up to 4096) must stay below 2^31 as well.
+constexpr long long MAX_NNZ = (1LL << 31) - (1LL << 16);
 // Owner-bucketed decrements of the PEEL round loop: vertex ids are split into
 // ranges of 2^shift ids (shift <= BKT_MAX_SHIFT, so a range's counters fit a
 // dense LDS histogram), at most BKT_MAX_NR ranges.  Larger graphs keep the

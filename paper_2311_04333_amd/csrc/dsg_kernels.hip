@@ -65,31 +65,68 @@ __global__ void k_check_range(int n, long long nnz, const int* __restrict__ adj,
 }
 
 // Full CSR check (DSG_VALIDATE): no self-loops, rows strictly increasing,
-// symmetric (u in row v  =>  v in row u, by binary search).
-__global__ void k_check_rows(int n, const int* __restrict__ off, const int* __restrict__ adj, Ctl* ctl) {
-    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
-        int a = off[v], b = off[v + 1];
-        int code = ERR_NONE;
-        for (int e = a; e < b && code == ERR_NONE; e++) {
-            int u = adj[e];
-            if (u == v) code = ERR_SELF_LOOP;
-            else if (e > a && adj[e - 1] >= u) code = ERR_ROW_ORDER;
-            else {
-                int lo = off[u], hi = off[u + 1] - 1;
+// symmetric (u in row v  =>  v in row u, by binary search in row u).
+// Edge-parallel over the static item list (every vertex with edges, in id
+// order, so the concatenated edge index is the adjacency index): a block
+// stages one chunk's items in LDS and each thread finds its edges' rows by
+// binary search, so hub rows are spread over many threads.
+__global__ __launch_bounds__(SORT_BLK) void k_check_rows(long long nnz, int K, const int* __restrict__ siv,
+                                                         const int* __restrict__ sie, const int* __restrict__ scf,
+                                                         const int* __restrict__ scl, const int* __restrict__ off,
+                                                         const int* __restrict__ adj, Ctl* ctl) {
+    __shared__ int fe[SORT_CH];
+    __shared__ int vv[SORT_CH];
+    const long long nchunks = (nnz + SORT_CH - 1) / SORT_CH;
+    for (long long c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        const long long x0 = c * SORT_CH, x1 = min(nnz, x0 + SORT_CH);
+        const int k0 = scf[c];
+        const int k1 = (c + 1 < nchunks) ? scl[c] : K - 1;
+        const int nitems = k1 - k0 + 1;
+        if (nitems < 1 || nitems > SORT_CH) {  // the item list is built from checked offsets
+            if (threadIdx.x == 0) {
+                atomicAdd(&ctl->err_count, 1);
+                ctl->err_code = ERR_INTERNAL;
+            }
+            return;
+        }
+        for (int j = threadIdx.x; j < nitems; j += SORT_BLK) {
+            fe[j] = sie[k0 + j];
+            vv[j] = siv[k0 + j];
+        }
+        __syncthreads();
+        for (long long x = x0 + threadIdx.x; x < x1; x += SORT_BLK) {
+            int lo = 0, hi = nitems - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (fe[mid] <= x) lo = mid; else hi = mid - 1;
+            }
+            const int v = vv[lo];
+            const int u = adj[x];
+            int code = ERR_NONE;
+            if (u == v) {
+                code = ERR_SELF_LOOP;
+            } else if (x > fe[lo] && adj[x - 1] >= u) {
+                code = ERR_ROW_ORDER;
+            } else {
+                int l = off[u], h = off[u + 1] - 1;
                 bool found = false;
-                while (lo <= hi) {
-                    int mid = (lo + hi) >> 1;
-                    int w = adj[mid];
-                    if (w == v) { found = true; break; }
-                    if (w < v) lo = mid + 1; else hi = mid - 1;
+                while (l <= h) {
+                    const int mid = l + ((h - l) >> 1);  // l + h can pass 2^31 when nnz > 2^30
+                    const int w = adj[mid];
+                    if (w == v) {
+                        found = true;
+                        break;
+                    }
+                    if (w < v) l = mid + 1; else h = mid - 1;
                 }
                 if (!found) code = ERR_ASYMMETRIC;
             }
+            if (code != ERR_NONE && atomicAdd(&ctl->err_count, 1) == 0) {
+                ctl->err_code = code;
+                ctl->err_vertex = v;
+            }
         }
-        if (code != ERR_NONE && atomicAdd(&ctl->err_count, 1) == 0) {
-            ctl->err_code = code;
-            ctl->err_vertex = v;
-        }
+        __syncthreads();
     }
 }
 
@@ -1595,7 +1632,11 @@ hipError_t launch_check_range(const GraphDev& g, hipStream_t s) {
 }
 
 hipError_t launch_check_rows(const GraphDev& g, hipStream_t s) {
-    k_check_rows<<<grid_for(g.n, 256), 256, 0, s>>>(g.n, g.off, g.adj, g.ctl);
+    // needs the static item list (launch_build_static_items) and n_items
+    if (g.nnz == 0) return hipSuccess;
+    const long long nchunks = (g.nnz + SORT_CH - 1) / SORT_CH;
+    const int grid = (int)(nchunks < 8192 ? nchunks : 8192);
+    k_check_rows<<<grid, SORT_BLK, 0, s>>>(g.nnz, g.n_items, g.siv, g.sie, g.scf, g.scl, g.off, g.adj, g.ctl);
     return hipGetLastError();
 }
 

@@ -58,6 +58,10 @@ def test_workspace_bytes_host_logic(lib):
         dsg.workspace_bytes(0, 0, 1)
     with pytest.raises(dsg.DsgError):
         dsg.workspace_bytes(10, 1 << 31, 1)
+    # int32 edge positions keep one sweep chunk of headroom below 2^31
+    assert dsg.workspace_bytes(10, (1 << 31) - (1 << 16), 1) > 0
+    with pytest.raises(dsg.DsgError):
+        dsg.workspace_bytes(10, (1 << 31) - (1 << 16) + 1, 1)
 
 
 def test_eps_parsing_is_exact():
