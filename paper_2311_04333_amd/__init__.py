@@ -50,6 +50,7 @@ SIGNATURES = [
     ("dsg_graph_destroy", ctypes.c_int, [_P]),
     ("dsg_last_run_ms", ctypes.c_int, [_P, _P]),
     ("dsg_set_peel_tuning", ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int64]),
+    ("dsg_set_sort_tuning", ctypes.c_int, [_P, _I32]),
     ("dsg_set_kernel_timing", ctypes.c_int, [_P, _I32]),
     ("dsg_get_kernel_timing", ctypes.c_int, [_P, _P, _P]),
     ("dsg_batch_workspace_bytes", ctypes.c_int, [_P, _I32, _I32, _P]),
@@ -243,6 +244,12 @@ class Graph:
         """PEEL round-loop tuning (results do not depend on it): frontier sizes (adjacency entries) from which a
         round applies decrements through owner buckets, and from which it sweeps coarse chunks; -1 = default."""
         _check(library().dsg_set_peel_tuning(self._h, int(bucket_min_edges), int(coarse_min_edges)))
+        return self
+
+    def set_sort_tuning(self, coarse_ranks: int = -1):
+        """SORT sweep tuning (results do not depend on it): coarse position classes first; -1 = by size, 0 = off,
+        1 = on."""
+        _check(library().dsg_set_sort_tuning(self._h, int(coarse_ranks)))
         return self
 
     def set_kernel_timing(self, enable: bool = True):

@@ -44,6 +44,7 @@ struct dsg_graph {
     int klaunches;                 // timed launches of the last dsg_run
     long long bkt_min_e;           // PEEL rounds with at least this many frontier edges use owner buckets
     long long coarse_min_e;        // ... and coarse sweep chunks; -1 = default
+    int sort_coarse;               // SORT coarse ranks: -1 = by size, 0 = off, 1 = on
 };
 
 struct dsg_batch {
@@ -117,7 +118,11 @@ long long carve(int n, long long nnz, int t_cap, char* base, GraphDev* g) {
     long long o_rd = L.add(4LL * t_cap), o_dg = L.add(8LL * t_cap);
     const int rshift = dsg::bucket_shift(N);
     long long o_bkt = L.add(rshift >= 0 ? 4 * nnz : 0), o_bf = L.add(4 * dsg::BKT_MAX_NR);
+    long long o_cb = L.add(4 * ((N + 7) / 8 + 1)), o_crb = L.add(4 * 16), o_crs = L.add(4 * (1 << 17));
     if (base && g) {
+        g->cr_samp = reinterpret_cast<int*>(base + o_crs);
+        g->cb = reinterpret_cast<unsigned int*>(base + o_cb);
+        g->cr_bounds = reinterpret_cast<int*>(base + o_crb);
         g->rshift = rshift >= 0 ? rshift : 0;
         g->nr = rshift >= 0 ? (int)((N + (1LL << rshift) - 1) >> rshift) : 0;
         g->bkt = reinterpret_cast<int*>(base + o_bkt);
@@ -262,6 +267,7 @@ dsg_status dsg_graph_create(dsg_ctx* ctx, int32_t n, int64_t nnz, const int32_t*
     g->last_variant = -1;
     g->bkt_min_e = dsg::BKT_DEFAULT_MIN_E;
     g->coarse_min_e = -1;
+    g->sort_coarse = -1;
     g->d.n = n;
     g->d.nnz = nnz;
     g->d.off = d_offsets;
@@ -346,7 +352,9 @@ dsg_status dsg_run(dsg_graph* g, int32_t T, int32_t eps_num, int32_t eps_den, ds
             long long bound = (long long)(g->iters_done + t) * (long long)g->d.max_deg;
             int bits = 0;
             while (bits < 31 && (bound >> bits) != 0) bits++;
-            e = dsg::enqueue_iter_sort(g->d, slot, bits, g->ctx->sort_grid, s, ea, eb);
+            const bool coarse = g->sort_coarse > 0 ||
+                                (g->sort_coarse < 0 && g->d.n >= dsg::SORT_COARSE_MIN_N && g->d.n <= dsg::SORT_COARSE_MAX_N);
+            e = dsg::enqueue_iter_sort(g->d, slot, bits, g->ctx->sort_grid, coarse && g->d.n < (1 << 26), s, ea, eb);
         } else {
             e = dsg::enqueue_iter_seq(g->d, slot, s, ea, eb);
         }
@@ -395,6 +403,13 @@ dsg_status dsg_set_peel_tuning(dsg_graph* g, int64_t bucket_min_edges, int64_t c
     if (bucket_min_edges < -1 || coarse_min_edges < -1) return fail(DSG_EINVAL, "thresholds must be >= -1");
     g->bkt_min_e = bucket_min_edges >= 0 ? bucket_min_edges : dsg::BKT_DEFAULT_MIN_E;
     g->coarse_min_e = coarse_min_edges;
+    return DSG_OK;
+}
+
+dsg_status dsg_set_sort_tuning(dsg_graph* g, int32_t coarse_ranks) {
+    if (!g) return fail(DSG_EINVAL, "graph is NULL");
+    if (coarse_ranks < -1 || coarse_ranks > 1) return fail(DSG_EINVAL, "coarse_ranks must be -1, 0 or 1");
+    g->sort_coarse = coarse_ranks;
     return DSG_OK;
 }
 

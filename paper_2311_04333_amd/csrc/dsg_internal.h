@@ -36,6 +36,10 @@ constexpr int BKT_MAX_SHIFT = 14;
 constexpr int BKT_MAX_NR = 1024;
 constexpr int BKT_CNT_BITS = 12;  // bucket entry = local id << 12 | (count - 1); count <= PEEL_CH
 constexpr long long BKT_DEFAULT_MIN_E = 1LL << 20;
+// SORT compares coarse ranks first when the 4-bit table (n/2 bytes) fits an
+// XCD's L2 comfortably and the position table (4n bytes) does not
+constexpr int SORT_COARSE_MIN_N = 1 << 19;
+constexpr int SORT_COARSE_MAX_N = 1 << 22;
 static_assert((1 << BKT_CNT_BITS) >= 4096, "chunk-local counts must fit the entry's count field");
 // Range shift for n vertices, or -1 when the graph is too large for the
 // bucketed path: the smallest shift >= 8 giving at most 256 ranges, capped
@@ -88,6 +92,7 @@ struct SweepArgs {
     const int* adj;
     int* inc;
     const int* pos;
+    const unsigned int* cb;  // SORT coarse ranks (4 bits per vertex) or null
     Ctl* ctl;
 };
 
@@ -137,6 +142,9 @@ struct GraphDev {
     unsigned int* bfill;
     int rshift;
     int nr;
+    unsigned int* cb;  // SORT coarse ranks
+    int* cr_bounds;    // first position of each coarse class
+    int* cr_samp;      // degrees at the sampled positions
     int n_items;  // vertices with degree > 0
     int max_deg;
 };
@@ -155,8 +163,8 @@ hipError_t launch_zero_ctl(const GraphDev& g, hipStream_t s);
 hipError_t enqueue_iter_peel(const GraphDev& g, int slot, int eps_num, int eps_den, int peel_grid,
                              long long bkt_min_e, long long coarse_min_e, hipStream_t s, hipEvent_t ev_a,
                              hipEvent_t ev_b);
-hipError_t enqueue_iter_sort(const GraphDev& g, int slot, int key_bits, int sort_grid, hipStream_t s, hipEvent_t ev_a,
-                             hipEvent_t ev_b);
+hipError_t enqueue_iter_sort(const GraphDev& g, int slot, int key_bits, int sort_grid, bool coarse, hipStream_t s,
+                             hipEvent_t ev_a, hipEvent_t ev_b);
 hipError_t enqueue_iter_seq(const GraphDev& g, int slot, hipStream_t s, hipEvent_t ev_a, hipEvent_t ev_b);
 
 // One graph of a batch: its CSR and every per-graph array, carved from the

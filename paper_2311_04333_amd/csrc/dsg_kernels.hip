@@ -498,6 +498,7 @@ __device__ __forceinline__ void sweep_chunks(int K, long long E, const int* __re
         }
 #pragma unroll
         for (int e = 0; e < EPT; e++) st[e] = jj[e] >= 0 ? op.gather(uu[e]) : 0;
+        op.template resolve<EPT>(jj, uu, st);
         bool hit[EPT];
 #pragma unroll
         for (int e = 0; e < EPT; e++) hit[e] = jj[e] >= 0 && op.edge(s.v[jj[e]], uu[e], st[e], jj[e]);
@@ -647,6 +648,8 @@ struct PeelEdgeOp {
     }
     __device__ __forceinline__ void stage_item(int, int) {}
     __device__ __forceinline__ int gather(int u) const { return st2_get(st2, u); }
+    template <int EPT>
+    __device__ __forceinline__ void resolve(const int (&)[EPT], const int (&)[EPT], int (&)[EPT]) const {}
     __device__ __forceinline__ bool edge(int v, int u, int su, int) {
         if (su == 1) {
             unsigned int h = ((unsigned int)u * 0x9E3779B1u) >> (32 - __builtin_ctz(DEC_SLOTS));
@@ -1000,33 +1003,136 @@ __global__ __launch_bounds__(PEEL_BLK, PEEL_BLOCKS_PER_CU) void k_peel_rounds(Pe
 }
 
 // ============================================================== SORT
-// pos[order[i]] = i (kept in rnd[], which is the "round" of SORT), charge 0.
-__global__ void k_sort_pos(int n, const int* __restrict__ order, int* __restrict__ rnd, int* __restrict__ inc) {
+// Coarse ranks: 16 position classes of about equal degree mass, as 4-bit
+// codes packed 8 to a word and indexed by vertex (n/2 bytes, so a 4M-vertex
+// table stays in each XCD's L2).  The class is non-decreasing in the
+// position, so different classes order two vertices; only equal classes
+// need the full positions.  The class bounds come from every 2^k-th
+// position of the order (the smallest k leaving at most 2^17 samples): the
+// degree mass of the sampled vertices is prefix-summed and class c starts at
+// the first sample whose running mass reaches c/16 of the total (a sampling
+// error only costs more ties).
+constexpr int CR_MAX_SAMPLES = 1 << 17;
+constexpr int CR_CLASSES = 16;
+__host__ __device__ inline int cr_shift(int n) {
+    int k = 0;
+    while (((long long)n + (1LL << k) - 1) >> k > CR_MAX_SAMPLES) k++;
+    return k;
+}
+constexpr int CR_POS_BITS = 28;  // staged word: class << 28 | position (n < 2^26)
+
+// pos[order[i]] = i (kept in rnd[], which is the "round" of SORT), charge 0;
+// with `sdeg`, also the degree of the vertex at each sampled position.
+__global__ void k_sort_pos(int n, const int* __restrict__ order, int* __restrict__ rnd, int* __restrict__ inc,
+                           const int* __restrict__ off, int* __restrict__ sdeg, int sshift) {
+    const int smask = (1 << sshift) - 1;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        rnd[order[i]] = i;
+        const int v = order[i];
+        rnd[v] = i;
         inc[i] = 0;
+        if (sdeg && (i & smask) == 0) sdeg[i >> sshift] = off[v + 1] - off[v];
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_coarse_bounds(int n, int sshift, const int* __restrict__ sdeg,
+                                                        int* __restrict__ bounds) {
+    __shared__ long long sh[1024 / WAVE];
+    constexpr int PER = CR_MAX_SAMPLES / 1024;
+    const int S = (int)(((long long)n + (1LL << sshift) - 1) >> sshift);
+    const int s0 = (int)threadIdx.x * PER;
+    long long mine = 0;
+    for (int k = 0; k < PER; k++)
+        if (s0 + k < S) mine += sdeg[s0 + k];
+    long long tot;
+    long long run = block_excl_scan<1024>(mine, &tot, sh);
+    if (threadIdx.x < CR_CLASSES) bounds[threadIdx.x] = threadIdx.x == 0 ? 0 : n;
+    __syncthreads();
+    if (tot == 0) return;
+    long long th[CR_CLASSES];
+#pragma unroll
+    for (int c = 1; c < CR_CLASSES; c++) th[c] = (tot * c) / CR_CLASSES;
+    for (int k = 0; k < PER && s0 + k < S; k++) {
+        const long long d = sdeg[s0 + k];
+        // classes whose threshold lies in (run, run + d]: exactly one sample
+        // crosses each threshold, since the running mass only grows
+#pragma unroll
+        for (int c = 1; c < CR_CLASSES; c++)
+            if (run < th[c] && th[c] <= run + d) bounds[c] = (s0 + k) << sshift;
+        run += d;
+    }
+}
+
+__global__ void k_coarse_pack(int n, const int* __restrict__ pos, const int* __restrict__ bounds,
+                              unsigned int* __restrict__ cb) {
+    int b[CR_CLASSES];
+#pragma unroll
+    for (int c = 0; c < CR_CLASSES; c++) b[c] = bounds[c];
+    const int words = (n + 7) / 8;
+    for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < words; w += gridDim.x * blockDim.x) {
+        unsigned int word = 0;
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+            const int v = w * 8 + k;
+            if (v < n) {
+                const int p = pos[v];
+                unsigned int cls = 0;
+#pragma unroll
+                for (int c = 1; c < CR_CLASSES; c++) cls += p >= b[c] ? 1u : 0u;
+                word |= cls << (4 * k);
+            }
+        }
+        cb[w] = word;
     }
 }
 
 struct SortEdgeOp {
     const int* pos;
+    const unsigned int* cb;  // coarse ranks, or null (compare positions directly)
     Ctl* ctl;
-    int* spos;  // LDS: position of each staged item
+    int* spos;  // LDS: per staged item, its position (and class << 28 with coarse ranks)
     __device__ void flag_error() {
         atomicAdd(&ctl->err_count, 1);
         ctl->err_code = ERR_INTERNAL;
     }
-    __device__ __forceinline__ void stage_item(int j, int v) { spos[j] = pos[v]; }
-    __device__ __forceinline__ int gather(int u) const { return pos[u]; }
-    // the edge is charged to v when v comes first in the order
-    __device__ __forceinline__ bool edge(int, int, int pu, int j) const { return pu > spos[j]; }
+    __device__ __forceinline__ int cls(int u) const { return (int)((cb[u >> 3] >> ((u & 7) * 4)) & 15u); }
+    __device__ __forceinline__ void stage_item(int j, int v) {
+        spos[j] = cb ? (int)(((unsigned int)cls(v) << CR_POS_BITS) | (unsigned int)pos[v]) : pos[v];
+    }
+    __device__ __forceinline__ int gather(int u) const { return cb ? cls(u) : pos[u]; }
+    // st becomes 1 when u comes after v (the edge is charged to v), else 0;
+    // with coarse ranks only the equal-class edges load u's position, all
+    // of a thread's at once
+    template <int EPT>
+    __device__ __forceinline__ void resolve(const int (&jj)[EPT], const int (&uu)[EPT], int (&st)[EPT]) const {
+        if (cb) {
+            bool tie[EPT];
+            int pu[EPT];
+#pragma unroll
+            for (int e = 0; e < EPT; e++)
+                tie[e] = jj[e] >= 0 && st[e] == (int)((unsigned int)spos[jj[e]] >> CR_POS_BITS);
+#pragma unroll
+            for (int e = 0; e < EPT; e++) pu[e] = tie[e] ? pos[uu[e]] : 0;
+#pragma unroll
+            for (int e = 0; e < EPT; e++) {
+                if (jj[e] < 0) continue;
+                const unsigned int sv = (unsigned int)spos[jj[e]];
+                st[e] = tie[e] ? (pu[e] > (int)(sv & ((1u << CR_POS_BITS) - 1)) ? 1 : 0)
+                               : (st[e] > (int)(sv >> CR_POS_BITS) ? 1 : 0);
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < EPT; e++)
+                if (jj[e] >= 0) st[e] = st[e] > spos[jj[e]] ? 1 : 0;
+        }
+    }
+    __device__ __forceinline__ bool edge(int, int, int later, int) const { return later != 0; }
     __device__ __forceinline__ void flush_chunk() {}
 };
 
 __global__ __launch_bounds__(SORT_BLK) void k_sweep_sort(SweepArgs a) {
     __shared__ SweepLds<SORT_CH> s;
     __shared__ int spos[SORT_CH];
-    SortEdgeOp op{a.pos, a.ctl, spos};
+    SortEdgeOp op{a.pos, a.cb, a.ctl, spos};
     sweep_chunks<SORT_BLK, SORT_CH, 1>(a.K, a.E, a.iv, a.ie, a.ir, a.cfirst, a.clast, a.adj, a.inc, op, s, blockIdx.x,
                                     gridDim.x, nullptr, nullptr);
 }
@@ -1264,6 +1370,8 @@ struct BatchPeelOp {
     __device__ void flag_error() { atomicAdd(err, 1); }
     __device__ __forceinline__ void stage_item(int, int) {}
     __device__ __forceinline__ int gather(int u) const { return rnd[u]; }
+    template <int EPT>
+    __device__ __forceinline__ void resolve(const int (&)[EPT], const int (&)[EPT], int (&)[EPT]) const {}
     __device__ __forceinline__ bool edge(int v, int u, int ru, int) {
         if (ru < 0) {
             unsigned int h = ((unsigned int)u * 0x9E3779B1u) >> (32 - __builtin_ctz(SLOTS));
@@ -1746,14 +1854,21 @@ hipError_t enqueue_iter_peel(const GraphDev& g, int slot, int eps_num, int eps_d
     return enqueue_alg3(g, slot, 0, s);
 }
 
-hipError_t enqueue_iter_sort(const GraphDev& g, int slot, int key_bits, int sort_grid, hipStream_t s, hipEvent_t ev_a,
-                             hipEvent_t ev_b) {
+hipError_t enqueue_iter_sort(const GraphDev& g, int slot, int key_bits, int sort_grid, bool coarse, hipStream_t s,
+                             hipEvent_t ev_a, hipEvent_t ev_b) {
     k_iter_begin<<<1, 64, 0, s>>>(g.ctl, nullptr, nullptr, 0);
     int passes = (key_bits + 7) / 8;
     if (passes < 1) passes = 1;
     hipError_t e = enqueue_radix(g, g.load, passes, 0, s);
     if (e != hipSuccess) return e;
-    k_sort_pos<<<grid_for(g.n, 256, 2048), 256, 0, s>>>(g.n, g.order, g.rnd, g.inc);
+    coarse = coarse && g.nnz > 0;
+    const int sshift = cr_shift(g.n);
+    k_sort_pos<<<grid_for(g.n, 256, 2048), 256, 0, s>>>(g.n, g.order, g.rnd, g.inc, g.off,
+                                                         coarse ? g.cr_samp : nullptr, sshift);
+    if (coarse) {
+        k_coarse_bounds<<<1, 1024, 0, s>>>(g.n, sshift, g.cr_samp, g.cr_bounds);
+        k_coarse_pack<<<grid_for((g.n + 7) / 8, 256, 2048), 256, 0, s>>>(g.n, g.rnd, g.cr_bounds, g.cb);
+    }
     SweepArgs a{};
     a.K = g.n_items;
     a.E = g.nnz;
@@ -1766,6 +1881,7 @@ hipError_t enqueue_iter_sort(const GraphDev& g, int slot, int key_bits, int sort
     a.adj = g.adj;
     a.inc = g.inc;
     a.pos = g.rnd;
+    a.cb = coarse ? g.cb : nullptr;
     a.ctl = g.ctl;
     if (ev_a && (e = hipEventRecord(ev_a, s)) != hipSuccess) return e;
     if (g.nnz > 0) k_sweep_sort<<<sort_grid, SORT_BLK, 0, s>>>(a);

@@ -235,3 +235,17 @@ def test_peel_bucket_more_ranges_than_blocks(dsg, ctx):
         g.run(2, (1, 10), "peel")
         assert_same(g, ref, f"bucket5M/{thr}")
         g.close()
+
+
+@pytest.mark.parametrize("name", list(_bucket_cases().keys()))
+def test_sort_coarse_rank_paths(dsg, ctx, name):
+    """SORT with the coarse position classes forced on and off: both equal the oracle (the classes only order
+    edges whose endpoints differ in class; equal classes fall back to the full positions)."""
+    o, a = _bucket_cases()[name]
+    ref = oracle.run(o, a, 5, "sort")
+    for coarse in [1, 0]:
+        log(f"sort coarse case={name} coarse={coarse}")
+        g = dsg.Graph(ctx, o, a, t_cap=8).set_sort_tuning(coarse)
+        g.run(5, (0, 1), "sort")
+        assert_same(g, ref, f"sortcoarse/{name}/{coarse}")
+        g.close()
