@@ -42,9 +42,11 @@ def log(msg):
 
 
 def kernel_source_hash() -> str:
+    """SHA-256 prefix over the sources the timed kernels are compiled from (the kernel translation unit and its
+    headers); a committed PMC summary applies only while it matches."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2311_04333_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
+    for name in ("dsg_device.h", "dsg_internal.h", "dsg_kernels.hip"):
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
