@@ -59,6 +59,8 @@ def _bind(lib):
     lib.orc_alg3.argtypes = [i32, P, P, P, P, P, P, P, P]
     lib.orc_digest.restype = ctypes.c_uint64
     lib.orc_digest.argtypes = [i32, P]
+    lib.orc_coreness.restype = i32
+    lib.orc_coreness.argtypes = [i32, P, P, P]
     return lib
 
 
@@ -227,3 +229,15 @@ def digest(round_arr, lib=None) -> int:
     lib = lib or load_library()
     r = np.ascontiguousarray(round_arr, dtype=np.int32)
     return int(lib.orc_digest(len(r), _ptr(r)))
+
+
+def coreness(offsets, adj, lib=None):
+    """Core numbers and k_max by Coreness (Section 2): (int32[n], k_max)."""
+    lib = lib or load_library()
+    o, a = _csr(offsets, adj)
+    n = len(o) - 1
+    core = np.zeros(max(n, 1), dtype=np.int32)
+    kmax = lib.orc_coreness(n, _ptr(o), _ptr(a), _ptr(core))
+    if kmax < 0:
+        raise MemoryError("oracle coreness: out of memory")
+    return core[:n], int(kmax)

@@ -395,3 +395,60 @@ int orc_run_fused(int32_t n, const int32_t* off, const int32_t* adj, int32_t T, 
     free(degH); free(start); free(inH); free(seq); free(inF);
     return 0;
 }
+
+/*
+ * Coreness (Section 2): peel a vertex of minimum current degree, one at a
+ * time, until none is left; D is the largest degree any vertex had when it
+ * was peeled, and core(v) = D at the moment v is peeled.  The minimum is
+ * found with degree buckets (a doubly linked list per degree) so that large
+ * graphs finish in O(n + m); which of several minimum-degree vertices goes
+ * first does not change any core number.  Returns k_max = max core(v) (0 for
+ * a graph without edges), or -1 when out of memory.
+ */
+int32_t orc_coreness(int32_t n, const int32_t* off, const int32_t* adj, int32_t* core) {
+    int32_t maxd = 0;
+    for (int32_t v = 0; v < n; v++)
+        if (off[v + 1] - off[v] > maxd) maxd = off[v + 1] - off[v];
+    int32_t* deg = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int32_t* head = (int32_t*)malloc(sizeof(int32_t) * (size_t)(maxd + 1));
+    int32_t* nxt = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int32_t* prv = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    uint8_t* gone = (uint8_t*)calloc((size_t)(n > 0 ? n : 1), 1);
+    if (!deg || !head || !nxt || !prv || !gone) {
+        free(deg); free(head); free(nxt); free(prv); free(gone);
+        return -1;
+    }
+    for (int32_t d = 0; d <= maxd; d++) head[d] = -1;
+    for (int32_t v = n - 1; v >= 0; v--) {
+        deg[v] = off[v + 1] - off[v];
+        prv[v] = -1;
+        nxt[v] = head[deg[v]];
+        if (head[deg[v]] >= 0) prv[head[deg[v]]] = v;
+        head[deg[v]] = v;
+    }
+    int32_t D = 0, lo = 0;
+    for (int32_t step = 0; step < n; step++) {
+        while (head[lo] < 0) lo++;  /* lo = current minimum degree */
+        const int32_t v = head[lo];
+        head[lo] = nxt[v];
+        if (nxt[v] >= 0) prv[nxt[v]] = -1;
+        gone[v] = 1;
+        if (deg[v] > D) D = deg[v];
+        core[v] = D;
+        for (int32_t e = off[v]; e < off[v + 1]; e++) {
+            const int32_t u = adj[e];
+            if (gone[u]) continue;
+            /* move u from bucket deg[u] to deg[u] - 1 */
+            if (prv[u] >= 0) nxt[prv[u]] = nxt[u]; else head[deg[u]] = nxt[u];
+            if (nxt[u] >= 0) prv[nxt[u]] = prv[u];
+            deg[u]--;
+            prv[u] = -1;
+            nxt[u] = head[deg[u]];
+            if (head[deg[u]] >= 0) prv[head[deg[u]]] = u;
+            head[deg[u]] = u;
+            if (deg[u] < lo) lo = deg[u];
+        }
+    }
+    free(deg); free(head); free(nxt); free(prv); free(gone);
+    return D;
+}
