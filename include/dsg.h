@@ -183,6 +183,52 @@ dsg_status dsg_set_kernel_timing(dsg_graph* g, int32_t enable);
  * the number of timed launches (0 when timing is off).  Waits for the work. */
 dsg_status dsg_get_kernel_timing(dsg_graph* g, float* total_ms, int32_t* launches);
 
+/* ------------------------------------------------- Pruning-and-Refining
+ * Algorithm 1 (Section 3) with exact k-core pruning, the "PaR" of
+ * PaRGreedy++ and PaRSorting++:
+ *   cores, k_max <- Coreness(G);  L <- ceil(k_max / 2);  G <- getCore(G, L);
+ *   S <- G;  then T times: S' <- one Greedy++ iteration of `variant` on G
+ *   (loads persist across iterations for the vertices that stay);  if
+ *   rho(S') > rho(S): S <- S', L <- max(L, rho(S)), G <- getCore(G, ceil L).
+ * getCore(G, j) is the subgraph induced by the vertices whose core number in
+ * the input graph is >= j, renumbered in input order (so lowest-id ties
+ * resolve as on the input).  The core numbers come from one PEEL pass with
+ * zero loads and eps = 0.  All device memory is the caller's workspace
+ * (dsg_par_workspace_bytes); the input CSR is only read. */
+typedef struct {
+    int64_t best_edges;   /* |E(S)| of the best subgraph found */
+    int64_t best_verts;   /* |S| */
+    int32_t best_iter;    /* iteration that found it, 1..T; 0 = the initial ceil(k_max/2)-core */
+    int32_t kmax;         /* largest core number of the input graph */
+    int32_t level;        /* final core level ceil(L) */
+    int32_t prunes;       /* prunes after the initial one */
+    int32_t final_n;      /* vertices of the last refined graph */
+    int32_t pad;
+    int64_t final_nnz;    /* adjacency entries of the last refined graph */
+} dsg_par_result;
+
+/* Device workspace bytes for dsg_par_run.  1 <= n < 2^26, 0 <= nnz <=
+ * 2^31 - 2^16, T >= 0.  About four int32 per entry plus the graph state. */
+dsg_status dsg_par_workspace_bytes(int32_t n, int64_t nnz, int32_t T, int64_t* bytes);
+
+/* Runs the framework on the symmetric int32 CSR (d_offsets, d_adj) (device,
+ * not modified), with T refinement iterations of `variant` (eps_num/eps_den
+ * used by DSG_PEEL).  flags: DSG_VALIDATE checks the input CSR as
+ * dsg_graph_create does.  Synchronous on the context's stream.  Host
+ * outputs, each optional (NULL to skip): per iteration t = 1..T the edges,
+ * vertices and index of S' (h_iter_edges, h_iter_verts, h_iter_index) and
+ * the size and core level of the graph it refined (h_iter_n, h_iter_nnz as
+ * undirected edges, h_iter_level); the best set's membership in input ids
+ * (h_best_mask, n bytes); the core numbers (h_core, n int32).  Errors:
+ * DSG_EINVAL (arguments, too small a workspace, invalid CSR, DSG_SEQ on a
+ * refined graph above 16000 vertices), DSG_EOVERFLOW ((T + 1) * max_degree
+ * >= 2^31), DSG_EDEVICE. */
+dsg_status dsg_par_run(dsg_ctx* ctx, int32_t n, int64_t nnz, const int32_t* d_offsets, const int32_t* d_adj,
+                       void* d_workspace, int64_t workspace_bytes, int32_t T, int32_t eps_num, int32_t eps_den,
+                       dsg_variant variant, int32_t flags, dsg_par_result* result, int64_t* h_iter_edges,
+                       int64_t* h_iter_verts, int32_t* h_iter_index, int32_t* h_iter_n, int64_t* h_iter_nnz,
+                       int32_t* h_iter_level, uint8_t* h_best_mask, int32_t* h_core);
+
 /* ------------------------------------------------------------------ batches
  * Many independent graphs peeled in one persistent launch (DSG_PEEL rule).
  * Each graph's results are bit-identical to running it alone through

@@ -49,6 +49,9 @@ SIGNATURES = [
     ("dsg_get_iter_digests", ctypes.c_int, [_P, _P, _P, _I32, _P]),
     ("dsg_graph_destroy", ctypes.c_int, [_P]),
     ("dsg_last_run_ms", ctypes.c_int, [_P, _P]),
+    ("dsg_par_workspace_bytes", ctypes.c_int, [_I32, _I64, _I32, _P]),
+    ("dsg_par_run", ctypes.c_int, [_P, _I32, _I64, _P, _P, _P, _I64, _I32, _I32, _I32, _I32, _I32, _P, _P, _P, _P, _P,
+                                   _P, _P, _P, _P]),
     ("dsg_set_peel_tuning", ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int64]),
     ("dsg_set_sort_tuning", ctypes.c_int, [_P, _I32]),
     ("dsg_set_kernel_timing", ctypes.c_int, [_P, _I32]),
@@ -575,3 +578,69 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+class _ParResultC(ctypes.Structure):
+    _fields_ = [("best_edges", ctypes.c_int64), ("best_verts", ctypes.c_int64), ("best_iter", ctypes.c_int32),
+                ("kmax", ctypes.c_int32), ("level", ctypes.c_int32), ("prunes", ctypes.c_int32),
+                ("final_n", ctypes.c_int32), ("pad", ctypes.c_int32), ("final_nnz", ctypes.c_int64)]
+
+
+class ParResult:
+    """Outcome of dsg_par_run (Pruning-and-Refining, Algorithm 1): best (edges, vertices, iteration), the best
+    set's mask, per-iteration (edges, vertices) and index of S', the (n_i, m_i) and core level of each refined
+    graph, core numbers, k_max, the final level and the number of prunes after the first."""
+
+    def __init__(self, c, hist, hist_idx, sizes, levels, best_mask, core):
+        self.best = (int(c.best_edges), int(c.best_verts), int(c.best_iter))
+        self.kmax = int(c.kmax)
+        self.level = int(c.level)
+        self.prunes = int(c.prunes)
+        self.final_size = (int(c.final_n), int(c.final_nnz) // 2)
+        self.hist = hist
+        self.hist_idx = hist_idx
+        self.sizes = sizes
+        self.levels = levels
+        self.best_mask = best_mask
+        self.core = core
+
+
+def par_workspace_bytes(n: int, nnz: int, T: int) -> int:
+    out = ctypes.c_int64()
+    _check(library().dsg_par_workspace_bytes(n, nnz, T, ctypes.addressof(out)))
+    return out.value
+
+
+def par_run(ctx: Context, offsets, adj, T: int, eps=(0, 1), variant: str = "peel", validate: bool = True,
+            workspace=None) -> ParResult:
+    """dsg_par_run on a CSR (numpy arrays or int32 device tensors).  `workspace` (a uint8 device tensor of at least
+    par_workspace_bytes + 256 bytes) may be passed to reuse one allocation across calls."""
+    import torch
+
+    dev = ctx.torch_device
+    o = Graph._dev_i32(offsets, dev)
+    a = Graph._dev_i32(adj, dev)
+    n, nnz = int(o.numel()) - 1, int(a.numel())
+    nbytes = par_workspace_bytes(n, nnz, T)
+    if workspace is None or workspace.numel() < nbytes + 256:
+        workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+    base = workspace.data_ptr()
+    aligned = (base + 255) // 256 * 256
+    c = _ParResultC()
+    he = np.zeros(max(T, 1), dtype=np.int64)
+    hv = np.zeros(max(T, 1), dtype=np.int64)
+    hi = np.zeros(max(T, 1), dtype=np.int32)
+    hn = np.zeros(max(T, 1), dtype=np.int32)
+    hm = np.zeros(max(T, 1), dtype=np.int64)
+    hl = np.zeros(max(T, 1), dtype=np.int32)
+    mask = np.zeros(n, dtype=np.uint8)
+    core = np.zeros(n, dtype=np.int32)
+    num, den = parse_eps(eps)
+    _check(library().dsg_par_run(ctx.handle, n, nnz, ctypes.c_void_p(o.data_ptr()),
+                                 ctypes.c_void_p(a.data_ptr() if nnz > 0 else 0), ctypes.c_void_p(aligned), nbytes, T,
+                                 num, den, VARIANTS[variant], VALIDATE if validate else 0, ctypes.addressof(c),
+                                 he.ctypes.data, hv.ctypes.data, hi.ctypes.data, hn.ctypes.data, hm.ctypes.data,
+                                 hl.ctypes.data, mask.ctypes.data, core.ctypes.data))
+    hist = [(int(he[t]), int(hv[t])) for t in range(T)]
+    return ParResult(c, hist, [int(x) for x in hi[:T]], [(int(hn[t]), int(hm[t])) for t in range(T)],
+                     [int(x) for x in hl[:T]], mask.astype(bool), core)

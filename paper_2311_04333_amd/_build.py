@@ -7,7 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = [os.path.join(CSRC, "dsg_kernels.hip"), os.path.join(CSRC, "dsg_api.hip")]
+SOURCES = [os.path.join(CSRC, "dsg_kernels.hip"), os.path.join(CSRC, "dsg_par.hip"), os.path.join(CSRC, "dsg_api.hip")]
 OUT = os.path.join(HERE, "libdsg.so")
 
 HIPCC_FLAGS = [

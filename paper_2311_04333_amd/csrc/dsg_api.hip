@@ -17,6 +17,7 @@
 #include "dsg.h"
 #include "dsg_device.h"
 #include "dsg_internal.h"
+#include "dsg_par.h"
 
 using dsg::GraphDev;
 
@@ -36,6 +37,7 @@ struct dsg_graph {
     int t_cap;
     int recorded;     // iterations recorded in the history
     int iters_done;   // iterations performed since the last reset (host mirror)
+    long long load_bound;  // upper bound on every load (grows by max_degree per iteration; 0 after reset)
     int last_variant; // -1 = none yet
     hipEvent_t ev0, ev1;
     bool timed;
@@ -326,7 +328,7 @@ dsg_status dsg_run(dsg_graph* g, int32_t T, int32_t eps_num, int32_t eps_den, ds
     if (variant == DSG_SEQ && g->d.n > dsg::SEQ_MAX_N) return fail(DSG_EINVAL, "DSG_SEQ supports n <= 16000");
     if (variant == DSG_PEEL && g->d.n >= dsg::PEEL_MAX_N) return fail(DSG_EINVAL, "DSG_PEEL supports n < 2^26");
     // loads grow by at most max_degree per iteration; priorities add one more
-    if (((long long)g->iters_done + T + 1) * (long long)g->d.max_deg >= (1LL << 31))
+    if (g->load_bound + ((long long)T + 1) * (long long)g->d.max_deg >= (1LL << 31))
         return fail(DSG_EOVERFLOW, "loads could exceed 31 bits");
     DSG_HIP(hipSetDevice(g->ctx->device), "hipSetDevice");
     hipStream_t s = g->ctx->stream;
@@ -349,7 +351,7 @@ dsg_status dsg_run(dsg_graph* g, int32_t T, int32_t eps_num, int32_t eps_den, ds
                                        g->coarse_min_e >= 0 ? g->coarse_min_e : dsg::PEEL_DEFAULT_COARSE_MIN_E,
                                        s, ea, eb);
         } else if (variant == DSG_SORT) {
-            long long bound = (long long)(g->iters_done + t) * (long long)g->d.max_deg;
+            long long bound = g->load_bound + (long long)t * (long long)g->d.max_deg;
             int bits = 0;
             while (bits < 31 && (bound >> bits) != 0) bits++;
             const bool coarse = g->sort_coarse > 0 ||
@@ -365,6 +367,7 @@ dsg_status dsg_run(dsg_graph* g, int32_t T, int32_t eps_num, int32_t eps_den, ds
     g->timed = true;
     g->recorded += T;
     g->iters_done += T;
+    g->load_bound += (long long)T * (long long)g->d.max_deg;
     if (T > 0) g->last_variant = variant;
     return DSG_OK;
 }
@@ -376,6 +379,7 @@ dsg_status dsg_reset(dsg_graph* g) {
     if (e != hipSuccess) return hip_fail(e, "reset");
     g->recorded = 0;
     g->iters_done = 0;
+    g->load_bound = 0;
     g->last_variant = -1;
     g->timed = false;
     return DSG_OK;
@@ -531,6 +535,211 @@ dsg_status dsg_graph_destroy(dsg_graph* g) {
     (void)hipEventDestroy(g->ev0);
     (void)hipEventDestroy(g->ev1);
     delete g;
+    return DSG_OK;
+}
+
+// ------------------------------------------------ Pruning-and-Refining
+
+}  // extern "C"
+
+namespace {
+
+struct ParWs {
+    char* gws;
+    long long gws_bytes;
+    int* core;
+    int* rv;
+    int* kmax;
+    int* off[2];
+    int* adj[2];
+    int* oldid[2];
+    int* iota;
+    int* load;
+    int* keep;
+    int* newid;
+    int* f;
+    int* fs;
+    long long* tiles;
+    long long* counts;
+    unsigned char* mask;
+};
+
+long long carve_par(int n, long long nnz, int T, char* base, ParWs* w) {
+    Layout L;
+    const long long N = n, E = nnz;
+    const long long gb = carve(n, nnz, T, nullptr, nullptr);
+    long long o_g = L.add(gb);
+    long long o_core = L.add(4 * N), o_rv = L.add(4 * (N + 1)), o_km = L.add(16);
+    long long o_off0 = L.add(4 * (N + 1)), o_adj0 = L.add(4 * (E > 0 ? E : 1));
+    long long o_off1 = L.add(4 * (N + 1)), o_adj1 = L.add(4 * (E > 0 ? E : 1));
+    long long o_id0 = L.add(4 * N), o_id1 = L.add(4 * N), o_iota = L.add(4 * N), o_load = L.add(4 * N);
+    long long o_keep = L.add(4 * (N + 1)), o_newid = L.add(4 * (N + 1));
+    long long o_f = L.add(4 * (E + 1)), o_fs = L.add(4 * (E + 1));
+    long long o_t = L.add(8 * dsg::par_scan_tiles((N > E ? N : E) + 1)), o_c = L.add(16), o_m = L.add(N);
+    if (base && w) {
+        w->gws = base + o_g;
+        w->gws_bytes = gb;
+        w->core = reinterpret_cast<int*>(base + o_core);
+        w->rv = reinterpret_cast<int*>(base + o_rv);
+        w->kmax = reinterpret_cast<int*>(base + o_km);
+        w->off[0] = reinterpret_cast<int*>(base + o_off0);
+        w->adj[0] = reinterpret_cast<int*>(base + o_adj0);
+        w->off[1] = reinterpret_cast<int*>(base + o_off1);
+        w->adj[1] = reinterpret_cast<int*>(base + o_adj1);
+        w->oldid[0] = reinterpret_cast<int*>(base + o_id0);
+        w->oldid[1] = reinterpret_cast<int*>(base + o_id1);
+        w->iota = reinterpret_cast<int*>(base + o_iota);
+        w->load = reinterpret_cast<int*>(base + o_load);
+        w->keep = reinterpret_cast<int*>(base + o_keep);
+        w->newid = reinterpret_cast<int*>(base + o_newid);
+        w->f = reinterpret_cast<int*>(base + o_f);
+        w->fs = reinterpret_cast<int*>(base + o_fs);
+        w->tiles = reinterpret_cast<long long*>(base + o_t);
+        w->counts = reinterpret_cast<long long*>(base + o_c);
+        w->mask = reinterpret_cast<unsigned char*>(base + o_m);
+    }
+    return L.total;
+}
+
+// Cut the `level`-core out of graph g into CSR buffer `dst`; returns the new
+// sizes.  Loads of the kept vertices go to w.load.
+dsg_status par_cut(dsg_graph* g, const ParWs& w, const int* oldid, int level, int dst, int* n_out, long long* nnz_out) {
+    dsg::CoreCut c{oldid, w.core, level, w.keep, w.newid, w.f, w.fs, w.tiles,
+                   w.off[dst], w.adj[dst], w.oldid[dst], w.load, w.counts};
+    hipError_t e = dsg::launch_get_core(g->d, c, g->ctx->stream);
+    if (e != hipSuccess) return hip_fail(e, "getCore");
+    long long cnt[2];
+    DSG_HIP(hipStreamSynchronize(g->ctx->stream), "hipStreamSynchronize");
+    DSG_HIP(hipMemcpy(cnt, w.counts, sizeof(cnt), hipMemcpyDeviceToHost), "hipMemcpy(core sizes)");
+    *n_out = (int)cnt[0];
+    *nnz_out = cnt[1];
+    return DSG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+dsg_status dsg_par_workspace_bytes(int32_t n, int64_t nnz, int32_t T, int64_t* bytes) {
+    if (!bytes) return fail(DSG_EINVAL, "bytes is NULL");
+    if (n < 1 || n >= dsg::PEEL_MAX_N) return fail(DSG_EINVAL, "n must be in [1, 2^26)");
+    if (nnz < 0 || nnz > dsg::MAX_NNZ) return fail(DSG_EINVAL, "nnz must be in [0, 2^31 - 2^16]");
+    if (T < 0) return fail(DSG_EINVAL, "T must be >= 0");
+    *bytes = carve_par(n, nnz, T > 0 ? T : 1, nullptr, nullptr);
+    return DSG_OK;
+}
+
+dsg_status dsg_par_run(dsg_ctx* ctx, int32_t n, int64_t nnz, const int32_t* d_offsets, const int32_t* d_adj,
+                       void* d_workspace, int64_t workspace_bytes, int32_t T, int32_t eps_num, int32_t eps_den,
+                       dsg_variant variant, int32_t flags, dsg_par_result* result, int64_t* h_iter_edges,
+                       int64_t* h_iter_verts, int32_t* h_iter_index, int32_t* h_iter_n, int64_t* h_iter_nnz,
+                       int32_t* h_iter_level, uint8_t* h_best_mask, int32_t* h_core) {
+    if (!ctx || !d_offsets || !d_workspace || !result) return fail(DSG_EINVAL, "NULL argument");
+    if (nnz > 0 && !d_adj) return fail(DSG_EINVAL, "d_adj is NULL");
+    if (n < 1 || n >= dsg::PEEL_MAX_N) return fail(DSG_EINVAL, "n must be in [1, 2^26)");
+    if (nnz < 0 || nnz > dsg::MAX_NNZ) return fail(DSG_EINVAL, "nnz must be in [0, 2^31 - 2^16]");
+    if (T < 0) return fail(DSG_EINVAL, "T must be >= 0");
+    if (eps_num < 0 || eps_den < 1) return fail(DSG_EINVAL, "eps must be eps_num >= 0, eps_den >= 1");
+    if (variant != DSG_SEQ && variant != DSG_PEEL && variant != DSG_SORT) return fail(DSG_EINVAL, "unknown variant");
+    const int tcap = T > 0 ? T : 1;
+    const long long need = carve_par(n, nnz, tcap, nullptr, nullptr);
+    if (workspace_bytes < need) return fail(DSG_EINVAL, "workspace too small (dsg_par_workspace_bytes)");
+    DSG_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    ParWs w;
+    carve_par(n, nnz, tcap, static_cast<char*>(d_workspace), &w);
+    hipStream_t s = ctx->stream;
+    dsg_graph* g = nullptr;
+    auto bail = [&](dsg_status st) {
+        if (g) dsg_graph_destroy(g);
+        return st;
+    };
+    // Coreness of the input graph: one PEEL pass with zero loads and eps = 0
+    dsg_status st = dsg_graph_create(ctx, n, nnz, d_offsets, d_adj, w.gws, w.gws_bytes, tcap, flags, &g);
+    if (st != DSG_OK) return st;
+    if (((long long)T + 1) * (long long)g->d.max_deg >= (1LL << 31))
+        return bail(fail(DSG_EOVERFLOW, "loads could exceed 31 bits: (T + 1) * max_degree >= 2^31"));
+    if ((st = dsg_run(g, 1, 0, 1, DSG_PEEL)) != DSG_OK) return bail(st);
+    int nrounds = 0, kmax = 0;
+    DSG_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+    DSG_HIP(hipMemcpy(&nrounds, g->d.rounds, sizeof(int), hipMemcpyDeviceToHost), "hipMemcpy(rounds)");
+    hipError_t e = dsg::launch_core_numbers(g->d, nrounds, w.rv, w.core, w.kmax, s);
+    if (e != hipSuccess) return bail(hip_fail(e, "core numbers"));
+    DSG_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+    DSG_HIP(hipMemcpy(&kmax, w.kmax, sizeof(int), hipMemcpyDeviceToHost), "hipMemcpy(kmax)");
+    // initial prune to the ceil(k_max / 2)-core, loads zero
+    int level = (kmax + 1) / 2;
+    if ((st = dsg_reset(g)) != DSG_OK) return bail(st);
+    if ((e = dsg::launch_iota(w.iota, n, s)) != hipSuccess) return bail(hip_fail(e, "iota"));
+    int cur = 0, nc = 0;
+    long long mc = 0;
+    if ((st = par_cut(g, w, w.iota, level, cur, &nc, &mc)) != DSG_OK) return bail(st);
+    dsg_graph_destroy(g);
+    g = nullptr;
+    const int created_flags = flags & ~DSG_VALIDATE;  // a cut of a valid graph is valid
+    if ((st = dsg_graph_create(ctx, nc, mc, w.off[cur], w.adj[cur], w.gws, w.gws_bytes, tcap, created_flags, &g)) !=
+        DSG_OK)
+        return st;
+    long long be = mc / 2, bv = nc;
+    int best_iter = 0, prunes = 0;
+    if ((e = dsg::launch_vertex_mask(nc, w.oldid[cur], w.mask, n, s)) != hipSuccess) return bail(hip_fail(e, "mask"));
+    for (int t = 1; t <= T; t++) {
+        if ((st = dsg_run(g, 1, eps_num, eps_den, variant)) != DSG_OK) return bail(st);
+        long long ie = 0, iv = 1;
+        int ii = 0;
+        const int slot = g->recorded - 1;
+        DSG_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+        DSG_HIP(hipMemcpy(&ie, g->d.hist_e + slot, 8, hipMemcpyDeviceToHost), "hipMemcpy(hist)");
+        DSG_HIP(hipMemcpy(&iv, g->d.hist_v + slot, 8, hipMemcpyDeviceToHost), "hipMemcpy(hist)");
+        DSG_HIP(hipMemcpy(&ii, g->d.hist_i + slot, 4, hipMemcpyDeviceToHost), "hipMemcpy(hist)");
+        if (h_iter_edges) h_iter_edges[t - 1] = ie;
+        if (h_iter_verts) h_iter_verts[t - 1] = iv;
+        if (h_iter_index) h_iter_index[t - 1] = ii;
+        if (h_iter_n) h_iter_n[t - 1] = nc;
+        if (h_iter_nnz) h_iter_nnz[t - 1] = mc / 2;
+        if (h_iter_level) h_iter_level[t - 1] = level;
+        // strict improvement by exact cross-multiplication (edges < 2^30, vertices < 2^26)
+        if (ie * bv > be * iv) {
+            be = ie;
+            bv = iv;
+            best_iter = t;
+            if ((e = dsg::launch_suffix_mask(g->d, w.oldid[cur], ii, w.mask, n, s)) != hipSuccess)
+                return bail(hip_fail(e, "mask"));
+            const int lv = (int)((ie + iv - 1) / iv);  // ceil(rho(S))
+            if (lv > level) {
+                level = lv;
+                prunes++;
+                int nn = 0;
+                long long mm = 0;
+                if ((st = par_cut(g, w, w.oldid[cur], level, 1 - cur, &nn, &mm)) != DSG_OK) return bail(st);
+                const long long lb = g->load_bound;
+                dsg_graph_destroy(g);
+                g = nullptr;
+                cur = 1 - cur;
+                nc = nn;
+                mc = mm;
+                if ((st = dsg_graph_create(ctx, nc, mc, w.off[cur], w.adj[cur], w.gws, w.gws_bytes, tcap,
+                                           created_flags, &g)) != DSG_OK)
+                    return st;
+                // the surviving vertices keep their loads (graph creation zeroed them), and so does the bound
+                // on them that sizes the SORT keys and the overflow guard
+                DSG_HIP(hipMemcpyAsync(g->d.load, w.load, sizeof(int) * (size_t)nc, hipMemcpyDeviceToDevice, s),
+                        "hipMemcpyAsync(loads)");
+                g->load_bound = lb;
+            }
+        }
+    }
+    DSG_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+    result->best_edges = be;
+    result->best_verts = bv;
+    result->best_iter = best_iter;
+    result->kmax = kmax;
+    result->level = level;
+    result->prunes = prunes;
+    result->final_n = nc;
+    result->final_nnz = mc;
+    if (h_best_mask) DSG_HIP(hipMemcpy(h_best_mask, w.mask, (size_t)n, hipMemcpyDeviceToHost), "hipMemcpy(mask)");
+    if (h_core) DSG_HIP(hipMemcpy(h_core, w.core, sizeof(int) * (size_t)n, hipMemcpyDeviceToHost), "hipMemcpy(core)");
+    dsg_graph_destroy(g);
     return DSG_OK;
 }
 

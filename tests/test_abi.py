@@ -81,3 +81,17 @@ def test_missing_library_fails_loudly(tmp_path, monkeypatch):
     monkeypatch.setattr(dsg, "_lib", None)
     with pytest.raises(RuntimeError):
         dsg.library()
+
+
+def test_par_workspace_bytes_host_logic(lib):
+    import paper_2311_04333_amd as dsg
+
+    small = dsg.par_workspace_bytes(2000, 41216, 8)
+    big = dsg.par_workspace_bytes(4194304, 128312518, 20)
+    assert 0 < small < big and big % 256 == 0
+    # the graph state plus two cut CSR buffers and two edge scans: more than four int32 per entry
+    assert big > dsg.workspace_bytes(4194304, 128312518, 20) + 4 * 4 * 128312518
+    with pytest.raises(dsg.DsgError):
+        dsg.par_workspace_bytes(1 << 26, 10, 1)
+    with pytest.raises(dsg.DsgError):
+        dsg.par_workspace_bytes(10, 10, -1)

@@ -1,0 +1,98 @@
+"""Pruning-and-Refining (Algorithm 1) on the GPU against the oracle's framework, bit for bit: core numbers, k_max,
+every refined graph's size and core level, the per-iteration (edges, vertices, index) of S', the best pair, the
+iteration that found it, the best set, the final level and the number of prunes."""
+import numpy as np
+import pytest
+
+import graphgen
+from gpu_helpers import log
+from oracle import prune
+from test_gpu_parity import edge_cases
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dsg():
+    import torch
+
+    import paper_2311_04333_amd as dsg
+
+    assert torch.cuda.is_available()
+    dsg.library()
+    return dsg
+
+
+@pytest.fixture(scope="module")
+def ctx(dsg):
+    c = dsg.Context(0)
+    yield c
+    c.close()
+
+
+def assert_par_same(g, r, what):
+    assert g.kmax == r.kmax, f"{what}: kmax {g.kmax} vs {r.kmax}"
+    assert np.array_equal(g.core, r.core), f"{what}: core numbers differ at {np.flatnonzero(g.core != r.core)[:10]}"
+    assert g.sizes == r.sizes, f"{what}: refined graph sizes {g.sizes} vs {r.sizes}"
+    assert g.levels == r.levels, f"{what}: levels differ"
+    assert g.hist == r.hist, f"{what}: per-iteration densities differ"
+    assert g.hist_idx == r.hist_idx, f"{what}: per-iteration indices differ"
+    assert g.best == r.best, f"{what}: best {g.best} vs {r.best}"
+    assert np.array_equal(g.best_mask, r.best_mask), f"{what}: best set differs"
+    assert g.level == r.level and g.prunes == r.prunes, f"{what}: level/prunes {g.level, g.prunes} vs {r.level, r.prunes}"
+
+
+def _cases():
+    ec = edge_cases()
+    cases = {k: ec[k] for k in ["single_vertex", "no_edges_n7", "one_edge", "triangle", "K8", "K40", "star_3000",
+                                "path_50", "isolated_mix", "two_cliques", "gnp_0", "gnp_8"]}
+    cases["config1_s1"] = graphgen.config1(1)
+    cases["config1_s2"] = graphgen.config1(2)
+    cases["ragged_12289"] = graphgen.er_planted(7 + 12289, 12289, 60000, 60, 1, 2)
+    cases["rmat12"] = graphgen.rmat(3, 12, 16 << 12)
+    cases["rmat16"] = graphgen.rmat(5, 16, 16 << 16)
+    cases["chunglu_200k"] = graphgen.chunglu(5, 200_000, 2.1, 30.0, 10_000.0)
+    return cases
+
+
+VARIANTS = [("peel", (1, 10)), ("peel", (0, 1)), ("sort", (0, 1))]
+
+
+@pytest.mark.parametrize("name", list(_cases().keys()))
+def test_par_against_oracle(dsg, ctx, name):
+    o, a = _cases()[name]
+    n = len(o) - 1
+    vs = VARIANTS + ([("seq", (0, 1))] if n <= 16000 else [])
+    for variant, eps in vs:
+        log(f"par case={name} variant={variant} eps={eps}")
+        ref = prune.par_run(o, a, 8, variant, eps)
+        g = dsg.par_run(ctx, o, a, 8, eps, variant)
+        assert_par_same(g, ref, f"{name}/{variant}/{eps}")
+
+
+def test_par_zero_iterations(dsg, ctx):
+    """T = 0: only the initial prune; the best is the ceil(k_max/2)-core."""
+    o, a = graphgen.config1(3)
+    ref = prune.par_run(o, a, 0, "peel", (1, 10))
+    g = dsg.par_run(ctx, o, a, 0, (1, 10), "peel")
+    assert g.best == ref.best and g.kmax == ref.kmax and np.array_equal(g.best_mask, ref.best_mask)
+
+
+def test_par_rmat22_full_size(dsg, ctx):
+    """R-MAT scale 22 (n = 4,194,304), PEEL eps = 1/10, T = 20, in the configuration bench.py times."""
+    log("par: generating R-MAT scale 22")
+    o, a = graphgen.config2(1)
+    log("par: oracle framework (coreness + cuts + 20 refinements)")
+    ref = prune.par_run(o, a, 20, "peel", (1, 10))
+    log(f"par: oracle done, k_max={ref.kmax} sizes {ref.sizes[0]} .. {ref.sizes[-1]}")
+    g = dsg.par_run(ctx, o, a, 20, (1, 10), "peel")
+    assert_par_same(g, ref, "rmat22")
+
+
+def test_par_invalid_arguments(dsg, ctx):
+    o, a = graphgen.complete(4)
+    with pytest.raises(dsg.DsgError):
+        dsg.par_run(ctx, o, a, -1, (1, 10), "peel")
+    bad_o, bad_a = np.array([0, 1, 2], np.int32), np.array([0, 1], np.int32)  # self-loops
+    with pytest.raises(dsg.DsgError):
+        dsg.par_run(ctx, bad_o, bad_a, 2, (1, 10), "peel")
