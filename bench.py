@@ -70,9 +70,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="rmat22", choices=["rmat22", "batch", "serve"],
+    ap.add_argument("--workload", default="rmat22", choices=["rmat22", "batch", "serve", "par"],
                     help="rmat22: one R-MAT scale-22 graph (default); batch: the 4096-graph batched mix; "
-                         "serve: Poisson request stream through the continuous-batching server")
+                         "serve: Poisson request stream through the continuous-batching server; par: "
+                         "Pruning-and-Refining (exact k-core pruning) on the R-MAT scale-22 graph")
     ap.add_argument("--rates", default="100,300,1000,3000", help="serve: offered request rates (req/s)")
     ap.add_argument("--window", type=float, default=3.0, help="serve: seconds of Poisson arrivals per rate")
     ap.add_argument("--variant", default="peel", choices=["peel", "sort"])
@@ -94,6 +95,8 @@ def main():
         return bench_batch(args)
     if args.workload == "serve":
         return bench_serve(args)
+    if args.workload == "par":
+        return bench_par(args)
 
     import numpy as np
     import torch
@@ -432,6 +435,95 @@ def bench_serve(args):
         "plain": {"graphs_per_s": plain_gps, "requests": len(plan)},
         "served_over_plain": best["graphs_per_s"] / plain_gps,
         "check": {"alone_equals_served": bool(same)},
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_par(args):
+    """Pruning-and-Refining (Algorithm 1) with exact k-core pruning and PEEL eps = 1/10 refinement, T iterations, on
+    the R-MAT graph.  A step is one whole dsg_par_run: Coreness (a PEEL pass with zero loads and eps = 0 over the
+    input), the cut to the ceil(k_max/2)-core, T refinements and the re-cuts.  The line gives the time per step
+    (lower is better) beside the unpruned refinement (T PEEL iterations on the input graph) timed in the same
+    process, and the CPU oracle running the same framework."""
+    import numpy as np
+    import torch
+
+    import graphgen
+    import paper_2311_04333_amd as dsg
+
+    T, eps = args.T, (1, 10)
+    offsets, adj = graphgen.rmat(1, args.scale, 16 << args.scale, 57, 19, 19)
+    n, m = len(offsets) - 1, len(adj) // 2
+    ctx = dsg.Context(0)
+    o_dev = torch.from_numpy(offsets).cuda()
+    a_dev = torch.from_numpy(adj).cuda()
+    ws = torch.empty(dsg.par_workspace_bytes(n, len(adj), T) + 256, dtype=torch.uint8, device="cuda")
+    for w in range(max(args.warmup, 1)):
+        r = dsg.par_run(ctx, o_dev, a_dev, T, eps, "peel", validate=False, workspace=ws)
+    log(f"par: k_max={r.kmax}, first cut {r.sizes[0] if r.sizes else None}, last {r.final_size}, best {r.best}, "
+        f"prunes after the first {r.prunes}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        r = dsg.par_run(ctx, o_dev, a_dev, T, eps, "peel", validate=False, workspace=ws)
+    torch.cuda.synchronize()
+    par_ms = 1e3 * (time.perf_counter() - t0) / args.steps
+    del ws
+    # the unpruned refinement, and the Coreness pass alone (the dominant kernel of a par step)
+    g = dsg.Graph(ctx, o_dev, a_dev, t_cap=T, validate=False)
+    g.set_kernel_timing(True)
+    g.reset().run(T, eps, "peel")
+    g.sync()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    g.reset().run(T, eps, "peel")
+    g.sync()
+    plain_ms = 1e3 * (time.perf_counter() - t1)
+    g.close()
+    _, kmax, core_rounds, core_ms = dsg.coreness(ctx, o_dev, a_dev, validate=False, timed=True)
+    alg_bytes = 16.0 * m + 16.0 * n
+    achieved = alg_bytes / (core_ms / 1e3) / 1e9 if core_ms > 0 else None
+    log(f"par: {par_ms:.1f} ms per step; unpruned refinement {plain_ms:.1f} ms; Coreness round loop {core_ms:.2f} ms "
+        f"({core_rounds} rounds)")
+    check = None
+    cpu = None
+    if not args.no_check or args.cpu_iters > 0:
+        from oracle import prune
+
+        t2 = time.perf_counter()
+        ref = prune.par_run(offsets, adj, T, "peel", eps)
+        cpu_s = time.perf_counter() - t2
+        check = {"matches_oracle": bool(ref.best == r.best and ref.hist == r.hist and ref.sizes == r.sizes and
+                                        ref.kmax == r.kmax and np.array_equal(ref.best_mask, r.best_mask))}
+        cpu = {"value": cpu_s * 1e3, "unit": "ms", "cores": 1, "kind": "oracle",
+               "sample": f"the whole framework on the same graph (T={T}), single thread"}
+    line = {
+        "metric": "PaRGreedy++ time (Coreness + k-core cuts + T refinements) vs the unpruned refinement",
+        "value": par_ms,
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": max(args.warmup, 1),
+        "ms_per_step": par_ms,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": f"R-MAT scale {args.scale} (n={n}, m={m}), PEEL eps=1/10 refinement, T={T}, exact "
+                               f"k-core pruning"},
+        "unpruned_ms": plain_ms,
+        "speedup_vs_unpruned": plain_ms / par_ms,
+        "k_max": r.kmax,
+        "cuts": {"first": r.sizes[0] if r.sizes else None, "last": r.final_size, "prunes_after_first": r.prunes},
+        "best": r.best,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": None,
+                     "kernel": "k_peel_rounds<true> (the Coreness pass: zero loads, eps = 0, monotone thresholds, "
+                               "whole input graph)",
+                     "avg_launch_ms": core_ms, "rounds": core_rounds, "alg_bytes_per_launch": alg_bytes},
+        "cpu_baseline": cpu,
+        "check": check,
     }
     print(json.dumps(line), flush=True)
 

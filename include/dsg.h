@@ -192,8 +192,8 @@ dsg_status dsg_get_kernel_timing(dsg_graph* g, float* total_ms, int32_t* launche
  *   rho(S') > rho(S): S <- S', L <- max(L, rho(S)), G <- getCore(G, ceil L).
  * getCore(G, j) is the subgraph induced by the vertices whose core number in
  * the input graph is >= j, renumbered in input order (so lowest-id ties
- * resolve as on the input).  The core numbers come from one PEEL pass with
- * zero loads and eps = 0.  All device memory is the caller's workspace
+ * resolve as on the input).  The core numbers come from dsg_coreness's
+ * pass.  All device memory is the caller's workspace
  * (dsg_par_workspace_bytes); the input CSR is only read. */
 typedef struct {
     int64_t best_edges;   /* |E(S)| of the best subgraph found */
@@ -206,6 +206,18 @@ typedef struct {
     int32_t pad;
     int64_t final_nnz;    /* adjacency entries of the last refined graph */
 } dsg_par_result;
+
+/* Core numbers (Coreness, Section 2) of a symmetric int32 CSR on the device:
+ * one PEEL pass with zero loads, eps = 0 and monotone round thresholds (every
+ * round peels all alive vertices whose degree is at most the largest round
+ * minimum so far, as bucketing does; those vertices' core number is that
+ * value).  Workspace: dsg_par_workspace_bytes(n, nnz, 1).  flags:
+ * DSG_VALIDATE.  Writes *kmax, h_core (n int32, optional), *rounds (optional)
+ * and *round_loop_ms (optional: device time of the round loop; timing it
+ * adds two events).  Synchronous.  DSG_EINVAL / DSG_EDEVICE as dsg_par_run. */
+dsg_status dsg_coreness(dsg_ctx* ctx, int32_t n, int64_t nnz, const int32_t* d_offsets, const int32_t* d_adj,
+                        void* d_workspace, int64_t workspace_bytes, int32_t flags, int32_t* h_core, int32_t* kmax,
+                        int32_t* rounds, float* round_loop_ms);
 
 /* Device workspace bytes for dsg_par_run.  1 <= n < 2^26, 0 <= nnz <=
  * 2^31 - 2^16, T >= 0.  About four int32 per entry plus the graph state. */

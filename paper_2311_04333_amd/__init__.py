@@ -49,6 +49,7 @@ SIGNATURES = [
     ("dsg_get_iter_digests", ctypes.c_int, [_P, _P, _P, _I32, _P]),
     ("dsg_graph_destroy", ctypes.c_int, [_P]),
     ("dsg_last_run_ms", ctypes.c_int, [_P, _P]),
+    ("dsg_coreness", ctypes.c_int, [_P, _I32, _I64, _P, _P, _P, _I64, _I32, _P, _P, _P, _P]),
     ("dsg_par_workspace_bytes", ctypes.c_int, [_I32, _I64, _I32, _P]),
     ("dsg_par_run", ctypes.c_int, [_P, _I32, _I64, _P, _P, _P, _I64, _I32, _I32, _I32, _I32, _I32, _P, _P, _P, _P, _P,
                                    _P, _P, _P, _P]),
@@ -644,3 +645,25 @@ def par_run(ctx: Context, offsets, adj, T: int, eps=(0, 1), variant: str = "peel
     hist = [(int(he[t]), int(hv[t])) for t in range(T)]
     return ParResult(c, hist, [int(x) for x in hi[:T]], [(int(hn[t]), int(hm[t])) for t in range(T)],
                      [int(x) for x in hl[:T]], mask.astype(bool), core)
+
+
+def coreness(ctx: Context, offsets, adj, validate: bool = True, timed: bool = False):
+    """dsg_coreness: (core numbers int32[n], k_max, rounds of the pass, round-loop ms or None)."""
+    import torch
+
+    dev = ctx.torch_device
+    o = Graph._dev_i32(offsets, dev)
+    a = Graph._dev_i32(adj, dev)
+    n, nnz = int(o.numel()) - 1, int(a.numel())
+    nbytes = par_workspace_bytes(n, nnz, 1)
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+    aligned = (ws.data_ptr() + 255) // 256 * 256
+    core = np.zeros(n, dtype=np.int32)
+    kmax = ctypes.c_int32()
+    rounds = ctypes.c_int32()
+    ms = ctypes.c_float()
+    _check(library().dsg_coreness(ctx.handle, n, nnz, ctypes.c_void_p(o.data_ptr()),
+                                  ctypes.c_void_p(a.data_ptr() if nnz > 0 else 0), ctypes.c_void_p(aligned), nbytes,
+                                  VALIDATE if validate else 0, core.ctypes.data, ctypes.addressof(kmax),
+                                  ctypes.addressof(rounds), ctypes.addressof(ms) if timed else None))
+    return core, int(kmax.value), int(rounds.value), (float(ms.value) if timed else None)

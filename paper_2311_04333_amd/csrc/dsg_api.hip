@@ -47,6 +47,7 @@ struct dsg_graph {
     long long bkt_min_e;           // PEEL rounds with at least this many frontier edges use owner buckets
     long long coarse_min_e;        // ... and coarse sweep chunks; -1 = default
     int sort_coarse;               // SORT coarse ranks: -1 = by size, 0 = off, 1 = on
+    int peel_mono;                 // internal: monotone round thresholds (Coreness by buckets)
 };
 
 struct dsg_batch {
@@ -349,7 +350,7 @@ dsg_status dsg_run(dsg_graph* g, int32_t T, int32_t eps_num, int32_t eps_den, ds
         if (variant == DSG_PEEL) {
             e = dsg::enqueue_iter_peel(g->d, slot, eps_num, eps_den, g->ctx->peel_grid, g->bkt_min_e,
                                        g->coarse_min_e >= 0 ? g->coarse_min_e : dsg::PEEL_DEFAULT_COARSE_MIN_E,
-                                       s, ea, eb);
+                                       g->peel_mono, s, ea, eb);
         } else if (variant == DSG_SORT) {
             long long bound = g->load_bound + (long long)t * (long long)g->d.max_deg;
             int bits = 0;
@@ -616,9 +617,76 @@ dsg_status par_cut(dsg_graph* g, const ParWs& w, const int* oldid, int level, in
     return DSG_OK;
 }
 
+// Coreness of the input CSR into w.core / w.kmax: one PEEL pass with zero
+// loads, eps = 0 and monotone thresholds.  Leaves the input graph alive in
+// *gout (its static items serve the first cut).
+dsg_status par_coreness(dsg_ctx* ctx, const ParWs& w, int n, long long nnz, const int32_t* d_offsets,
+                        const int32_t* d_adj, int tcap, int flags, bool timed, dsg_graph** gout, int* nrounds_out,
+                        int* kmax_out, float* ms_out) {
+    dsg_graph* g = nullptr;
+    dsg_status st = dsg_graph_create(ctx, n, nnz, d_offsets, d_adj, w.gws, w.gws_bytes, tcap, flags, &g);
+    if (st != DSG_OK) return st;
+    hipStream_t s = ctx->stream;
+    g->peel_mono = 1;
+    if (timed) dsg_set_kernel_timing(g, 1);
+    st = dsg_run(g, 1, 0, 1, DSG_PEEL);
+    g->peel_mono = 0;
+    if (st != DSG_OK) {
+        dsg_graph_destroy(g);
+        return st;
+    }
+    int nrounds = 0, kmax = 0;
+    if (timed) {
+        int launches = 0;
+        float ms = 0.f;
+        dsg_get_kernel_timing(g, &ms, &launches);
+        if (ms_out) *ms_out = ms;
+        dsg_set_kernel_timing(g, 0);
+    }
+    hipError_t e;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess ||
+        (e = hipMemcpy(&nrounds, g->d.rounds, sizeof(int), hipMemcpyDeviceToHost)) != hipSuccess ||
+        (e = dsg::launch_core_numbers(g->d, nrounds, w.rv, w.core, w.kmax, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess ||
+        (e = hipMemcpy(&kmax, w.kmax, sizeof(int), hipMemcpyDeviceToHost)) != hipSuccess) {
+        dsg_graph_destroy(g);
+        return hip_fail(e, "core numbers");
+    }
+    *gout = g;
+    *nrounds_out = nrounds;
+    *kmax_out = kmax;
+    return DSG_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+dsg_status dsg_coreness(dsg_ctx* ctx, int32_t n, int64_t nnz, const int32_t* d_offsets, const int32_t* d_adj,
+                        void* d_workspace, int64_t workspace_bytes, int32_t flags, int32_t* h_core, int32_t* kmax,
+                        int32_t* rounds, float* round_loop_ms) {
+    if (!ctx || !d_offsets || !d_workspace || !kmax) return fail(DSG_EINVAL, "NULL argument");
+    if (nnz > 0 && !d_adj) return fail(DSG_EINVAL, "d_adj is NULL");
+    if (n < 1 || n >= dsg::PEEL_MAX_N) return fail(DSG_EINVAL, "n must be in [1, 2^26)");
+    if (nnz < 0 || nnz > dsg::MAX_NNZ) return fail(DSG_EINVAL, "nnz must be in [0, 2^31 - 2^16]");
+    const long long need = carve_par(n, nnz, 1, nullptr, nullptr);
+    if (workspace_bytes < need) return fail(DSG_EINVAL, "workspace too small (dsg_par_workspace_bytes with T = 1)");
+    DSG_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    ParWs w;
+    carve_par(n, nnz, 1, static_cast<char*>(d_workspace), &w);
+    dsg_graph* g = nullptr;
+    int nr = 0, km = 0;
+    float ms = 0.f;
+    dsg_status st = par_coreness(ctx, w, n, nnz, d_offsets, d_adj, 1, flags, round_loop_ms != nullptr, &g, &nr, &km,
+                                 &ms);
+    if (st != DSG_OK) return st;
+    dsg_graph_destroy(g);
+    *kmax = km;
+    if (rounds) *rounds = nr;
+    if (round_loop_ms) *round_loop_ms = ms;
+    if (h_core) DSG_HIP(hipMemcpy(h_core, w.core, sizeof(int) * (size_t)n, hipMemcpyDeviceToHost), "hipMemcpy(core)");
+    return DSG_OK;
+}
 
 dsg_status dsg_par_workspace_bytes(int32_t n, int64_t nnz, int32_t T, int64_t* bytes) {
     if (!bytes) return fail(DSG_EINVAL, "bytes is NULL");
@@ -653,19 +721,13 @@ dsg_status dsg_par_run(dsg_ctx* ctx, int32_t n, int64_t nnz, const int32_t* d_of
         if (g) dsg_graph_destroy(g);
         return st;
     };
-    // Coreness of the input graph: one PEEL pass with zero loads and eps = 0
-    dsg_status st = dsg_graph_create(ctx, n, nnz, d_offsets, d_adj, w.gws, w.gws_bytes, tcap, flags, &g);
+    // Coreness of the input graph (Coreness by buckets on the PEEL round loop)
+    int nrounds = 0, kmax = 0;
+    dsg_status st = par_coreness(ctx, w, n, nnz, d_offsets, d_adj, tcap, flags, false, &g, &nrounds, &kmax, nullptr);
     if (st != DSG_OK) return st;
     if (((long long)T + 1) * (long long)g->d.max_deg >= (1LL << 31))
         return bail(fail(DSG_EOVERFLOW, "loads could exceed 31 bits: (T + 1) * max_degree >= 2^31"));
-    if ((st = dsg_run(g, 1, 0, 1, DSG_PEEL)) != DSG_OK) return bail(st);
-    int nrounds = 0, kmax = 0;
-    DSG_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
-    DSG_HIP(hipMemcpy(&nrounds, g->d.rounds, sizeof(int), hipMemcpyDeviceToHost), "hipMemcpy(rounds)");
-    hipError_t e = dsg::launch_core_numbers(g->d, nrounds, w.rv, w.core, w.kmax, s);
-    if (e != hipSuccess) return bail(hip_fail(e, "core numbers"));
-    DSG_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
-    DSG_HIP(hipMemcpy(&kmax, w.kmax, sizeof(int), hipMemcpyDeviceToHost), "hipMemcpy(kmax)");
+    hipError_t e;
     // initial prune to the ceil(k_max / 2)-core, loads zero
     int level = (kmax + 1) / 2;
     if ((st = dsg_reset(g)) != DSG_OK) return bail(st);

@@ -161,8 +161,8 @@ hipError_t launch_zero_ctl(const GraphDev& g, hipStream_t s);
 // ev_a / ev_b (may be null) are recorded on `s` right before and after the
 // iteration's dominant kernel (PEEL round loop, SORT sweep, SEQ peel).
 hipError_t enqueue_iter_peel(const GraphDev& g, int slot, int eps_num, int eps_den, int peel_grid,
-                             long long bkt_min_e, long long coarse_min_e, hipStream_t s, hipEvent_t ev_a,
-                             hipEvent_t ev_b);
+                             long long bkt_min_e, long long coarse_min_e, int mono, hipStream_t s, hipEvent_t ev_a,
+                             hipEvent_t ev_b);  // mono: monotone round thresholds (Coreness by buckets)
 hipError_t enqueue_iter_sort(const GraphDev& g, int slot, int key_bits, int sort_grid, bool coarse, hipStream_t s,
                              hipEvent_t ev_a, hipEvent_t ev_b);
 hipError_t enqueue_iter_seq(const GraphDev& g, int slot, hipStream_t s, hipEvent_t ev_a, hipEvent_t ev_b);

@@ -773,6 +773,7 @@ static_assert(PEEL_BLK * SEL_U <= (int)TCNT_MASK, "tile counts must fit their pa
 //   grid sync
 // L_0 is implicit (all vertices).  The loop ends when L_r is empty.  Every
 // block reads the same counters after a grid sync, so all leave together.
+template <bool MONO>
 __global__ __launch_bounds__(PEEL_BLK, PEEL_BLOCKS_PER_CU) void k_peel_rounds(PeelArgs a) {
     __shared__ PeelLds lds;
     __shared__ unsigned long long shs[PEEL_BLK / WAVE];
@@ -780,6 +781,7 @@ __global__ __launch_bounds__(PEEL_BLK, PEEL_BLOCKS_PER_CU) void k_peel_rounds(Pe
     __shared__ unsigned long long s_fbase;
     __shared__ unsigned int s_lbase;
     __shared__ int s_chunk;
+    __shared__ long long s_thr;  // previous round's threshold (MONO)
     Ctl* ctl = a.ctl;
     GridSync* gs = a.gs;
     const unsigned int nblocks = gridDim.x;
@@ -810,7 +812,14 @@ __global__ __launch_bounds__(PEEL_BLK, PEEL_BLOCKS_PER_CU) void k_peel_rounds(Pe
             break;
         }
         prevLc = Lc;
-        const long long thr = ((q + p) * (long long)mn) / q;
+        long long thr = ((q + p) * (long long)mn) / q;
+        if constexpr (MONO) {
+            // Coreness by buckets: peel everything at or below the largest
+            // threshold so far (the round's vertices all have core number thr)
+            if (r > 0) thr = max(thr, s_thr);
+            __syncthreads();
+            if (threadIdx.x == 0) s_thr = thr;
+        }
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             const int zs = (r + 2) & 3;
             ctl->mn[zs] = 0xFFFFFFFFu;
@@ -1717,7 +1726,7 @@ int ctl_bytes() { return (int)sizeof(Ctl); }
 
 int peel_blocks_per_cu() {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(k_peel_rounds), PEEL_BLK, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(k_peel_rounds<false>), PEEL_BLK, 0) !=
         hipSuccess)
         return 1;
     return nb < 1 ? 1 : nb;
@@ -1808,7 +1817,7 @@ static int bits_for(long long maxval) {
 }
 
 hipError_t enqueue_iter_peel(const GraphDev& g, int slot, int eps_num, int eps_den, int peel_grid,
-                             long long bkt_min_e, long long coarse_min_e, hipStream_t s, hipEvent_t ev_a,
+                             long long bkt_min_e, long long coarse_min_e, int mono, hipStream_t s, hipEvent_t ev_a,
                              hipEvent_t ev_b) {
     k_iter_begin<<<1, 256, 0, s>>>(g.ctl, g.gsync, g.bfill, g.nr);
     k_peel_init<<<grid_for(g.n, 256, 2048), 256, 0, s>>>(g.n, g.off, g.load, g.prio, g.rnd, g.inc, g.st2, g.ctl);
@@ -1842,8 +1851,9 @@ hipError_t enqueue_iter_peel(const GraphDev& g, int slot, int eps_num, int eps_d
     a.coarse_min_e = coarse_min_e;
     void* args[] = {&a};
     if (ev_a && (e = hipEventRecord(ev_a, s)) != hipSuccess) return e;
-    e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_peel_rounds), dim3(peel_grid), dim3(PEEL_BLK), args,
-                                   0, s);
+    e = hipLaunchCooperativeKernel(mono ? reinterpret_cast<const void*>(k_peel_rounds<true>)
+                                        : reinterpret_cast<const void*>(k_peel_rounds<false>),
+                                   dim3(peel_grid), dim3(PEEL_BLK), args, 0, s);
     if (e != hipSuccess) return e;
     if (ev_b && (e = hipEventRecord(ev_b, s)) != hipSuccess) return e;
     // rounds <= n, so ceil(bits(n-1)/8) digit passes cover every round index

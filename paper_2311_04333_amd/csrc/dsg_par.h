@@ -9,12 +9,13 @@ namespace dsg {
 // Exclusive-scan scratch: one int64 per 4096-element tile.
 long long par_scan_tiles(long long count);
 
-// Core numbers from a finished PEEL iteration run with zero loads and
-// eps = 0 on graph `g`: every round peels exactly the vertices whose
-// priority (= current degree) equals the round minimum, and a peeled
-// vertex's priority stays at that value, so core(v) is the running maximum
-// of the round minima up to v's round (Coreness, Section 2).  `rv` holds
-// `nrounds` ints of scratch.  Writes core[0..n) and *kmax_dev (one int).
+// Core numbers from a finished PEEL iteration run with zero loads, eps = 0
+// and monotone thresholds on graph `g`: round r peels every alive vertex
+// whose degree is at most D_r = max(D_{r-1}, round minimum), and a peeled
+// vertex's priority stays at its degree when peeled, so core(v) is the
+// running maximum of the round minima up to v's round (Coreness, Section 2,
+// by buckets).  `rv` holds `nrounds` ints of scratch.  Writes core[0..n)
+// and *kmax_dev (one int).
 hipError_t launch_core_numbers(const GraphDev& g, int nrounds, int* rv, int* core, int* kmax_dev, hipStream_t s);
 
 // Subgraph of the current graph `g` induced by {x : core[oldid[x]] >= level}

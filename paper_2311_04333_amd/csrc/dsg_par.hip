@@ -102,13 +102,13 @@ __global__ void k_par_fill(int* __restrict__ p, int v, long long cnt) {
         p[i] = v;
 }
 
-// rv[r] = the priority of the vertices peeled in round r (all equal when
-// eps = 0: the round takes exactly the minimum)
+// rv[r] = the smallest priority among the vertices peeled in round r (the
+// round minimum: a peeled vertex's priority stays at its value when peeled)
 __global__ void k_round_value(int n, int nrounds, const int* __restrict__ rnd, const int* __restrict__ prio,
                               int* __restrict__ rv) {
     for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
         const int r = rnd[v];
-        if (r >= 0 && r < nrounds) atomicMax(&rv[r], prio[v]);
+        if (r >= 0 && r < nrounds) atomicMin(&rv[r], prio[v]);
     }
 }
 
@@ -146,7 +146,7 @@ __global__ void k_core_from_rounds(int n, int nrounds, const int* __restrict__ r
 
 hipError_t launch_core_numbers(const GraphDev& g, int nrounds, int* rv, int* core, int* kmax_dev, hipStream_t s) {
     if (nrounds > 0) {
-        k_par_fill<<<grid_cap(nrounds, 256, 2048), 256, 0, s>>>(rv, 0, nrounds);
+        k_par_fill<<<grid_cap(nrounds, 256, 2048), 256, 0, s>>>(rv, 0x7FFFFFFF, nrounds);
         k_round_value<<<grid_cap(g.n, 256, 2048), 256, 0, s>>>(g.n, nrounds, g.rnd, g.prio, rv);
     }
     k_prefix_max<<<1, PBLK, 0, s>>>(rv, nrounds, kmax_dev);

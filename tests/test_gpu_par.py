@@ -96,3 +96,29 @@ def test_par_invalid_arguments(dsg, ctx):
     bad_o, bad_a = np.array([0, 1, 2], np.int32), np.array([0, 1], np.int32)  # self-loops
     with pytest.raises(dsg.DsgError):
         dsg.par_run(ctx, bad_o, bad_a, 2, (1, 10), "peel")
+
+
+@pytest.mark.parametrize("name", ["single_vertex", "no_edges_n7", "triangle", "K40", "star_3000", "path_50",
+                                  "isolated_mix", "config1_s1", "rmat16", "chunglu_200k"])
+def test_coreness_against_oracle(dsg, ctx, name):
+    """dsg_coreness equals the oracle's sequential Coreness (core numbers are unique)."""
+    import oracle
+
+    o, a = _cases()[name]
+    core, kmax, rounds, _ = dsg.coreness(ctx, o, a)
+    ref, rk = oracle.coreness(o, a)
+    assert kmax == rk and np.array_equal(core, ref)
+    assert rounds >= 1
+
+
+def test_coreness_chunglu_40m(dsg, ctx):
+    """Core numbers of the 40M-vertex Chung-Lu graph (1.1 billion adjacency entries) against the oracle."""
+    import oracle
+
+    log("coreness: generating Chung-Lu n=40M")
+    o, a = graphgen.config3(1)
+    log("coreness: GPU")
+    core, kmax, rounds, ms = dsg.coreness(ctx, o, a, validate=False, timed=True)
+    log(f"coreness: k_max={kmax}, {rounds} rounds, {ms:.1f} ms; oracle")
+    ref, rk = oracle.coreness(o, a)
+    assert kmax == rk and np.array_equal(core, ref)
