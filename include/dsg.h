@@ -138,6 +138,15 @@ dsg_status dsg_get_order(dsg_graph* g, int32_t* h_round, int32_t* h_pos, int32_t
  * (h_rounds may be NULL). */
 dsg_status dsg_get_iter_digests(dsg_graph* g, uint64_t* h_digest, int32_t* h_rounds, int32_t cap, int32_t* count);
 
+/* Width and certificate diagnostics (Section 4.4): per recorded iteration,
+ * the empirical width w_t = max over v of the iteration's load increase
+ * (rho* <= w_t <= max degree), and the largest load after it, L_t.  After t
+ * iterations since the last reset, rho* <= L_t / t (the load-based upper
+ * bound), so the best density found is certified within a factor
+ * (L_t / t) / rho(best).  cap entries at most; *count = recorded
+ * iterations.  Waits for the work. */
+dsg_status dsg_get_iter_bounds(dsg_graph* g, int32_t* h_width, int64_t* h_load_max, int32_t cap, int32_t* count);
+
 /* Release the handle.  Caller memory (CSR, workspace) is not freed. */
 dsg_status dsg_graph_destroy(dsg_graph* g);
 

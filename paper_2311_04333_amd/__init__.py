@@ -50,6 +50,7 @@ SIGNATURES = [
     ("dsg_graph_destroy", ctypes.c_int, [_P]),
     ("dsg_last_run_ms", ctypes.c_int, [_P, _P]),
     ("dsg_coreness", ctypes.c_int, [_P, _I32, _I64, _P, _P, _P, _I64, _I32, _P, _P, _P, _P]),
+    ("dsg_get_iter_bounds", ctypes.c_int, [_P, _P, _P, _I32, _P]),
     ("dsg_par_workspace_bytes", ctypes.c_int, [_I32, _I64, _I32, _P]),
     ("dsg_par_run", ctypes.c_int, [_P, _I32, _I64, _P, _P, _P, _I64, _I32, _I32, _I32, _I32, _I32, _P, _P, _P, _P, _P,
                                    _P, _P, _P, _P]),
@@ -255,6 +256,15 @@ class Graph:
         1 = on."""
         _check(library().dsg_set_sort_tuning(self._h, int(coarse_ranks)))
         return self
+
+    def iter_bounds(self):
+        """Per recorded iteration: (empirical width, largest load after it).  rho* <= largest load / iterations."""
+        w = np.zeros(self.t_cap, dtype=np.int32)
+        lm = np.zeros(self.t_cap, dtype=np.int64)
+        cnt = ctypes.c_int32()
+        _check(library().dsg_get_iter_bounds(self._h, w.ctypes.data, lm.ctypes.data, self.t_cap, ctypes.addressof(cnt)))
+        k = min(cnt.value, self.t_cap)
+        return [(int(w[i]), int(lm[i])) for i in range(k)]
 
     def set_kernel_timing(self, enable: bool = True):
         _check(library().dsg_set_kernel_timing(self._h, 1 if enable else 0))

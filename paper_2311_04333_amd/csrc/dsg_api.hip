@@ -118,7 +118,7 @@ long long carve(int n, long long nnz, int t_cap, char* base, GraphDev* g) {
     long long o_ts = L.add(8 * ntiles), o_to = L.add(8 * ntiles), o_tb = L.add(24 * ntiles);
     long long o_rh = L.add(4 * 256 * rtiles);
     long long o_he = L.add(8LL * t_cap), o_hv = L.add(8LL * t_cap), o_hi = L.add(4LL * t_cap);
-    long long o_rd = L.add(4LL * t_cap), o_dg = L.add(8LL * t_cap);
+    long long o_rd = L.add(4LL * t_cap), o_dg = L.add(8LL * t_cap), o_hw = L.add(4LL * t_cap), o_hl = L.add(4LL * t_cap);
     const int rshift = dsg::bucket_shift(N);
     long long o_bkt = L.add(rshift >= 0 ? 4 * nnz : 0), o_bf = L.add(4 * dsg::BKT_MAX_NR);
     long long o_cb = L.add(4 * ((N + 7) / 8 + 1)), o_crb = L.add(4 * 16), o_crs = L.add(4 * (1 << 17));
@@ -166,6 +166,8 @@ long long carve(int n, long long nnz, int t_cap, char* base, GraphDev* g) {
         g->hist_i = reinterpret_cast<int*>(base + o_hi);
         g->rounds = reinterpret_cast<int*>(base + o_rd);
         g->digest = reinterpret_cast<unsigned long long*>(base + o_dg);
+        g->hist_w = reinterpret_cast<int*>(base + o_hw);
+        g->hist_lmax = reinterpret_cast<int*>(base + o_hl);
     }
     return L.total;
 }
@@ -513,6 +515,23 @@ dsg_status dsg_get_order(dsg_graph* g, int32_t* h_round, int32_t* h_pos, int32_t
         DSG_HIP(hipMemcpy(&r, g->d.rounds + (g->recorded - 1), sizeof(int), hipMemcpyDeviceToHost), "hipMemcpy(rounds)");
         *n_rounds = r;
     }
+    return DSG_OK;
+}
+
+dsg_status dsg_get_iter_bounds(dsg_graph* g, int32_t* h_width, int64_t* h_load_max, int32_t cap, int32_t* count) {
+    if (!g) return fail(DSG_EINVAL, "graph is NULL");
+    DSG_HIP(hipStreamSynchronize(g->ctx->stream), "hipStreamSynchronize");
+    const int k = cap < g->recorded ? cap : g->recorded;
+    if (k > 0) {
+        std::vector<int32_t> tmp((size_t)k);
+        if (h_width)
+            DSG_HIP(hipMemcpy(h_width, g->d.hist_w, 4 * (size_t)k, hipMemcpyDeviceToHost), "hipMemcpy(width)");
+        if (h_load_max) {
+            DSG_HIP(hipMemcpy(tmp.data(), g->d.hist_lmax, 4 * (size_t)k, hipMemcpyDeviceToHost), "hipMemcpy(lmax)");
+            for (int i = 0; i < k; i++) h_load_max[i] = tmp[(size_t)i];
+        }
+    }
+    if (count) *count = g->recorded;
     return DSG_OK;
 }
 

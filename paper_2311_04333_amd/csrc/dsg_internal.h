@@ -138,6 +138,8 @@ struct GraphDev {
     int* hist_i;
     int* rounds;
     unsigned long long* digest;
+    int* hist_w;     // per iteration: largest load increase (empirical width)
+    int* hist_lmax;  // per iteration: largest load after it
     int* bkt;
     unsigned int* bfill;
     int rshift;

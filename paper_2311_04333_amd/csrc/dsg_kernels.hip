@@ -1301,7 +1301,8 @@ __global__ __launch_bounds__(SCAN_BLK) void k_suffix_argmax(int n, const int* __
 __global__ __launch_bounds__(1024) void k_iter_end(const long long* __restrict__ tile_best, int ntiles, Ctl* ctl,
                                                    long long* __restrict__ hist_e, long long* __restrict__ hist_v,
                                                    int* __restrict__ hist_i, unsigned long long* __restrict__ digest,
-                                                   int* __restrict__ rounds, int slot, int nrounds_static) {
+                                                   int* __restrict__ rounds, int* __restrict__ hist_w,
+                                                   int* __restrict__ hist_lmax, int slot, int nrounds_static) {
     __shared__ Cand shc[1024 / WAVE];
     Cand best{-1, 1, 0x7FFFFFFFFFFFFFFFll};
     for (int b = threadIdx.x; b < ntiles; b += 1024) {
@@ -1314,6 +1315,8 @@ __global__ __launch_bounds__(1024) void k_iter_end(const long long* __restrict__
         hist_v[slot] = best.v;
         hist_i[slot] = (int)best.i;
         digest[slot] = 0;
+        hist_w[slot] = 0;
+        hist_lmax[slot] = 0;
         rounds[slot] = nrounds_static > 0 ? nrounds_static : ctl->nrounds;
         const int it = ctl->iters_done + 1;
         ctl->iters_done = it;
@@ -1334,17 +1337,31 @@ __global__ __launch_bounds__(1024) void k_iter_end(const long long* __restrict__
 __global__ __launch_bounds__(256) void k_finalize(int n, int* __restrict__ load, const int* __restrict__ inc,
                                                   const int* __restrict__ rnd, const int* __restrict__ order,
                                                   int* __restrict__ best_order, const Ctl* ctl,
-                                                  unsigned long long* __restrict__ digest_slot) {
+                                                  unsigned long long* __restrict__ digest_slot, int* __restrict__ w_slot,
+                                                  int* __restrict__ lmax_slot) {
     __shared__ unsigned long long sh[256 / WAVE];
+    __shared__ unsigned int shm[256 / WAVE];
     const bool improved = ctl->improved != 0;
     unsigned long long h = 0;
+    unsigned int wmax = 0, lmax = 0;  // loads and charges are non-negative
     for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
-        load[v] += inc[v];
+        const int c = inc[v];
+        const int l = load[v] + c;
+        load[v] = l;
+        wmax = max(wmax, (unsigned int)c);
+        lmax = max(lmax, (unsigned int)l);
         h += mix64(((unsigned long long)(unsigned int)v << 32) | (unsigned long long)(unsigned int)rnd[v]);
         if (improved) best_order[v] = order[v];
     }
     h = block_sum<256>(h, sh);
-    if (threadIdx.x == 0) atomicAdd(digest_slot, h);
+    // block maxima as minima of the complements: one atomic per block
+    const unsigned int bw = 0xFFFFFFFFu - block_min<256>(0xFFFFFFFFu - wmax, shm);
+    const unsigned int bl = 0xFFFFFFFFu - block_min<256>(0xFFFFFFFFu - lmax, shm);
+    if (threadIdx.x == 0) {
+        atomicAdd(digest_slot, h);
+        atomicMax(w_slot, (int)bw);
+        atomicMax(lmax_slot, (int)bl);
+    }
 }
 
 // =============================================================== BATCH
@@ -1803,10 +1820,10 @@ static hipError_t enqueue_alg3(const GraphDev& g, int slot, int nrounds_static, 
     k_gather_A<<<ntiles, SCAN_BLK, 0, s>>>(g.n, g.order, g.inc, g.A, g.tile_sum);
     k_suffix_top<<<1, 1024, 0, s>>>(g.tile_sum, g.tile_off, ntiles);
     k_suffix_argmax<<<ntiles, SCAN_BLK, 0, s>>>(g.n, g.A, g.tile_off, g.tile_best);
-    k_iter_end<<<1, 1024, 0, s>>>(g.tile_best, ntiles, g.ctl, g.hist_e, g.hist_v, g.hist_i, g.digest, g.rounds, slot,
-                                  nrounds_static);
+    k_iter_end<<<1, 1024, 0, s>>>(g.tile_best, ntiles, g.ctl, g.hist_e, g.hist_v, g.hist_i, g.digest, g.rounds,
+                                  g.hist_w, g.hist_lmax, slot, nrounds_static);
     k_finalize<<<grid_for(g.n, 256, 2048), 256, 0, s>>>(g.n, g.load, g.inc, g.rnd, g.order, g.best_order, g.ctl,
-                                                        g.digest + slot);
+                                                        g.digest + slot, g.hist_w + slot, g.hist_lmax + slot);
     return hipGetLastError();
 }
 

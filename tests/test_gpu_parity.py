@@ -249,3 +249,22 @@ def test_sort_coarse_rank_paths(dsg, ctx, name):
         g.run(5, (0, 1), "sort")
         assert_same(g, ref, f"sortcoarse/{name}/{coarse}")
         g.close()
+
+
+@pytest.mark.parametrize("name", ["K40", "star_3000", "isolated_mix", "config1", "ragged_4097", "rmat16"])
+def test_width_and_load_bounds(dsg, ctx, name):
+    """Per-iteration empirical width (largest load increase) and largest load equal the oracle's, for every
+    variant; the load bound rho* <= L_t / t is then the oracle's too."""
+    o, a = _bucket_cases()[name]
+    n = len(o) - 1
+    for variant, eps in VARIANTS:
+        if variant == "seq" and n > 16000:
+            continue
+        log(f"bounds case={name} variant={variant}")
+        g = dsg.Graph(ctx, o, a, t_cap=8).run(5, eps, variant)
+        st, ref = None, []
+        for _ in range(5):
+            st = oracle.run(o, a, 1, variant, eps, state=st)
+            ref.append((st.width[-1], int(st.loads.max()) if n > 0 else 0))
+        assert g.iter_bounds() == ref, f"{name}/{variant}: {g.iter_bounds()} vs {ref}"
+        g.close()
