@@ -66,46 +66,40 @@ __global__ void k_check_range(int n, long long nnz, const int* __restrict__ adj,
 
 // Full CSR check (DSG_VALIDATE): no self-loops, rows strictly increasing,
 // symmetric (u in row v  =>  v in row u, by binary search in row u).
-// Edge-parallel over the static item list (every vertex with edges, in id
-// order, so the concatenated edge index is the adjacency index): a block
-// stages one chunk's items in LDS and each thread finds its edges' rows by
-// binary search, so hub rows are spread over many threads.
-__global__ __launch_bounds__(SORT_BLK) void k_check_rows(long long nnz, int K, const int* __restrict__ siv,
-                                                         const int* __restrict__ sie, const int* __restrict__ scf,
-                                                         const int* __restrict__ scl, const int* __restrict__ off,
+// Edge-parallel, so hub rows are spread over many threads, and it needs
+// nothing but the (already checked) offsets: a block takes chunks of
+// SORT_CH consecutive adjacency entries, finds the rows holding the chunk's
+// first and last entry by binary search over all offsets, and each thread
+// finds its entries' rows by binary search within that range (a few KB of
+// offsets, cache-resident).  The row of entry x is the largest v with
+// off[v] <= x: it skips empty rows, and off[v + 1] > x holds since
+// off[n] = nnz > x.
+__device__ __forceinline__ int row_of_entry(const int* __restrict__ off, int lo, int hi, long long x) {
+    while (lo < hi) {
+        const int mid = lo + ((hi - lo + 1) >> 1);
+        if (off[mid] <= x) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(SORT_BLK) void k_check_rows(int n, long long nnz, const int* __restrict__ off,
                                                          const int* __restrict__ adj, Ctl* ctl) {
-    __shared__ int fe[SORT_CH];
-    __shared__ int vv[SORT_CH];
+    __shared__ int s_k[2];
     const long long nchunks = (nnz + SORT_CH - 1) / SORT_CH;
     for (long long c = blockIdx.x; c < nchunks; c += gridDim.x) {
         const long long x0 = c * SORT_CH, x1 = min(nnz, x0 + SORT_CH);
-        const int k0 = scf[c];
-        const int k1 = (c + 1 < nchunks) ? scl[c] : K - 1;
-        const int nitems = k1 - k0 + 1;
-        if (nitems < 1 || nitems > SORT_CH) {  // the item list is built from checked offsets
-            if (threadIdx.x == 0) {
-                atomicAdd(&ctl->err_count, 1);
-                ctl->err_code = ERR_INTERNAL;
-            }
-            return;
-        }
-        for (int j = threadIdx.x; j < nitems; j += SORT_BLK) {
-            fe[j] = sie[k0 + j];
-            vv[j] = siv[k0 + j];
-        }
+        if (threadIdx.x < 2) s_k[threadIdx.x] = row_of_entry(off, 0, n - 1, threadIdx.x == 0 ? x0 : x1 - 1);
         __syncthreads();
+        const int k0 = s_k[0], k1 = s_k[1];
         for (long long x = x0 + threadIdx.x; x < x1; x += SORT_BLK) {
-            int lo = 0, hi = nitems - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (fe[mid] <= x) lo = mid; else hi = mid - 1;
-            }
-            const int v = vv[lo];
+            const int v = row_of_entry(off, k0, k1, x);
             const int u = adj[x];
             int code = ERR_NONE;
-            if (u == v) {
+            if (u < 0 || u >= n) {  // callers may launch this before reading the range check's verdict
+                code = ERR_ADJ_RANGE;
+            } else if (u == v) {
                 code = ERR_SELF_LOOP;
-            } else if (x > fe[lo] && adj[x - 1] >= u) {
+            } else if (x > off[v] && adj[x - 1] >= u) {
                 code = ERR_ROW_ORDER;
             } else {
                 int l = off[u], h = off[u + 1] - 1;
@@ -126,7 +120,7 @@ __global__ __launch_bounds__(SORT_BLK) void k_check_rows(long long nnz, int K, c
                 ctl->err_vertex = v;
             }
         }
-        __syncthreads();
+        __syncthreads();  // s_k is rewritten for the next chunk
     }
 }
 
@@ -1766,11 +1760,11 @@ hipError_t launch_check_range(const GraphDev& g, hipStream_t s) {
 }
 
 hipError_t launch_check_rows(const GraphDev& g, hipStream_t s) {
-    // needs the static item list (launch_build_static_items) and n_items
+    // needs n, nnz, off, adj and ctl only; offsets and entries already checked
     if (g.nnz == 0) return hipSuccess;
     const long long nchunks = (g.nnz + SORT_CH - 1) / SORT_CH;
     const int grid = (int)(nchunks < 8192 ? nchunks : 8192);
-    k_check_rows<<<grid, SORT_BLK, 0, s>>>(g.nnz, g.n_items, g.siv, g.sie, g.scf, g.scl, g.off, g.adj, g.ctl);
+    k_check_rows<<<grid, SORT_BLK, 0, s>>>(g.n, g.nnz, g.off, g.adj, g.ctl);
     return hipGetLastError();
 }
 

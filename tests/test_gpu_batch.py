@@ -11,7 +11,7 @@ import pytest
 
 import graphgen
 import oracle
-from gpu_helpers import assert_same, log
+from gpu_helpers import assert_same, bad_csrs, log
 
 pytestmark = pytest.mark.gpu
 
@@ -104,3 +104,20 @@ def test_batch_history_guard(dsg, ctx):
     with pytest.raises(dsg.DsgError) as ei:
         b.run()
     assert ei.value.status == -1
+
+
+def test_batch_validation(dsg, ctx):
+    """DSG_VALIDATE on a batch: valid graphs (empty rows, hubs spanning many chunks) pass and match the oracle,
+    and every broken CSR property anywhere in the batch is DSG_EINVAL."""
+    good = [graphgen.rmat(5, 14, 16 << 14), graphgen.from_edges(6, [(0, 5), (2, 5)]),
+            graphgen.from_edges(3, []), graphgen.chunglu(7, 50_000, 2.1, 20.0, 8000.0)]
+    b = dsg.Batch(ctx, good, T=3, eps=(1, 10), t_cap=4, validate=True).run()
+    for i, (o, a) in enumerate(good):
+        ref = oracle.run(o, a, 3, "peel", (1, 10))
+        assert b.best(i) == tuple(int(x) for x in ref.best), i
+    b.close()
+    for name, (o, a) in bad_csrs().items():
+        log(f"batch validation case={name}")
+        with pytest.raises(dsg.DsgError) as ei:
+            dsg.Batch(ctx, [good[1], (o, a)], T=2, eps=(1, 10), t_cap=2, validate=True)
+        assert ei.value.status == -1, name

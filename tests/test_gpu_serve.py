@@ -13,7 +13,7 @@ import pytest
 
 import graphgen
 import oracle
-from gpu_helpers import log
+from gpu_helpers import bad_csrs, log
 
 pytestmark = pytest.mark.gpu
 
@@ -181,4 +181,18 @@ def test_serve_registered_graphs(dsg, ctx):
             assert all(r["digests"] == rs[0]["digests"] and r["best"] == rs[0]["best"] for r in rs), key
     finally:
         srv.stop()
+        srv.close()
+
+
+def test_serve_register_validation(dsg, ctx):
+    """Registering with validation rejects every broken CSR property (DSG_EINVAL) and accepts valid graphs."""
+    srv = dsg.Server(ctx, 1 << 28, ring_size=8)
+    try:
+        for name, (o, a) in bad_csrs().items():
+            log(f"register validation case={name}")
+            with pytest.raises(dsg.DsgError) as ei:
+                srv.register(o, a, validate=True)
+            assert ei.value.status == -1, name
+        assert srv.register(*graphgen.rmat(5, 14, 16 << 14), validate=True) == 0
+    finally:
         srv.close()
