@@ -156,6 +156,21 @@ def test_reset(dsg, ctx):
     assert_same(g, oracle.run(o, a, 3, "sort"), "reset")
 
 
+@pytest.mark.parametrize("variant", ["peel", "sort", "seq"])
+def test_kernel_timing(dsg, ctx, variant):
+    """Kernel timing (events around each iteration's dominant kernel) changes no result and counts one launch per
+    iteration of the last run; with timing off it reports nothing."""
+    o, a = graphgen.er_planted(21, 3000, 24000, 40, 1, 2)
+    ref = oracle.run(o, a, 4, variant, (1, 10))
+    g = dsg.Graph(ctx, o, a, t_cap=8).set_kernel_timing(True).run(4, (1, 10), variant)
+    ms, launches = g.kernel_timing()
+    assert launches == 4 and ms > 0.0
+    assert_same(g, ref, f"timed {variant}")
+    g.set_kernel_timing(False).run(1, (1, 10), variant)
+    assert g.kernel_timing() == (0.0, 0)
+    assert_same(g, oracle.run(o, a, 5, variant, (1, 10)), f"untimed {variant} after timed")
+
+
 def test_deterministic(dsg, ctx):
     """Atomics only commute integers: two runs are bit-identical."""
     o, a = graphgen.rmat(9, 14, 16 << 14)
