@@ -147,6 +147,7 @@ struct GraphDev {
     unsigned int* cb;  // SORT coarse ranks
     int* cr_bounds;    // first position of each coarse class
     int* cr_samp;      // degrees at the sampled positions
+    long long* cr_tsum;  // sampled degree mass per tile of 1024 samples
     int n_items;  // vertices with degree > 0
     int max_deg;
 };

@@ -1037,32 +1037,74 @@ __global__ void k_sort_pos(int n, const int* __restrict__ order, int* __restrict
     }
 }
 
-__global__ __launch_bounds__(1024) void k_coarse_bounds(int n, int sshift, const int* __restrict__ sdeg,
-                                                        int* __restrict__ bounds) {
-    __shared__ long long sh[1024 / WAVE];
-    constexpr int PER = CR_MAX_SAMPLES / 1024;
+// Class bounds in two launches: k_coarse_tiles sums the sampled degree
+// mass per tile of 1024 samples (one block per tile, coalesced), then
+// k_coarse_bounds (one block) scans the tile sums and, for each class c,
+// one wave scans the tile holding threshold c/16 of the total mass to find
+// the crossing sample.
+constexpr int CR_TILE = 1024;
+constexpr int CR_MAX_TILES = CR_MAX_SAMPLES / CR_TILE;
+static_assert(CR_MAX_TILES <= 1024 && (CR_CLASSES - 1) * WAVE <= 1024, "one block scans the tiles, a wave per class");
+
+__global__ __launch_bounds__(CR_TILE) void k_coarse_tiles(int n, int sshift, const int* __restrict__ sdeg,
+                                                          long long* __restrict__ tsum) {
+    __shared__ long long sh[CR_TILE / WAVE];
     const int S = (int)(((long long)n + (1LL << sshift) - 1) >> sshift);
-    const int s0 = (int)threadIdx.x * PER;
-    long long mine = 0;
-    for (int k = 0; k < PER; k++)
-        if (s0 + k < S) mine += sdeg[s0 + k];
+    const int i = (int)blockIdx.x * CR_TILE + (int)threadIdx.x;
+    const long long t = block_sum<CR_TILE>((long long)(i < S ? sdeg[i] : 0), sh);
+    if (threadIdx.x == 0) tsum[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(1024) void k_coarse_bounds(int n, int sshift, const int* __restrict__ sdeg,
+                                                        const long long* __restrict__ tsum, int* __restrict__ bounds) {
+    __shared__ long long sh[1024 / WAVE];
+    __shared__ long long s_tex[CR_MAX_TILES];
+    __shared__ long long s_tsum[CR_MAX_TILES];
+    const int S = (int)(((long long)n + (1LL << sshift) - 1) >> sshift);
+    const int nt = (S + CR_TILE - 1) / CR_TILE;
+    const long long v = (int)threadIdx.x < nt ? tsum[threadIdx.x] : 0;
     long long tot;
-    long long run = block_excl_scan<1024>(mine, &tot, sh);
-    if (threadIdx.x < CR_CLASSES) bounds[threadIdx.x] = threadIdx.x == 0 ? 0 : n;
-    __syncthreads();
-    if (tot == 0) return;
-    long long th[CR_CLASSES];
-#pragma unroll
-    for (int c = 1; c < CR_CLASSES; c++) th[c] = (tot * c) / CR_CLASSES;
-    for (int k = 0; k < PER && s0 + k < S; k++) {
-        const long long d = sdeg[s0 + k];
-        // classes whose threshold lies in (run, run + d]: exactly one sample
-        // crosses each threshold, since the running mass only grows
-#pragma unroll
-        for (int c = 1; c < CR_CLASSES; c++)
-            if (run < th[c] && th[c] <= run + d) bounds[c] = (s0 + k) << sshift;
-        run += d;
+    const long long ex = block_excl_scan<1024>(v, &tot, sh);
+    if ((int)threadIdx.x < nt) {
+        s_tex[threadIdx.x] = ex;
+        s_tsum[threadIdx.x] = v;
     }
+    __syncthreads();
+    // class c starts at the first sample whose running mass reaches
+    // floor(tot * c / 16); a zero threshold (or no mass) leaves the class empty
+    const int c = (int)threadIdx.x / WAVE + 1;
+    const int lane = (int)threadIdx.x & (WAVE - 1);
+    if (threadIdx.x == 0) bounds[0] = 0;
+    if (c >= CR_CLASSES) return;
+    const long long th = (tot * c) / CR_CLASSES;
+    int bound = n;
+    if (th > 0) {
+        // the tile whose mass interval (ex, ex + sum] holds th: exactly one
+        int tile = -1;
+        for (int t = lane; t < nt; t += WAVE)
+            if (s_tex[t] < th && th <= s_tex[t] + s_tsum[t]) tile = t;
+        for (int o = WAVE / 2; o > 0; o >>= 1) tile = max(tile, __shfl_xor(tile, o, WAVE));
+        // lane l scans samples [l*16, l*16 + 16) of the tile
+        constexpr int PL = CR_TILE / WAVE;
+        const int s0 = tile * CR_TILE + lane * PL;
+        int d[PL];
+        long long mine = 0;
+#pragma unroll
+        for (int k = 0; k < PL; k++) {
+            d[k] = s0 + k < S ? sdeg[s0 + k] : 0;
+            mine += d[k];
+        }
+        long long run = s_tex[tile] + wave_incl_scan(mine) - mine;
+        int hit = -1;
+#pragma unroll
+        for (int k = 0; k < PL; k++) {
+            if (run < th && th <= run + d[k]) hit = s0 + k;
+            run += d[k];
+        }
+        for (int o = WAVE / 2; o > 0; o >>= 1) hit = max(hit, __shfl_xor(hit, o, WAVE));
+        if (hit >= 0) bound = hit << sshift;
+    }
+    if (lane == 0) bounds[c] = bound;
 }
 
 __global__ void k_coarse_pack(int n, const int* __restrict__ pos, const int* __restrict__ bounds,
@@ -1887,7 +1929,9 @@ hipError_t enqueue_iter_sort(const GraphDev& g, int slot, int key_bits, int sort
     k_sort_pos<<<grid_for(g.n, 256, 2048), 256, 0, s>>>(g.n, g.order, g.rnd, g.inc, g.off,
                                                          coarse ? g.cr_samp : nullptr, sshift);
     if (coarse) {
-        k_coarse_bounds<<<1, 1024, 0, s>>>(g.n, sshift, g.cr_samp, g.cr_bounds);
+        const int ntiles = (int)((((long long)g.n + (1LL << sshift) - 1) >> sshift) + CR_TILE - 1) / CR_TILE;
+        k_coarse_tiles<<<ntiles, CR_TILE, 0, s>>>(g.n, sshift, g.cr_samp, g.cr_tsum);
+        k_coarse_bounds<<<1, 1024, 0, s>>>(g.n, sshift, g.cr_samp, g.cr_tsum, g.cr_bounds);
         k_coarse_pack<<<grid_for((g.n + 7) / 8, 256, 2048), 256, 0, s>>>(g.n, g.rnd, g.cr_bounds, g.cb);
     }
     SweepArgs a{};
