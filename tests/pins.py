@@ -11,7 +11,8 @@ Sources of the facts:
     two disjoint cliques, the empty graph, a triangle and a path under
     round-synchronous peeling);
   * exhaustive enumeration (``oracle.brute``) for the exact optimum rho* on
-    graphs with n <= 14;
+    graphs with n <= 14, and Goldberg's min-cut construction (``exact_density``,
+    scipy's max-flow as the step) on graphs of thousands of vertices;
   * Charikar's 2-approximation for the first iteration (Section 3.2), and
     the (1+eps)-relaxed form of it for round-synchronous peeling;
   * the dual bound rho* <= max_v l(v) / T: every edge of S* is charged to an
@@ -214,6 +215,52 @@ def pin_bounds_against_brute_force(lib):
                 if T == 1 and var == "peel":
                     q, p = eps[1], eps[0]
                     assert 2 * (q + p) * be * vs >= q * es * bv, "relaxed Charikar bound"
+
+
+_MEDIUM_EXACT = {}
+
+
+def _medium_graphs_exact():
+    """Medium graphs with rho* from the max-flow tool (exact_density), cached: config 1 (ER n=2000 plus a planted
+    50-set), R-MAT scale 11, a Chung-Lu graph and a small planted ER graph."""
+    from exact_density import densest_exact
+
+    if not _MEDIUM_EXACT:
+        for name, (o, a) in [("config1", graphgen.config1(1)), ("rmat11", graphgen.rmat(3, 11, 16 << 11)),
+                             ("chunglu3000", graphgen.chunglu(5, 3000, 2.1, 10.0, 300.0)),
+                             ("planted500", graphgen.er_planted(7, 500, 3000, 30, 1, 3))]:
+            r, _ = densest_exact(o, a)
+            _MEDIUM_EXACT[name] = (o, a, r.numerator, r.denominator)
+    return _MEDIUM_EXACT
+
+
+def pin_bounds_against_exact_medium(lib):
+    """The brute-force bounds carried to graphs of thousands of vertices, with rho* = es/vs from Goldberg's
+    min-cut construction (exact_density, itself checked against brute force):
+      rho_best <= rho* <= max l / T for every variant and T (every edge of S* is charged inside S*);
+      iteration 1: SEQ rho_best >= rho*/2 (Charikar), PEEL rho_best >= rho* / (2 (1 + eps));
+      the empirical width of every iteration is at least ceil(rho*);
+      k_max / 2 <= rho* <= k_max (the k_max-core has minimum degree k_max; every vertex of S* has at least
+      rho* neighbours in S*, so S* lies in the ceil(rho*)-core).
+    Sequential Greedy++ converges to rho* (observed here within 20 iterations on every graph)."""
+    for name, (o, a, es, vs) in _medium_graphs_exact().items():
+        _, kmax = oracle.coreness(o, a, lib=lib)
+        assert kmax * vs <= 2 * es and es <= kmax * vs, (name, kmax, es, vs)
+        for var, eps in (("seq", (0, 1)), ("peel", (1, 10)), ("sort", (0, 1))):
+            st = None
+            for T in range(1, 21):
+                st = oracle.run(o, a, 1, var, eps, state=st, lib=lib)
+                be, bv = int(st.best[0]), int(st.best[1])
+                assert be * vs <= es * bv, (name, var, T, "best exceeds the optimum")
+                assert es * T <= int(st.loads.max()) * vs, (name, var, T, "dual bound violated")
+                assert -(-es // vs) <= st.width[-1], (name, var, T, "width below ceil(rho*)")
+                if T == 1 and var == "seq":
+                    assert 2 * be * vs >= es * bv, (name, "Charikar bound")
+                if T == 1 and var == "peel":
+                    q, p = eps[1], eps[0]
+                    assert 2 * (q + p) * be * vs >= q * es * bv, (name, "relaxed Charikar bound")
+            if var == "seq":
+                assert int(st.best[0]) * vs == es * int(st.best[1]), (name, st.best[:2], (es, vs))
 
 
 def pin_convergence(lib):

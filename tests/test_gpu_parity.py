@@ -171,6 +171,29 @@ def test_kernel_timing(dsg, ctx, variant):
     assert_same(g, oracle.run(o, a, 5, variant, (1, 10)), f"untimed {variant} after timed")
 
 
+@pytest.mark.parametrize("variant", ["peel", "sort", "seq"])
+def test_bounds_against_exact_density(dsg, ctx, variant):
+    """Independent of the oracle: on config 1 and R-MAT scale 11 the GPU's best density never exceeds the exact
+    rho* (Goldberg's min cut), rho* <= max load / T holds after every iteration, and sequential Greedy++
+    reaches rho* within 20 iterations."""
+    from exact_density import densest_exact
+
+    eps = (1, 10) if variant == "peel" else (0, 1)
+    for name, (o, a) in [("config1", graphgen.config1(1)), ("rmat11", graphgen.rmat(3, 11, 16 << 11))]:
+        r, _ = densest_exact(o, a)
+        es, vs = r.numerator, r.denominator
+        g = dsg.Graph(ctx, o, a, t_cap=20)
+        for T in range(1, 21):
+            g.run(1, eps, variant)
+            be, bv = g.best()[:2]
+            assert be * vs <= es * bv, (name, T)
+            assert es * T <= int(g.loads().max()) * vs, (name, T)
+        if variant == "seq":
+            assert be * vs == es * bv, (name, (be, bv), (es, vs))
+        log(f"{name} {variant}: best {be}/{bv} vs rho* {es}/{vs}")
+        g.close()
+
+
 def test_deterministic(dsg, ctx):
     """Atomics only commute integers: two runs are bit-identical."""
     o, a = graphgen.rmat(9, 14, 16 << 14)
