@@ -6,11 +6,12 @@
 //       PEEL -- round-synchronous (1+eps)-of-minimum peeling, the parallel
 //               ordering of Section 3.3 (k_peel_init + k_peel_rounds);
 //       SORT -- sort by start-of-iteration load, Sections 3.2/3.3 (radix sort
-//               + k_sort_pos + k_sweep_sort);
+//               + k_sort_pos + coarse classes k_coarse_tiles/bounds/pack
+//               + k_sweep_sort);
 //   * Algorithm 3 (density and load computation): each edge charges its
 //     earlier endpoint (owner-computes sweep), suffix sums over positions, the
 //     densest suffix as an exact rational, loads += charges (k_gather_A,
-//     k_tile_sums, k_suffix_argmax, k_iter_end, k_finalize).
+//     k_suffix_top, k_suffix_argmax, k_iter_end, k_finalize).
 // All arithmetic is integer.  Device loads are int32; the host guarantees
 // (iterations + 1) * max_degree < 2^31 so loads and priorities cannot wrap.
 #include "dsg_device.h"
