@@ -19,7 +19,10 @@ constexpr int PEEL_MARK = 1024;    // PEEL chunk markers are written per 1024 ed
 // about one coarse chunk per block of the grid)
 constexpr long long PEEL_DEFAULT_COARSE_MIN_E = 1LL << 20;
 constexpr int SORT_BLK = 512;      // threads per block of the SORT sweep
-constexpr int SORT_CH = 4096;      // edges per SORT sweep chunk
+// edges per SORT sweep chunk: at 2048 a block's LDS is 40 KB and four blocks
+// (8 waves per SIMD) share a CU; at 4096 (80 KB) only two did, and the SORT
+// iteration on R-MAT scale 22 took 26% longer
+constexpr int SORT_CH = 2048;
 constexpr int MIN_CH = PEEL_MARK < SORT_CH ? PEEL_MARK : SORT_CH;  // finest chunk-marker granularity
 constexpr int SEQ_BLK = 1024;      // threads of the single SEQ block
 constexpr int SEQ_MAX_N = 16000;   // SEQ keeps n priorities in LDS (< 64 KB)
