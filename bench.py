@@ -81,7 +81,10 @@ def main():
     ap.add_argument("--plain-sample", type=int, default=256, help="graphs of the mix timed on the plain path")
     ap.add_argument("--T", type=int, default=20)
     ap.add_argument("--scale", type=int, default=22)
-    ap.add_argument("--cpu-iters", type=int, default=2, help="oracle iterations timed for cpu_baseline (0 = skip)")
+    ap.add_argument("--cpu-iters", type=int, default=8,
+                    help="single graph: oracle iterations timed for cpu_baseline (0 = skip)")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="batch: oracle runs of whole graphs (T iterations each) until this much CPU time (0 = skip)")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (calibrates HBM byte counters)")
@@ -278,18 +281,23 @@ def bench_batch(args):
         f"{graphs_per_s / plain_gps:.1f}x; alone == batched on {min(32, len(idx))} graphs: {same}")
 
     cpu = None
-    if args.cpu_iters > 0:
+    if args.cpu_seconds > 0:
         import oracle
 
-        cs = idx[:: max(1, len(idx) // 8)][:8]
+        # whole graphs of the same systematic sample, T iterations each, until the time budget is spent
         tc = time.perf_counter()
-        for i in cs:
-            oracle.run(*graphs[i], args.cpu_iters, "peel", eps)
+        done, m_c = 0, 0
+        for i in idx:
+            oracle.run(*graphs[i], T, "peel", eps)
+            done += 1
+            m_c += len(graphs[i][1]) // 2
+            if time.perf_counter() - tc >= args.cpu_seconds:
+                break
         cpu_s = time.perf_counter() - tc
-        m_c = sum(len(graphs[i][1]) // 2 for i in cs)
-        cpu = {"value": 2.0 * m_c * args.cpu_iters / cpu_s, "unit": "edge-visits/s", "cores": 1, "kind": "oracle",
-               "sample": f"{len(cs)} graphs of the mix x {args.cpu_iters} iterations ({cpu_s:.1f} s); "
-                         f"graphs/s at T={T} extrapolates to {len(cs) * args.cpu_iters / T / cpu_s:.3f}"}
+        cpu = {"value": 2.0 * m_c * T / cpu_s, "unit": "edge-visits/s", "cores": 1, "kind": "oracle",
+               "sample": f"the first {done} graphs of the plain-path sample, T={T} each, in {cpu_s:.1f} s: "
+                         f"{done / cpu_s:.2f} graphs/s"}
+        log(f"cpu oracle: {done} graphs x {T} iterations in {cpu_s:.1f}s")
     line = {
         "metric": "graphs/s, batched persistent launch (edge-visits/s beside it); batched vs plain",
         "value": graphs_per_s,
