@@ -1,0 +1,97 @@
+"""Seeded random sweep: many small graphs of every generator family, random T and eps, all three orderings and one
+batch, each against the oracle bit for bit.
+
+The hand-picked parity cases cover the known edge cases; this sweep is for the unknown ones (ties between rounds,
+empty rounds, isolated vertices, one-vertex frontiers, hubs next to sparse tails) at sizes from one vertex to a few
+thousand, so that every output (loads, per-iteration densities and indices, best pair and set, order digests, round
+counts, last-iteration rounds and positions) is compared on a broad family.
+"""
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+from gpu_helpers import assert_same, log
+
+pytestmark = pytest.mark.gpu
+
+EPS = [(0, 1), (1, 10), (1, 2), (3, 1), (1, 1000)]
+
+
+def random_graphs(seed: int, count: int):
+    """(name, offsets, adj, T, eps) from a seeded mix of generator families."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        n = int(np.exp(rng.uniform(0.0, np.log(3000.0))))
+        kind = i % 5
+        s = int(rng.integers(1, 1 << 30))
+        if kind == 0:
+            o, a = graphgen.gnp(s, max(n, 1), int(rng.integers(1, 8)), max(n, 8))
+        elif kind == 1:
+            m = int(rng.integers(0, min(4 * n, n * (n - 1) // 2) + 1))
+            k = int(rng.integers(0, min(n, 40) + 1))
+            o, a = graphgen.er_planted(s, n, m, k, 1, 2)
+        elif kind == 2:
+            scale = max(1, int(np.ceil(np.log2(max(n, 2)))))
+            o, a = graphgen.rmat(s, scale, int(rng.integers(1, 12)) << scale, n=n)
+        elif kind == 3:
+            mean = float(rng.uniform(1.0, 12.0))
+            o, a = graphgen.chunglu(s, max(n, 2), 2.1, mean, max(mean, float(n // 4)))
+        else:
+            # a clique, a star and a path glued into one graph: ties and one-vertex rounds
+            c = int(rng.integers(2, 12))
+            st = int(rng.integers(1, 30))
+            pl = int(rng.integers(1, 30))
+            edges = [(x, y) for x in range(c) for y in range(x + 1, c)]
+            edges += [(c, c + 1 + j) for j in range(st)]
+            base = c + 1 + st
+            edges += [(base + j, base + j + 1) for j in range(pl)]
+            edges += [(0, c), (c + st, base)]
+            o, a = graphgen.from_edges(base + pl + 1, edges)
+        T = int(rng.integers(1, 7))
+        eps = EPS[int(rng.integers(0, len(EPS)))]
+        out.append((f"g{i}_kind{kind}_n{len(o) - 1}_m{len(a) // 2}_T{T}_eps{eps[0]}/{eps[1]}", o, a, T, eps))
+    return out
+
+
+@pytest.fixture(scope="module")
+def dsg():
+    import torch
+
+    import paper_2311_04333_amd as dsg
+
+    assert torch.cuda.is_available()
+    return dsg
+
+
+@pytest.fixture(scope="module")
+def ctx(dsg):
+    c = dsg.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("seed", [101, 202, 404, 505])
+def test_random_graphs_all_orderings(dsg, ctx, seed):
+    for name, o, a, T, eps in random_graphs(seed, 60):
+        for variant in ("peel", "sort", "seq"):
+            e = eps if variant == "peel" else (0, 1)
+            log(f"random sweep {name} {variant}")
+            g = dsg.Graph(ctx, o, a, t_cap=T)
+            g.run(T, e, variant)
+            assert_same(g, oracle.run(o, a, T, variant, e), f"{name} {variant}")
+            g.close()
+
+
+def test_random_graphs_one_batch(dsg, ctx):
+    graphs = random_graphs(303, 60)
+    b = dsg.Batch(ctx, [(o, a) for _, o, a, _, _ in graphs], T=[T for *_, T, _ in graphs],
+                  eps=[eps for *_, eps in graphs], t_cap=8).run()
+    for i, (name, o, a, T, eps) in enumerate(graphs):
+        ref = oracle.run(o, a, T, "peel", eps)
+        assert np.array_equal(b.loads(i), ref.loads), name
+        assert b.best(i) == tuple(int(x) for x in ref.best), name
+        assert [(e, v) for e, v, _ in b.iter_densities(i)] == ref.hist, name
+        assert b.digests(i) == (ref.digests, ref.rounds), name
+    b.close()
