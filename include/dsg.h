@@ -182,6 +182,22 @@ dsg_status dsg_set_peel_tuning(dsg_graph* g, int64_t bucket_min_edges, int64_t c
  * NULL graph. */
 dsg_status dsg_set_sort_tuning(dsg_graph* g, int32_t coarse_ranks);
 
+/* Optional graph replay (off by default).  When on, dsg_run captures the
+ * launches of its T iterations once into a HIP graph (on a private stream of
+ * the graph object, at the default priority) and launches the instantiated
+ * graph on the context's stream.  A later dsg_run with the same T, eps,
+ * variant, history position and load bound (as after dsg_reset), and the
+ * same tuning, replays it without re-issuing the launches; any other call
+ * captures anew.  Results are the same as without replay.  The captured
+ * launches hold no memset nodes.  If the runtime refuses to capture a launch,
+ * dsg_run runs eagerly and keeps doing so until replay is switched on again.
+ * Kernel timing (dsg_set_kernel_timing) runs eagerly. */
+dsg_status dsg_set_graph_replay(dsg_graph* g, int32_t enable);
+
+/* *state = 1 when a captured run is cached, 0 when replay is off or nothing
+ * is captured yet, -1 when capture was refused (runs are eager). */
+dsg_status dsg_get_graph_replay(dsg_graph* g, int32_t* state);
+
 /* Optional per-launch timing of each iteration's dominant kernel (the PEEL
  * round loop, the SORT sweep, the SEQ peel): HIP events are recorded on the
  * graph's stream right before and after every such launch of later dsg_run

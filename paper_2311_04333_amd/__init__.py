@@ -56,6 +56,8 @@ SIGNATURES = [
                                    _P, _P, _P, _P]),
     ("dsg_set_peel_tuning", ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int64]),
     ("dsg_set_sort_tuning", ctypes.c_int, [_P, _I32]),
+    ("dsg_set_graph_replay", ctypes.c_int, [_P, _I32]),
+    ("dsg_get_graph_replay", ctypes.c_int, [_P, _P]),
     ("dsg_set_kernel_timing", ctypes.c_int, [_P, _I32]),
     ("dsg_get_kernel_timing", ctypes.c_int, [_P, _P, _P]),
     ("dsg_batch_workspace_bytes", ctypes.c_int, [_P, _I32, _I32, _P]),
@@ -265,6 +267,17 @@ class Graph:
         _check(library().dsg_get_iter_bounds(self._h, w.ctypes.data, lm.ctypes.data, self.t_cap, ctypes.addressof(cnt)))
         k = min(cnt.value, self.t_cap)
         return [(int(w[i]), int(lm[i])) for i in range(k)]
+
+    def set_graph_replay(self, enable: bool = True):
+        """Capture a run's launches into a HIP graph and replay it for repeated runs with the same parameters."""
+        _check(library().dsg_set_graph_replay(self._h, 1 if enable else 0))
+        return self
+
+    def graph_replay_state(self) -> int:
+        """1 = a captured run is cached, 0 = none (or replay off), -1 = capture refused (eager runs)."""
+        st = ctypes.c_int32()
+        _check(library().dsg_get_graph_replay(self._h, ctypes.addressof(st)))
+        return st.value
 
     def set_kernel_timing(self, enable: bool = True):
         _check(library().dsg_set_kernel_timing(self._h, 1 if enable else 0))

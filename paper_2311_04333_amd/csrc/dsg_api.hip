@@ -48,6 +48,14 @@ struct dsg_graph {
     long long coarse_min_e;        // ... and coarse sweep chunks; -1 = default
     int sort_coarse;               // SORT coarse ranks: -1 = by size, 0 = off, 1 = on
     int peel_mono;                 // internal: monotone round thresholds (Coreness by buckets)
+    // graph replay (dsg_set_graph_replay): the launches of one dsg_run are
+    // captured on a private stream into a HIP graph, which later calls with
+    // the same key replay on the context's stream
+    bool replay;
+    int replay_state;              // 1 = a run is captured, 0 = none yet, -1 = capture refused (eager from then on)
+    hipStream_t cap_stream;
+    hipGraphExec_t gexec;
+    long long gkey[10];
 };
 
 struct dsg_batch {
@@ -345,28 +353,73 @@ dsg_status dsg_run(dsg_graph* g, int32_t T, int32_t eps_num, int32_t eps_den, ds
         }
     }
     g->klaunches = 0;
-    DSG_HIP(hipEventRecord(g->ev0, s), "hipEventRecord");
-    for (int t = 0; t < T; t++) {
-        const int slot = g->recorded + t;
-        hipEvent_t ea = g->ktime ? g->kev[2 * t] : nullptr;
-        hipEvent_t eb = g->ktime ? g->kev[2 * t + 1] : nullptr;
-        hipError_t e;
-        if (variant == DSG_PEEL) {
-            e = dsg::enqueue_iter_peel(g->d, slot, eps_num, eps_den, g->ctx->peel_grid, g->bkt_min_e,
-                                       g->coarse_min_e >= 0 ? g->coarse_min_e : dsg::PEEL_DEFAULT_COARSE_MIN_E,
-                                       g->peel_mono, s, ea, eb);
-        } else if (variant == DSG_SORT) {
-            long long bound = g->load_bound + (long long)t * (long long)g->d.max_deg;
-            int bits = 0;
-            while (bits < 31 && (bound >> bits) != 0) bits++;
-            const bool coarse = g->sort_coarse > 0 ||
-                                (g->sort_coarse < 0 && g->d.n >= dsg::SORT_COARSE_MIN_N && g->d.n <= dsg::SORT_COARSE_MAX_N);
-            e = dsg::enqueue_iter_sort(g->d, slot, bits, g->ctx->sort_grid, coarse && g->d.n < (1 << 26), s, ea, eb);
-        } else {
-            e = dsg::enqueue_iter_seq(g->d, slot, s, ea, eb);
+    // every launch of the T iterations, on stream `qs` (`timed`: events around
+    // each iteration's dominant kernel)
+    auto enqueue_run = [&](hipStream_t qs, bool timed) -> hipError_t {
+        for (int t = 0; t < T; t++) {
+            const int slot = g->recorded + t;
+            hipEvent_t ea = timed ? g->kev[2 * t] : nullptr;
+            hipEvent_t eb = timed ? g->kev[2 * t + 1] : nullptr;
+            hipError_t e;
+            if (variant == DSG_PEEL) {
+                e = dsg::enqueue_iter_peel(g->d, slot, eps_num, eps_den, g->ctx->peel_grid, g->bkt_min_e,
+                                           g->coarse_min_e >= 0 ? g->coarse_min_e : dsg::PEEL_DEFAULT_COARSE_MIN_E,
+                                           g->peel_mono, qs, ea, eb);
+            } else if (variant == DSG_SORT) {
+                long long bound = g->load_bound + (long long)t * (long long)g->d.max_deg;
+                int bits = 0;
+                while (bits < 31 && (bound >> bits) != 0) bits++;
+                const bool coarse =
+                    g->sort_coarse > 0 ||
+                    (g->sort_coarse < 0 && g->d.n >= dsg::SORT_COARSE_MIN_N && g->d.n <= dsg::SORT_COARSE_MAX_N);
+                e = dsg::enqueue_iter_sort(g->d, slot, bits, g->ctx->sort_grid, coarse && g->d.n < (1 << 26), qs,
+                                           ea, eb);
+            } else {
+                e = dsg::enqueue_iter_seq(g->d, slot, qs, ea, eb);
+            }
+            if (e != hipSuccess) return e;
+            if (timed) g->klaunches++;
         }
+        return hipSuccess;
+    };
+    DSG_HIP(hipEventRecord(g->ev0, s), "hipEventRecord");
+    bool launched = false;
+    if (g->replay && !g->ktime && g->replay_state >= 0 && T > 0) {
+        // everything the launches depend on besides the device state
+        const long long key[10] = {T, eps_num, eps_den, (long long)variant, g->recorded, g->load_bound,
+                                   g->bkt_min_e, g->coarse_min_e, g->sort_coarse, g->peel_mono};
+        if (!(g->gexec && memcmp(key, g->gkey, sizeof key) == 0)) {
+            hipGraph_t graph = nullptr;
+            hipGraphExec_t ex = nullptr;
+            hipError_t e = g->cap_stream ? hipSuccess : hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking);
+            if (e == hipSuccess) e = hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                const hipError_t eq = enqueue_run(g->cap_stream, false);
+                e = hipStreamEndCapture(g->cap_stream, &graph);  // always ends the capture
+                if (eq != hipSuccess) e = eq;
+            }
+            if (e == hipSuccess && graph) e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+            if (graph) (void)hipGraphDestroy(graph);
+            if (e == hipSuccess && ex) {
+                if (g->gexec) (void)hipGraphExecDestroy(g->gexec);
+                g->gexec = ex;
+                memcpy(g->gkey, key, sizeof key);
+                g->replay_state = 1;
+            } else {
+                // the runtime refused to capture some launch: run eagerly
+                (void)hipGetLastError();
+                if (ex) (void)hipGraphExecDestroy(ex);
+                g->replay_state = -1;
+            }
+        }
+        if (g->replay_state == 1) {
+            DSG_HIP(hipGraphLaunch(g->gexec, s), "hipGraphLaunch");
+            launched = true;
+        }
+    }
+    if (!launched) {
+        const hipError_t e = enqueue_run(s, g->ktime);
         if (e != hipSuccess) return hip_fail(e, "enqueue iteration");
-        if (g->ktime) g->klaunches++;
     }
     DSG_HIP(hipEventRecord(g->ev1, s), "hipEventRecord");
     g->timed = true;
@@ -419,6 +472,19 @@ dsg_status dsg_set_sort_tuning(dsg_graph* g, int32_t coarse_ranks) {
     if (!g) return fail(DSG_EINVAL, "graph is NULL");
     if (coarse_ranks < -1 || coarse_ranks > 1) return fail(DSG_EINVAL, "coarse_ranks must be -1, 0 or 1");
     g->sort_coarse = coarse_ranks;
+    return DSG_OK;
+}
+
+dsg_status dsg_set_graph_replay(dsg_graph* g, int32_t enable) {
+    if (!g) return fail(DSG_EINVAL, "graph is NULL");
+    g->replay = enable != 0;
+    if (g->replay && g->replay_state < 0) g->replay_state = 0;  // allow another capture attempt
+    return DSG_OK;
+}
+
+dsg_status dsg_get_graph_replay(dsg_graph* g, int32_t* state) {
+    if (!g || !state) return fail(DSG_EINVAL, "NULL argument");
+    *state = g->replay ? g->replay_state : 0;
     return DSG_OK;
 }
 
@@ -556,6 +622,8 @@ dsg_status dsg_graph_destroy(dsg_graph* g) {
     for (hipEvent_t ev : g->kev) (void)hipEventDestroy(ev);
     (void)hipEventDestroy(g->ev0);
     (void)hipEventDestroy(g->ev1);
+    if (g->gexec) (void)hipGraphExecDestroy(g->gexec);
+    if (g->cap_stream) (void)hipStreamDestroy(g->cap_stream);
     delete g;
     return DSG_OK;
 }

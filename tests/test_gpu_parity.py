@@ -194,6 +194,35 @@ def test_bounds_against_exact_density(dsg, ctx, variant):
         g.close()
 
 
+@pytest.mark.parametrize("variant", ["peel", "sort", "seq"])
+def test_graph_replay(dsg, ctx, variant):
+    """A run captured into a HIP graph and replayed gives the oracle's results on every replay, with other eager work
+    and synchronisations between the replays; a different T, or a run continuing the history, captures anew."""
+    eps = (1, 10) if variant == "peel" else (0, 1)
+    o, a = graphgen.er_planted(23, 3000, 24000, 40, 1, 2)
+    ref = oracle.run(o, a, 4, variant, eps)
+    other = dsg.Graph(ctx, *graphgen.rmat(4, 12, 16 << 12), t_cap=4)
+    g = dsg.Graph(ctx, o, a, t_cap=8).set_graph_replay(True)
+    states = []
+    for rep in range(4):
+        g.reset().run(4, eps, variant)
+        states.append(g.graph_replay_state())
+        assert_same(g, ref, f"{variant} replay {rep}")
+        other.reset().run(2, (1, 10), "peel")  # eager work on the same stream between the replays
+        other.sync()
+    log(f"{variant}: replay states {states}")
+    assert states == [1, 1, 1, 1]
+    g.reset().run(3, eps, variant)
+    assert_same(g, oracle.run(o, a, 3, variant, eps), f"{variant} recaptured for T=3")
+    g.run(2, eps, variant)
+    assert_same(g, oracle.run(o, a, 5, variant, eps), f"{variant} continued history")
+    g.set_graph_replay(False).reset().run(4, eps, variant)
+    assert g.graph_replay_state() == 0
+    assert_same(g, ref, f"{variant} eager again")
+    g.close()
+    other.close()
+
+
 def test_deterministic(dsg, ctx):
     """Atomics only commute integers: two runs are bit-identical."""
     o, a = graphgen.rmat(9, 14, 16 << 14)
