@@ -70,7 +70,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="rmat22", choices=["rmat22", "batch", "serve", "par"],
+    ap.add_argument("--workload", default="rmat22", choices=["rmat22", "batch", "serve", "par", "c3"],
                     help="rmat22: one R-MAT scale-22 graph (default); batch: the 4096-graph batched mix; "
                          "serve: Poisson request stream through the continuous-batching server; par: "
                          "Pruning-and-Refining (exact k-core pruning) on the R-MAT scale-22 graph")
@@ -100,6 +100,8 @@ def main():
         return bench_serve(args)
     if args.workload == "par":
         return bench_par(args)
+    if args.workload == "c3":
+        return bench_c3(args)
 
     import numpy as np
     import torch
@@ -532,6 +534,76 @@ def bench_par(args):
                      "avg_launch_ms": core_ms, "rounds": core_rounds, "alg_bytes_per_launch": alg_bytes},
         "cpu_baseline": cpu,
         "check": check,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_c3(args):
+    """Config 3: the sort-based ordering against round-synchronous peeling on the 40M-vertex Chung-Lu graph
+    (gamma 2.1, mean degree 30, degrees capped at 2M), T = 50, eps = 1/20 for PEEL, each with and without exact
+    k-core pruning.  One timed run of each, after one warm-up iteration; the line's value is the SORT time and the
+    others sit beside it with the best density each reaches."""
+    from fractions import Fraction
+
+    import torch
+
+    import graphgen
+    import paper_2311_04333_amd as dsg
+
+    T, eps_peel = 50, (1, 20)
+    t0 = time.time()
+    log("generating Chung-Lu n=40M (about two minutes)")
+    offsets, adj = graphgen.config3(1)
+    n, m = len(offsets) - 1, len(adj) // 2
+    log(f"generated n={n} m={m} in {time.time() - t0:.1f}s")
+    ctx = dsg.Context(0)
+    o_dev = torch.from_numpy(offsets).cuda()
+    a_dev = torch.from_numpy(adj).cuda()
+    out = {}
+    for variant, eps in (("sort", (0, 1)), ("peel", eps_peel)):
+        g = dsg.Graph(ctx, o_dev, a_dev, t_cap=T, validate=False)
+        g.reset().run(1, eps, variant)
+        g.sync()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        g.reset().run(T, eps, variant)
+        g.sync()
+        sec = time.perf_counter() - t1
+        e, v = g.best()[:2]
+        out[variant] = {"seconds": sec, "edge_visits_per_s": 2.0 * m * T / sec, "best": [e, v],
+                        "density": float(Fraction(e, v))}
+        log(f"{variant}: {sec:.2f} s for T={T} ({2.0 * m * T / sec / 1e9:.1f} G edge-visits/s), best {e}/{v}")
+        g.close()
+    ws = torch.empty(dsg.par_workspace_bytes(n, len(adj), T) + 256, dtype=torch.uint8, device="cuda")
+    for variant, eps in (("sort", (0, 1)), ("peel", eps_peel)):
+        dsg.par_run(ctx, o_dev, a_dev, 1, eps, variant, validate=False, workspace=ws)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        r = dsg.par_run(ctx, o_dev, a_dev, T, eps, variant, validate=False, workspace=ws)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t1
+        out["par_" + variant] = {"seconds": sec, "best": list(r.best[:2]),
+                                 "density": float(Fraction(r.best[0], r.best[1])), "k_max": r.kmax,
+                                 "first_cut": r.sizes[0] if r.sizes else None, "last_cut": r.final_size}
+        log(f"par {variant}: {sec:.2f} s for T={T}, best {r.best[0]}/{r.best[1]}, k_max {r.kmax}, "
+            f"cuts {r.sizes[0] if r.sizes else None} -> {r.final_size}")
+    line = {
+        "metric": "config 3: seconds for T iterations, SORT vs PEEL, with and without exact k-core pruning",
+        "value": out["sort"]["seconds"],
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 1,
+        "ms_per_step": out["sort"]["seconds"] * 1e3,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": f"Chung-Lu n={n} m={m} (gamma 2.1, mean degree 30, max degree 2M), T={T}, "
+                               f"PEEL eps=1/20"},
+        "runs": out,
+        "peel_over_sort_time": out["peel"]["seconds"] / out["sort"]["seconds"],
     }
     print(json.dumps(line), flush=True)
 
