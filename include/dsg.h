@@ -174,10 +174,11 @@ dsg_status dsg_set_peel_tuning(dsg_graph* g, int64_t bucket_min_edges, int64_t c
 
 /* Tuning of the SORT sweep; results do not depend on it.  With coarse ranks
  * the sweep first compares 4-bit position classes of about equal degree
- * mass, kept in an n/2-byte table that an XCD's L2 holds, and loads the
- * neighbour's full position only when the classes are equal.  Without them
- * it loads every neighbour's position.  coarse_ranks: -1 = on for
- * 2^19 <= n <= 2^22 (the default), 0 = off, 1 = on (ignored for n >= 2^26).
+ * mass, kept in an n/2-byte table (held by an XCD's L2 up to n = 2^22, by
+ * the MALL above), and loads the neighbour's full position only when the
+ * classes are equal.  Without them it loads every neighbour's position.
+ * coarse_ranks: -1 = on for 2^19 <= n < 2^26 (the default), 0 = off, 1 = on
+ * (ignored for n >= 2^26).
  * The setting is kept across dsg_reset.  DSG_EINVAL for other values or a
  * NULL graph. */
 dsg_status dsg_set_sort_tuning(dsg_graph* g, int32_t coarse_ranks);

@@ -39,10 +39,13 @@ constexpr int BKT_MAX_SHIFT = 14;
 constexpr int BKT_MAX_NR = 1024;
 constexpr int BKT_CNT_BITS = 12;  // bucket entry = local id << 12 | (count - 1); count <= PEEL_CH
 constexpr long long BKT_DEFAULT_MIN_E = 1LL << 20;
-// SORT compares coarse ranks first when the 4-bit table (n/2 bytes) fits an
-// XCD's L2 comfortably and the position table (4n bytes) does not
+// SORT compares coarse ranks first once the position table (4n bytes) no
+// longer fits an XCD's L2.  The 4-bit table (n/2 bytes) fits it up to 2^22
+// vertices; above that both tables live in the MALL, where the 8x smaller
+// one still wins (13.7% on the 40M-vertex Chung-Lu graph).  A staged word
+// holds class << 28 | position, so n < 2^26.
 constexpr int SORT_COARSE_MIN_N = 1 << 19;
-constexpr int SORT_COARSE_MAX_N = 1 << 22;
+constexpr int SORT_COARSE_MAX_N = (1 << 26) - 1;
 static_assert((1 << BKT_CNT_BITS) >= 4096, "chunk-local counts must fit the entry's count field");
 // Range shift for n vertices, or -1 when the graph is too large for the
 // bucketed path: the smallest shift >= 8 giving at most 256 ranges, capped
