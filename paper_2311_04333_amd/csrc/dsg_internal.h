@@ -83,6 +83,7 @@ struct PeelArgs {
     int nr;                // ranges; 0 = bucketed path off
     long long bkt_min_e;   // frontier edges from which a round is bucketed
     long long coarse_min_e;  // frontier edges from which a round sweeps coarse chunks
+    int* seg;              // alive-list segments per block, by round parity: [2][start | len][PEEL_BLK]
 };
 
 struct SweepArgs {
@@ -153,6 +154,7 @@ struct GraphDev {
     unsigned int* cb;  // SORT coarse ranks
     int* cr_bounds;    // first position of each coarse class
     int* cr_samp;      // degrees at the sampled positions
+    int* seg;          // PEEL alive-list segments (4 * PEEL_BLK ints)
     long long* cr_tsum;  // sampled degree mass per tile of 1024 samples
     int n_items;  // vertices with degree > 0
     int max_deg;

@@ -600,6 +600,8 @@ struct PeelLds {
     };
     int bcnt[BKT_MAX_NR];   // per-range entries of the chunk being flushed
     int bbase[BKT_MAX_NR];  // their reserved start in the range's bucket
+    int spref[PEEL_BLK];    // select: virtual start of each block's segment of the alive list
+    int sstart[PEEL_BLK];   // ... and its physical start
 };
 static_assert(sizeof(PeelSweepLds) >= sizeof(int) * (1 << BKT_MAX_SHIFT), "dense histogram aliases the sweep");
 
@@ -745,12 +747,10 @@ constexpr unsigned long long FCNT_MASK = (1ull << FCNT_SHIFT) - 1;
 // no VGPR spills, and the whole loop runs 7.5% faster than at 4 (25 spilled
 // VGPRs) on R-MAT scale 22; at 8 (56 spilled) it is 35% slower.
 constexpr int SEL_U = 2;
-// Packed per-tile scan value: [edges: bits 0-31][survivors: 32-44][items: 45-57].
-// A tile holds PEEL_BLK * SEL_U entries, so 13 bits per count field suffice.
-constexpr int TSURV_SHIFT = 32;
+// Packed per-tile item scan value: [edges: bits 0-31][items: 45-63]; the
+// select's per-tile survivor and item counts share a 32-bit word (16 bits each).
 constexpr int TITEM_SHIFT = 45;
-constexpr unsigned long long TCNT_MASK = 0x1FFFull;
-static_assert(PEEL_BLK * SEL_U <= (int)TCNT_MASK, "tile counts must fit their packed fields");
+static_assert(PEEL_BLK * SEL_U < (1 << 16), "tile counts must fit their packed fields");
 
 // Persistent round loop of one PEEL iteration (cooperative launch, one block
 // per CU).  Per round r:
@@ -778,7 +778,6 @@ __global__ __launch_bounds__(PEEL_BLK, PEEL_BLOCKS_PER_CU) void k_peel_rounds(Pe
     __shared__ unsigned long long shs[PEEL_BLK / WAVE];
     __shared__ unsigned int shm[PEEL_BLK / WAVE];
     __shared__ unsigned long long s_fbase;
-    __shared__ unsigned int s_lbase;
     __shared__ int s_chunk;
     __shared__ long long s_thr;  // previous round's threshold (MONO)
     Ctl* ctl = a.ctl;
@@ -840,21 +839,70 @@ __global__ __launch_bounds__(PEEL_BLK, PEEL_BLOCKS_PER_CU) void k_peel_rounds(Pe
                 atomicAnd(&a.st2[u >> 4], ~(3u << ((u & 15) * 2)));
             }
         }
-        // ---------------- select: this block's slice of L_r, in tiles of
-        // PEEL_BLK * SEL_U entries; thread t owns SEL_U consecutive entries
+        // ---------------- select: this block's slice [beg, end) of L_r, in
+        // tiles of PEEL_BLK * SEL_U entries; thread t owns SEL_U consecutive
+        // entries.  L_r is virtual: the concatenation, in block order, of the
+        // segments the blocks wrote in round r - 1 (segment j starts at
+        // seg[start][j] of Lin and holds seg[len][j] entries); L_0 is all
+        // vertices.  Block b writes its survivors to Lout[beg, beg + S) and
+        // its frontier vertices that have edges to the tail Lout[end - I,
+        // end), both in one pass without any global reservation, so only the
+        // frontier is read again to place it in the item list.
         const int per = (Lc + (int)nblocks - 1) / (int)nblocks;
         const int beg = min(Lc, (int)blockIdx.x * per), end = min(Lc, beg + per);
         constexpr int TILE = PEEL_BLK * SEL_U;
         unsigned int lmin = 0xFFFFFFFFu;
-        unsigned long long my_items = 0, my_edges = 0, my_surv = 0;
-        // a slice of one tile stays in registers for the writing pass
+        unsigned long long my_edges = 0;
+        const int* __restrict__ seg_in = a.seg + ((r - 1) & 1) * 2 * PEEL_BLK;  // [start | len]
+        int* __restrict__ seg_out = a.seg + (r & 1) * 2 * PEEL_BLK;
+        bool map_ok = true;
+        if (r > 0) {
+            const int j = (int)threadIdx.x;
+            const int len = j < (int)nblocks ? seg_in[PEEL_BLK + j] : 0;
+            unsigned long long tot;
+            const unsigned long long ex = block_excl_scan<PEEL_BLK>((unsigned long long)len, &tot, shs);
+            if (j < (int)nblocks) {
+                lds.spref[j] = (int)ex;
+                lds.sstart[j] = seg_in[j];
+            }
+            __syncthreads();
+            // the segments hold exactly the alive count (both are sums of the
+            // same per-block survivor counts); never map past them
+            map_ok = tot == (unsigned long long)Lc;
+            if (!map_ok && blockIdx.x == 0 && threadIdx.x == 0) {
+                atomicAdd(&ctl->err_count, 1);
+                ctl->err_code = ERR_INTERNAL;
+            }
+        }
+        // physical position in Lin of virtual index idx < Lc (r > 0): the last
+        // segment whose prefix is <= idx holds it (empty ones are skipped).
+        // A thread's indices only grow, so it finds its first segment by
+        // binary search and then walks forward (usually not at all).
+        int sj = 0;
+        if (r > 0 && map_ok) {
+            const int first = beg + (int)threadIdx.x * SEL_U;
+            int lo = 0, hi = (int)nblocks - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (lds.spref[mid] <= first) lo = mid; else hi = mid - 1;
+            }
+            sj = lo;
+        }
+        auto phys = [&](int idx) -> int {
+            while (sj + 1 < (int)nblocks && lds.spref[sj + 1] <= idx) sj++;
+            return lds.sstart[sj] + (idx - lds.spref[sj]);
+        };
+        // a slice of one tile stays in registers for the item pass
         const bool one_tile = end - beg <= TILE;
         int u[SEL_U], pu[SEL_U], o0[SEL_U], o1[SEL_U];
+#pragma unroll
+        for (int k = 0; k < SEL_U; k++) u[k] = -1;  // an empty slice leaves no entries
+        int s_run = 0, i_run = 0;  // survivors and tail items written so far (uniform)
         for (int base = beg; base < end; base += TILE) {
 #pragma unroll
             for (int k = 0; k < SEL_U; k++) {
                 const int idx = base + (int)threadIdx.x * SEL_U + k;
-                u[k] = idx < end ? ((r == 0) ? idx : Lin[idx]) : -1;
+                u[k] = (idx < end && map_ok) ? ((r == 0) ? idx : Lin[phys(idx)]) : -1;
             }
 #pragma unroll
             for (int k = 0; k < SEL_U; k++) pu[k] = u[k] >= 0 ? a.prio[u[k]] : 0;
@@ -864,50 +912,8 @@ __global__ __launch_bounds__(PEEL_BLK, PEEL_BLOCKS_PER_CU) void k_peel_rounds(Pe
                 o0[k] = fr ? a.off[u[k]] : 0;
                 o1[k] = fr ? a.off[u[k] + 1] : 0;
             }
-#pragma unroll
-            for (int k = 0; k < SEL_U; k++) {
-                if (u[k] < 0) continue;
-                if ((long long)pu[k] <= thr) {
-                    const int d = o1[k] - o0[k];
-                    if (d > 0) {
-                        my_items++;
-                        my_edges += d;
-                    }
-                } else {
-                    my_surv++;
-                    lmin = min(lmin, (unsigned int)pu[k]);
-                }
-            }
-        }
-        {
-            unsigned long long packed = (my_items << FCNT_SHIFT) | my_edges;
-            packed = block_sum<PEEL_BLK>(packed, shs);
-            unsigned long long sv = block_sum<PEEL_BLK>(my_surv, shs);
-            if (threadIdx.x == 0) {
-                s_fbase = packed ? atomicAdd(&ctl->fcnt[slot], packed) : 0ull;
-                s_lbase = sv ? atomicAdd(&ctl->lcnt[nslot], (unsigned int)sv) : 0u;
-            }
-            __syncthreads();
-        }
-        unsigned long long fb = s_fbase;
-        unsigned int lb = s_lbase;
-        for (int base = beg; base < end; base += TILE) {
-            if (!one_tile) {
-#pragma unroll
-                for (int k = 0; k < SEL_U; k++) {
-                    const int idx = base + (int)threadIdx.x * SEL_U + k;
-                    u[k] = idx < end ? ((r == 0) ? idx : Lin[idx]) : -1;
-                }
-#pragma unroll
-                for (int k = 0; k < SEL_U; k++) pu[k] = u[k] >= 0 ? a.prio[u[k]] : 0;
-#pragma unroll
-                for (int k = 0; k < SEL_U; k++) {
-                    const bool fr = u[k] >= 0 && (long long)pu[k] <= thr;
-                    o0[k] = fr ? a.off[u[k]] : 0;
-                    o1[k] = fr ? a.off[u[k] + 1] : 0;
-                }
-            }
-            unsigned long long val = 0;
+            // packed per-thread counts: [survivors: bits 0-15][items: 16-31]
+            unsigned int val = 0;
 #pragma unroll
             for (int k = 0; k < SEL_U; k++) {
                 if (u[k] < 0) continue;
@@ -915,37 +921,85 @@ __global__ __launch_bounds__(PEEL_BLK, PEEL_BLOCKS_PER_CU) void k_peel_rounds(Pe
                     a.rnd[u[k]] = r;
                     const int d = o1[k] - o0[k];
                     if (d > 0) {
-                        val += (1ull << TITEM_SHIFT) + (unsigned long long)d;
+                        val += 1u << 16;
+                        my_edges += (unsigned long long)d;
                         atomicOr(&a.st2[u[k] >> 4], 2u << ((u[k] & 15) * 2));
                     }
                 } else {
-                    val += 1ull << TSURV_SHIFT;
+                    val += 1u;
+                    lmin = min(lmin, (unsigned int)pu[k]);
                 }
             }
-            unsigned long long tot;
-            unsigned long long ex = block_excl_scan<PEEL_BLK>(val, &tot, shs);
-            unsigned long long it = (fb >> FCNT_SHIFT) + (ex >> TITEM_SHIFT);
-            unsigned long long ed = (fb & FCNT_MASK) + (ex & 0xFFFFFFFFull);
-            unsigned int sv = lb + (unsigned int)((ex >> TSURV_SHIFT) & TCNT_MASK);
+            unsigned int tot;
+            const unsigned int ex = block_excl_scan<PEEL_BLK>(val, &tot, shm);
+            int sr = beg + s_run + (int)(ex & 0xFFFFu);
+            int ir = end - 1 - (i_run + (int)(ex >> 16));
 #pragma unroll
             for (int k = 0; k < SEL_U; k++) {
                 if (u[k] < 0) continue;
-                if ((long long)pu[k] <= thr) {
-                    const int d = o1[k] - o0[k];
-                    if (d > 0) {
-                        ivr[it] = u[k];
-                        a.ie[it] = (int)ed;
-                        a.ir[it] = o0[k] - (int)ed;
-                        mark_chunks<PEEL_MARK>((long long)ed, (long long)ed + d, (int)it, a.cfirst, a.clast);
-                        it++;
-                        ed += d;
-                    }
-                } else {
-                    Lout[sv++] = u[k];
+                if ((long long)pu[k] > thr) {
+                    Lout[sr++] = u[k];
+                } else if (!one_tile && o1[k] > o0[k]) {
+                    Lout[ir--] = u[k];
+                }
+            }
+            s_run += (int)(tot & 0xFFFFu);
+            i_run += (int)(tot >> 16);
+        }
+        {
+            const unsigned long long eb = block_sum<PEEL_BLK>(my_edges, shs);
+            const unsigned long long packed = ((unsigned long long)i_run << FCNT_SHIFT) | eb;
+            if (threadIdx.x == 0) {
+                s_fbase = packed ? atomicAdd(&ctl->fcnt[slot], packed) : 0ull;
+                if (s_run) atomicAdd(&ctl->lcnt[nslot], (unsigned int)s_run);
+                seg_out[blockIdx.x] = beg;
+                seg_out[PEEL_BLK + blockIdx.x] = s_run;
+            }
+            __syncthreads();  // also orders the tail writes before the reads below
+        }
+        unsigned long long fb = s_fbase;
+        // item pass: the frontier vertices with edges, from registers (one
+        // tile) or from the tail, placed at the reserved item range
+        const int item_end = one_tile ? (end > beg ? 1 : 0) : i_run;  // one register pass, or the tail
+        for (int base = 0; base < item_end; base += TILE) {
+            if (!one_tile) {
+#pragma unroll
+                for (int k = 0; k < SEL_U; k++) {
+                    const int j = base + (int)threadIdx.x * SEL_U + k;
+                    u[k] = j < i_run ? Lout[end - 1 - j] : -1;
+                }
+#pragma unroll
+                for (int k = 0; k < SEL_U; k++) {
+                    o0[k] = u[k] >= 0 ? a.off[u[k]] : 0;
+                    o1[k] = u[k] >= 0 ? a.off[u[k] + 1] : 0;
+                    pu[k] = 0;  // every tail entry is a frontier vertex
+                }
+            }
+            unsigned long long val = 0;
+#pragma unroll
+            for (int k = 0; k < SEL_U; k++) {
+                if (u[k] < 0 || (long long)pu[k] > thr) continue;
+                const int d = o1[k] - o0[k];
+                if (d > 0) val += (1ull << TITEM_SHIFT) + (unsigned long long)d;
+            }
+            unsigned long long tot;
+            const unsigned long long ex = block_excl_scan<PEEL_BLK>(val, &tot, shs);
+            unsigned long long it = (fb >> FCNT_SHIFT) + (ex >> TITEM_SHIFT);
+            unsigned long long ed = (fb & FCNT_MASK) + (ex & 0xFFFFFFFFull);
+#pragma unroll
+            for (int k = 0; k < SEL_U; k++) {
+                if (u[k] < 0 || (long long)pu[k] > thr) continue;
+                const int d = o1[k] - o0[k];
+                if (d > 0) {
+                    ivr[it] = u[k];
+                    a.ie[it] = (int)ed;
+                    a.ir[it] = o0[k] - (int)ed;
+                    mark_chunks<PEEL_MARK>((long long)ed, (long long)ed + d, (int)it, a.cfirst, a.clast);
+                    it++;
+                    ed += d;
                 }
             }
             fb += ((tot >> TITEM_SHIFT) << FCNT_SHIFT) + (tot & 0xFFFFFFFFull);
-            lb += (unsigned int)((tot >> TSURV_SHIFT) & TCNT_MASK);
         }
         grid_sync(bar);
         // ---------------- sweep
@@ -1907,6 +1961,8 @@ hipError_t enqueue_iter_peel(const GraphDev& g, int slot, int eps_num, int eps_d
     a.nr = g.nr;
     a.bkt_min_e = bkt_min_e;
     a.coarse_min_e = coarse_min_e;
+    a.seg = g.seg;
+    if (peel_grid > PEEL_BLK) return hipErrorInvalidValue;  // one segment per thread of a block
     void* args[] = {&a};
     if (ev_a && (e = hipEventRecord(ev_a, s)) != hipSuccess) return e;
     e = hipLaunchCooperativeKernel(mono ? reinterpret_cast<const void*>(k_peel_rounds<true>)
