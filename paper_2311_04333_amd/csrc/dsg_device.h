@@ -214,7 +214,11 @@ __device__ __forceinline__ GridBarrier grid_sync_init(GridSync* gs, unsigned int
 // then arrives on the global counter; the arrival that completes the global
 // count publishes the epoch.  Every block then performs its own agent-scope
 // acquire (L1 and L2 invalidate, waited for).
-__device__ __forceinline__ void grid_sync(GridBarrier& b) {
+//
+// The barrier comes in two halves.  Between grid_arrive and grid_wait a
+// block may read what was published at an earlier barrier and write LDS,
+// but its global writes are not released by this barrier.
+__device__ __forceinline__ void grid_arrive(GridBarrier& b) {
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     b.epoch++;
@@ -231,11 +235,21 @@ __device__ __forceinline__ void grid_sync(GridBarrier& b) {
                 __hip_atomic_fetch_add(&gs->gcnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (g == b.epoch * b.nx - 1) st_agent(&gs->gen, b.epoch);
         }
-        while (ld_agent(&gs->gen) < b.epoch) __builtin_amdgcn_s_sleep(1);
+    }
+}
+
+__device__ __forceinline__ void grid_wait(GridBarrier& b) {
+    if (threadIdx.x == 0) {
+        while (ld_agent(&b.gs->gen) < b.epoch) __builtin_amdgcn_s_sleep(1);
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     }
     __syncthreads();
+}
+
+__device__ __forceinline__ void grid_sync(GridBarrier& b) {
+    grid_arrive(b);
+    grid_wait(b);
 }
 
 }  // namespace dsg

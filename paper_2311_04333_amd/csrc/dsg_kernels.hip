@@ -780,6 +780,7 @@ __global__ __launch_bounds__(PEEL_BLK, PEEL_BLOCKS_PER_CU) void k_peel_rounds(Pe
     __shared__ unsigned long long s_fbase;
     __shared__ int s_chunk;
     __shared__ long long s_thr;  // previous round's threshold (MONO)
+    __shared__ unsigned long long s_segtot;  // entries in the previous round's segments
     Ctl* ctl = a.ctl;
     GridSync* gs = a.gs;
     const unsigned int nblocks = gridDim.x;
@@ -853,26 +854,15 @@ __global__ __launch_bounds__(PEEL_BLK, PEEL_BLOCKS_PER_CU) void k_peel_rounds(Pe
         constexpr int TILE = PEEL_BLK * SEL_U;
         unsigned int lmin = 0xFFFFFFFFu;
         unsigned long long my_edges = 0;
-        const int* __restrict__ seg_in = a.seg + ((r - 1) & 1) * 2 * PEEL_BLK;  // [start | len]
-        int* __restrict__ seg_out = a.seg + (r & 1) * 2 * PEEL_BLK;
-        bool map_ok = true;
-        if (r > 0) {
-            const int j = (int)threadIdx.x;
-            const int len = j < (int)nblocks ? seg_in[PEEL_BLK + j] : 0;
-            unsigned long long tot;
-            const unsigned long long ex = block_excl_scan<PEEL_BLK>((unsigned long long)len, &tot, shs);
-            if (j < (int)nblocks) {
-                lds.spref[j] = (int)ex;
-                lds.sstart[j] = seg_in[j];
-            }
-            __syncthreads();
-            // the segments hold exactly the alive count (both are sums of the
-            // same per-block survivor counts); never map past them
-            map_ok = tot == (unsigned long long)Lc;
-            if (!map_ok && blockIdx.x == 0 && threadIdx.x == 0) {
-                atomicAdd(&ctl->err_count, 1);
-                ctl->err_code = ERR_INTERNAL;
-            }
+        int* __restrict__ seg_out = a.seg + (r & 1) * 2 * PEEL_BLK;  // [start | len]
+        // lds.spref / lds.sstart / s_segtot were filled from the previous
+        // round's table inside the round-end barrier.  The segments hold
+        // exactly the alive count (both are sums of the same per-block
+        // survivor counts); never map past them.
+        const bool map_ok = r == 0 || s_segtot == (unsigned long long)Lc;
+        if (!map_ok && blockIdx.x == 0 && threadIdx.x == 0) {
+            atomicAdd(&ctl->err_count, 1);
+            ctl->err_code = ERR_INTERNAL;
         }
         // physical position in Lin of virtual index idx < Lc (r > 0): the last
         // segment whose prefix is <= idx holds it (empty ones are skipped).
@@ -1060,7 +1050,26 @@ __global__ __launch_bounds__(PEEL_BLK, PEEL_BLOCKS_PER_CU) void k_peel_rounds(Pe
         }
         const unsigned int bmin = block_min<PEEL_BLK>(rmin, shm);
         if (threadIdx.x == 0 && bmin != 0xFFFFFFFFu) atomicMin(&ctl->mn[nslot], bmin);
-        grid_sync(bar);
+        {
+            // This round's segment table was published by the grid sync after
+            // the select, so the next round's mapping is built while the
+            // round-end barrier completes: the loads share the barrier's wait
+            // for outstanding memory operations, the scan runs between its
+            // halves.
+            const int* __restrict__ seg_next = a.seg + (r & 1) * 2 * PEEL_BLK;
+            const int j = (int)threadIdx.x;
+            const int len = j < (int)nblocks ? seg_next[PEEL_BLK + j] : 0;
+            const int st = j < (int)nblocks ? seg_next[j] : 0;
+            grid_arrive(bar);
+            unsigned long long tot;
+            const unsigned long long ex = block_excl_scan<PEEL_BLK>((unsigned long long)len, &tot, shs);
+            if (j < (int)nblocks) {
+                lds.spref[j] = (int)ex;
+                lds.sstart[j] = st;
+            }
+            if (j == 0) s_segtot = tot;
+            grid_wait(bar);
+        }
     }
 }
 
