@@ -28,7 +28,7 @@ _SRC = os.path.join(_HERE, "greedypp_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "_oracle.so")
 _lib = None
 
-VARIANTS = {"seq": 0, "peel": 1, "sort": 2}
+VARIANTS = {"seq": 0, "peel": 1, "sort": 2, "peel_mono": 3}
 
 
 def build(force: bool = True, extra_flags=(), out: str | None = None) -> str:
@@ -53,6 +53,8 @@ def _bind(lib):
     lib.orc_order_seq.argtypes = [i32, P, P, P, P, P]
     lib.orc_order_peel.restype = i32
     lib.orc_order_peel.argtypes = [i32, P, P, P, i64, i64, P, P]
+    lib.orc_order_peel_rule.restype = i32
+    lib.orc_order_peel_rule.argtypes = [i32, P, P, P, i64, i64, i32, P, P]
     lib.orc_order_sort.restype = i32
     lib.orc_order_sort.argtypes = [i32, P, P, P]
     lib.orc_alg3.restype = None
@@ -204,6 +206,9 @@ def order(offsets, adj, loads, variant: str, eps=(0, 1), lib=None):
     elif variant == "peel":
         num, den = parse_eps(eps)
         r = lib.orc_order_peel(n, _ptr(off), _ptr(a), _ptr(ld), num, den, _ptr(pos), _ptr(rnd))
+    elif variant == "peel_mono":
+        num, den = parse_eps(eps)
+        r = lib.orc_order_peel_rule(n, _ptr(off), _ptr(a), _ptr(ld), num, den, 1, _ptr(pos), _ptr(rnd))
     else:
         r = lib.orc_order_sort(n, _ptr(ld), _ptr(pos), _ptr(rnd))
     return pos, rnd, int(r)

@@ -38,6 +38,13 @@
  *           charged to its lower-id endpoint.
  *   SORT -- GreedySorting++ (Section 3.2): sort by the load at the start of the
  *           iteration, ascending, ties -> lower id.
+ *   PEEL_MONO -- PEEL with the bucketing of the exact k-core algorithm the
+ *           paper uses (Section 3.1, Julienne): a bucket bound d only grows.
+ *           Round r peels every alive v with l(v)+deg(v) <= d_r, where
+ *           d_r = max(d_{r-1}, (1+eps) mn_r) and d_{-1} = -infinity; with
+ *           eps = 0 and zero loads this is "peel everything of degree at
+ *           most d, raise d when nothing is left at or below it".  d starts
+ *           afresh in every iteration.
  *
  * The fused form (orc_run_fused) is Algorithm 2 as printed: it keeps |E(H)|
  * and |V(H)| while peeling one vertex at a time and charges each vertex its
@@ -58,7 +65,7 @@ typedef int64_t i64;
 typedef uint64_t u64;
 typedef __int128 i128;
 
-enum { ORC_SEQ = 0, ORC_PEEL = 1, ORC_SORT = 2 };
+enum { ORC_SEQ = 0, ORC_PEEL = 1, ORC_SORT = 2, ORC_PEEL_MONO = 3 };
 
 static u64 orc_mix64(u64 z) {
     z += 0x9E3779B97F4A7C15ULL;
@@ -109,9 +116,10 @@ int32_t orc_order_seq(int32_t n, const int32_t* off, const int32_t* adj, const i
 
 /* PEEL: round-synchronous (1+eps)-of-minimum peeling.  The alive list is kept
  * in ascending id order, so each round's frontier comes out in ascending id.
- * Returns the number of rounds. */
-int32_t orc_order_peel(int32_t n, const int32_t* off, const int32_t* adj, const i64* load, i64 eps_num, i64 eps_den,
-                       int32_t* pos, int32_t* round) {
+ * With `mono`, the bound of a round is the largest bound of the iteration so
+ * far (PEEL_MONO).  Returns the number of rounds. */
+int32_t orc_order_peel_rule(int32_t n, const int32_t* off, const int32_t* adj, const i64* load, i64 eps_num,
+                            i64 eps_den, int32_t mono, int32_t* pos, int32_t* round) {
     i64* deg = (i64*)malloc(sizeof(i64) * (size_t)n);
     int32_t* alive = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
     if (!deg || !alive) {
@@ -125,6 +133,7 @@ int32_t orc_order_peel(int32_t n, const int32_t* off, const int32_t* adj, const 
         alive[v] = v;
     }
     int32_t nalive = n, r = 0, next = 0;
+    i128 dmax = -1; /* largest bound so far, scaled by eps_den (PEEL_MONO) */
     while (nalive > 0) {
         /* minimum priority over the alive vertices */
         i64 mn = load[alive[0]] + deg[alive[0]];
@@ -132,9 +141,14 @@ int32_t orc_order_peel(int32_t n, const int32_t* off, const int32_t* adj, const 
             i64 p = load[alive[k]] + deg[alive[k]];
             if (p < mn) mn = p;
         }
-        /* frontier: every alive v with eps_den * p(v) <= (eps_den + eps_num) * mn,
-         * selected with the degrees of the round's start, in ascending id */
-        const i128 lim = (i128)(eps_den + eps_num) * (i128)mn;
+        /* frontier: every alive v with eps_den * p(v) <= (eps_den + eps_num) * mn
+         * (or the larger earlier bound, PEEL_MONO), selected with the degrees
+         * of the round's start, in ascending id */
+        i128 lim = (i128)(eps_den + eps_num) * (i128)mn;
+        if (mono) {
+            if (dmax > lim) lim = dmax;
+            dmax = lim;
+        }
         for (int32_t k = 0; k < nalive; k++) {
             int32_t v = alive[k];
             if ((i128)eps_den * (i128)(load[v] + deg[v]) <= lim) {
@@ -159,6 +173,11 @@ int32_t orc_order_peel(int32_t n, const int32_t* off, const int32_t* adj, const 
     free(deg);
     free(alive);
     return r;
+}
+
+int32_t orc_order_peel(int32_t n, const int32_t* off, const int32_t* adj, const i64* load, i64 eps_num, i64 eps_den,
+                       int32_t* pos, int32_t* round) {
+    return orc_order_peel_rule(n, off, adj, load, eps_num, eps_den, 0, pos, round);
 }
 
 /* SORT: ids ordered by (load, id) ascending.  qsort on packed pairs. */
@@ -255,8 +274,9 @@ int orc_run(int32_t n, const int32_t* off, const int32_t* adj, int32_t T, int32_
         int32_t rounds;
         if (variant == ORC_SEQ)
             rounds = orc_order_seq(n, off, adj, load, last_pos, last_round);
-        else if (variant == ORC_PEEL)
-            rounds = orc_order_peel(n, off, adj, load, eps_num, eps_den, last_pos, last_round);
+        else if (variant == ORC_PEEL || variant == ORC_PEEL_MONO)
+            rounds = orc_order_peel_rule(n, off, adj, load, eps_num, eps_den, variant == ORC_PEEL_MONO, last_pos,
+                                         last_round);
         else
             rounds = orc_order_sort(n, load, last_pos, last_round);
         if (rounds < 0) {
@@ -361,12 +381,17 @@ int orc_run_fused(int32_t n, const int32_t* off, const int32_t* adj, int32_t T, 
                 }
                 PEEL_ONE(bestv);
             }
-        } else if (variant == ORC_PEEL) {
+        } else if (variant == ORC_PEEL || variant == ORC_PEEL_MONO) {
+            i128 dmax = -1;
             while (j < n) {
                 i64 mn = -1;
                 for (int32_t v = 0; v < n; v++)
                     if (inH[v] && (mn < 0 || start[v] + degH[v] < mn)) mn = start[v] + degH[v];
-                const i128 lim = (i128)(eps_den + eps_num) * (i128)mn;
+                i128 lim = (i128)(eps_den + eps_num) * (i128)mn;
+                if (variant == ORC_PEEL_MONO) {
+                    if (dmax > lim) lim = dmax;
+                    dmax = lim;
+                }
                 for (int32_t v = 0; v < n; v++)
                     inF[v] = inH[v] && (i128)eps_den * (i128)(start[v] + degH[v]) <= lim;
                 for (int32_t v = 0; v < n; v++)

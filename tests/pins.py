@@ -24,6 +24,8 @@ Sources of the facts:
     checked against networkx.core_number and against the k-core definition;
   * the ordering property of Section 3.2 / 3.3: for positions i < j,
     l(v_i) <= l(v_j) + Delta (eps = 0), and its (1+eps)-relaxed form;
+  * the bucketing k-core algorithm of Section 3.1: with zero loads and
+    eps = 0, the monotone-bound rounds are the core-number buckets;
   * the SplitMix64 known answer: from state 0 its first output is
     0xE220A8397B1DCDAF.
 """
@@ -201,7 +203,8 @@ def pin_bounds_against_brute_force(lib):
     for o, a in _small_graphs():
         es, vs = brute.densest_brute(o, a)
         delta = int(np.diff(o).max())
-        for var, eps in (("seq", (0, 1)), ("peel", (1, 10)), ("peel", (1, 2)), ("sort", (0, 1))):
+        for var, eps in (("seq", (0, 1)), ("peel", (1, 10)), ("peel", (1, 2)), ("sort", (0, 1)),
+                         ("peel_mono", (0, 1)), ("peel_mono", (1, 10))):
             st = None
             for T in range(1, 7):
                 st = oracle.run(o, a, 1, var, eps, state=st, lib=lib)
@@ -212,7 +215,7 @@ def pin_bounds_against_brute_force(lib):
                 assert -(-es // vs) <= w <= delta, (w, es, vs, delta)
                 if T == 1 and var == "seq":
                     assert 2 * be * vs >= es * bv, "Charikar bound"
-                if T == 1 and var == "peel":
+                if T == 1 and var in ("peel", "peel_mono"):
                     q, p = eps[1], eps[0]
                     assert 2 * (q + p) * be * vs >= q * es * bv, "relaxed Charikar bound"
 
@@ -238,7 +241,7 @@ def pin_bounds_against_exact_medium(lib):
     """The brute-force bounds carried to graphs of thousands of vertices, with rho* = es/vs from Goldberg's
     min-cut construction (exact_density, itself checked against brute force):
       rho_best <= rho* <= max l / T for every variant and T (every edge of S* is charged inside S*);
-      iteration 1: SEQ rho_best >= rho*/2 (Charikar), PEEL rho_best >= rho* / (2 (1 + eps));
+      iteration 1: SEQ rho_best >= rho*/2 (Charikar), PEEL and PEEL_MONO rho_best >= rho* / (2 (1 + eps));
       the empirical width of every iteration is at least ceil(rho*);
       k_max / 2 <= rho* <= k_max (the k_max-core has minimum degree k_max; every vertex of S* has at least
       rho* neighbours in S*, so S* lies in the ceil(rho*)-core).
@@ -246,7 +249,7 @@ def pin_bounds_against_exact_medium(lib):
     for name, (o, a, es, vs) in _medium_graphs_exact().items():
         _, kmax = oracle.coreness(o, a, lib=lib)
         assert kmax * vs <= 2 * es and es <= kmax * vs, (name, kmax, es, vs)
-        for var, eps in (("seq", (0, 1)), ("peel", (1, 10)), ("sort", (0, 1))):
+        for var, eps in (("seq", (0, 1)), ("peel", (1, 10)), ("sort", (0, 1)), ("peel_mono", (1, 20))):
             st = None
             for T in range(1, 21):
                 st = oracle.run(o, a, 1, var, eps, state=st, lib=lib)
@@ -256,7 +259,7 @@ def pin_bounds_against_exact_medium(lib):
                 assert -(-es // vs) <= st.width[-1], (name, var, T, "width below ceil(rho*)")
                 if T == 1 and var == "seq":
                     assert 2 * be * vs >= es * bv, (name, "Charikar bound")
-                if T == 1 and var == "peel":
+                if T == 1 and var in ("peel", "peel_mono"):
                     q, p = eps[1], eps[0]
                     assert 2 * (q + p) * be * vs >= q * es * bv, (name, "relaxed Charikar bound")
             if var == "seq":
@@ -304,7 +307,7 @@ def pin_load_sum_and_best_mask(lib):
     recounted from the CSR has exactly (best edges, best vertices)."""
     for o, a in _small_graphs() + [graphgen.config1(3)]:
         m = len(a) // 2
-        for var, eps in (("seq", (0, 1)), ("peel", (1, 10)), ("sort", (0, 1))):
+        for var, eps in (("seq", (0, 1)), ("peel", (1, 10)), ("sort", (0, 1)), ("peel_mono", (1, 10))):
             st = oracle.run(o, a, 5, var, eps, lib=lib)
             assert st.loads.sum() == 5 * m
             mask = st.best_mask()
@@ -316,7 +319,8 @@ def pin_fused_equals_decoupled(lib):
     """Algorithm 2 run fused (density checked before every single peel) and decoupled (ordering, then
     Algorithm 3) agree exactly: loads, per-iteration records and best."""
     for o, a in _small_graphs() + [graphgen.config1(2)]:
-        for var, eps in (("seq", (0, 1)), ("peel", (1, 10)), ("peel", (0, 1)), ("sort", (0, 1))):
+        for var, eps in (("seq", (0, 1)), ("peel", (1, 10)), ("peel", (0, 1)), ("sort", (0, 1)),
+                         ("peel_mono", (0, 1)), ("peel_mono", (1, 10))):
             d = oracle.run(o, a, 4, var, eps, lib=lib)
             f = oracle.run_fused(o, a, 4, var, eps, lib=lib)
             assert np.array_equal(d.loads, f.loads), var
@@ -328,7 +332,7 @@ def pin_fused_equals_decoupled(lib):
 def pin_resume(lib):
     """The state carries across calls: run(a) then run(b) equals run(a + b)."""
     o, a = graphgen.config1(4)
-    for var in ("seq", "peel", "sort"):
+    for var in ("seq", "peel", "sort", "peel_mono"):
         one = oracle.run(o, a, 5, var, (1, 10), lib=lib)
         two = oracle.run(o, a, 2, var, (1, 10), lib=lib)
         two = oracle.run(o, a, 3, var, (1, 10), state=two, lib=lib)
@@ -368,10 +372,13 @@ def pin_degeneracy_order_gives_core_numbers(lib):
 def pin_ordering_property(lib):
     """For positions i < j with start-of-iteration loads: SEQ, SORT and PEEL with eps = 0 satisfy
     l(v_i) <= l(v_j) + Delta (Sections 3.2-3.3); PEEL with eps = p/q satisfies
-    q l(v_i) <= (q + p)(l(v_j) + Delta)."""
+    q l(v_i) <= (q + p)(l(v_j) + Delta).  So does PEEL_MONO: the bound a vertex v_i is peeled under
+    is (1 + eps) times the minimum of some earlier round, when v_j was alive with priority at most
+    l(v_j) + Delta."""
     for o, a in _small_graphs() + [graphgen.config1(1)]:
         delta = int(np.diff(o).max())
-        for var, eps in (("seq", (0, 1)), ("sort", (0, 1)), ("peel", (0, 1)), ("peel", (1, 10))):
+        for var, eps in (("seq", (0, 1)), ("sort", (0, 1)), ("peel", (0, 1)), ("peel", (1, 10)),
+                         ("peel_mono", (0, 1)), ("peel_mono", (1, 10))):
             st = None
             for _ in range(4):
                 start = np.zeros(len(o) - 1, dtype=np.int64) if st is None else st.loads.copy()
@@ -380,6 +387,49 @@ def pin_ordering_property(lib):
                 run_max = np.maximum.accumulate(seq)
                 p, q = eps
                 assert np.all(q * run_max <= (q + p) * (seq + delta))
+
+
+def pin_peel_mono_rounds_are_core_buckets(lib):
+    """PEEL_MONO with eps = 0 in the first iteration (loads 0) is the bucketing k-core algorithm of
+    Section 3.1 (peel everything of degree at most d, raise d when nothing is left at or below it): the
+    vertices of one round share one core number k (networkx.core_number, and the k-core definition on
+    the smallest graphs), k never falls from one round to the next, and a round takes exactly the alive
+    vertices whose current degree is at most k.  Plain PEEL takes only those at the round minimum, so it
+    needs more rounds wherever the minimum drops below the core number reached (checked to happen)."""
+    import networkx as nx
+
+    graphs = _small_graphs() + [graphgen.config1(1), graphgen.gnp(9, 40, 1, 6), graphgen.rmat(3, 8, 6 << 8)]
+    separated = False
+    for o, a in graphs:
+        n = len(o) - 1
+        G = nx.Graph()
+        G.add_nodes_from(range(n))
+        G.add_edges_from(brute.edge_list(o, a).tolist())
+        cn = nx.core_number(G)
+        core = np.array([cn[v] for v in range(n)], dtype=np.int64)
+        if n <= 14:
+            assert np.array_equal(core, brute.core_numbers_brute(o, a))
+        st = oracle.run(o, a, 1, "peel_mono", (0, 1), lib=lib)
+        rnd = st.last_round
+        src = np.repeat(np.arange(n), np.diff(o))
+        alive = np.ones(n, dtype=bool)
+        prev_k = -1
+        for r in range(st.rounds[0]):
+            members = np.flatnonzero(rnd == r)
+            ks = set(core[members].tolist())
+            assert len(ks) == 1, (r, ks)
+            k = ks.pop()
+            assert k >= prev_k
+            prev_k = k
+            cur = np.bincount(src, weights=alive[np.asarray(a)], minlength=n)
+            expect = np.flatnonzero(alive & (cur <= k))
+            assert np.array_equal(members, expect), r
+            alive[members] = False
+        assert not alive.any()
+        plain = oracle.run(o, a, 1, "peel", (0, 1), lib=lib)
+        assert plain.rounds[0] >= st.rounds[0]
+        separated |= plain.rounds[0] > st.rounds[0]
+    assert separated
 
 
 def pin_seq_is_greedy_min(lib):

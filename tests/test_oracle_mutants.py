@@ -23,9 +23,13 @@ MUTANTS = [
      "if (best < 0 || load[v] + deg[v] <= load[best] + deg[best]) best = v;"),
     ("seq_decrement_twice", "if (alive[adj[k]]) deg[adj[k]]--;", "if (alive[adj[k]]) deg[adj[k]] -= 2;"),
     ("peel_round_max_not_min", "if (p < mn) mn = p;", "if (p > mn) mn = p;"),
-    ("peel_eps_factor_wrong", "const i128 lim = (i128)(eps_den + eps_num) * (i128)mn;\n        for (int32_t k = 0;",
-     "const i128 lim = (i128)(eps_den + 2 * eps_num) * (i128)mn;\n        for (int32_t k = 0;"),
+    ("peel_eps_factor_wrong", "i128 lim = (i128)(eps_den + eps_num) * (i128)mn;\n        if (mono) {",
+     "i128 lim = (i128)(eps_den + 2 * eps_num) * (i128)mn;\n        if (mono) {"),
     ("peel_no_delayed_decrement", "if (round[adj[e]] == -1) deg[adj[e]]--;", "if (round[adj[e]] == -2) deg[adj[e]]--;"),
+    ("peel_mono_bound_not_kept", "if (mono) {\n            if (dmax > lim) lim = dmax;\n            dmax = lim;",
+     "if (mono) {\n            dmax = lim;"),
+    ("peel_mono_bound_unscaled", "if (mono) {\n            if (dmax > lim) lim = dmax;\n            dmax = lim;",
+     "if (mono) {\n            if (dmax > lim) lim = dmax;\n            dmax = mn;"),
     ("alg3_charge_later_endpoint", "A[pos[u] < pos[v] ? pos[u] : pos[v]] += 1;",
      "A[pos[u] > pos[v] ? pos[u] : pos[v]] += 1;"),
     ("alg3_suffix_off_by_one", "run += A[i];\n        B[i] = run;", "B[i] = run;\n        run += A[i];"),
