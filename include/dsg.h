@@ -19,6 +19,15 @@
  *   DSG_SORT -- GreedySorting++ / ParallelGreedySorting++ (Sections 3.2,
  *               3.3): order by the load at the start of the iteration,
  *               ties to the lower id.
+ *   DSG_PEEL_MONO -- DSG_PEEL with the bucketing of the exact k-core
+ *               algorithm that the paper's parallel implementation uses
+ *               (Section 3.1): the round bound only grows within an
+ *               iteration.  Round r peels every remaining vertex with
+ *               load+degree <= d_r, d_r = max(d_{r-1}, (1 + eps) * (round
+ *               minimum)); d starts afresh in each iteration.  With eps = 0
+ *               this is "peel everything at or below d, raise d when nothing
+ *               is left there".  Fewer rounds than DSG_PEEL when degrees fall
+ *               below the bound already reached.
  *
  * Every ordering feeds the same density-and-load computation (Algorithm 3):
  * each edge charges its earlier endpoint, the suffix sums give
@@ -63,7 +72,7 @@ typedef enum {
     DSG_EBUSY = -6      /* server admission refused (over the HBM budget) */
 } dsg_status;
 
-typedef enum { DSG_SEQ = 0, DSG_PEEL = 1, DSG_SORT = 2 } dsg_variant;
+typedef enum { DSG_SEQ = 0, DSG_PEEL = 1, DSG_SORT = 2, DSG_PEEL_MONO = 3 } dsg_variant;
 
 /* flags for dsg_graph_create */
 #define DSG_VALIDATE 1 /* check every CSR property listed above on the device */
@@ -94,7 +103,8 @@ dsg_status dsg_graph_create(dsg_ctx* ctx, int32_t n, int64_t nnz, const int32_t*
 /* Run T more iterations of the given variant (T >= 0), appending to the
  * current state: loads and best carry over, so run(a) then run(b) equals
  * run(a + b).  eps = eps_num / eps_den with eps_num >= 0, eps_den >= 1; only
- * DSG_PEEL reads it.  DSG_SEQ requires n <= 16000 (its state sits in LDS).
+ * DSG_PEEL and DSG_PEEL_MONO read it.  DSG_SEQ requires n <= 16000 (its state
+ * sits in LDS); DSG_PEEL and DSG_PEEL_MONO require n < 2^26.
  * Fails with DSG_EINVAL if the recorded iterations would exceed t_cap, and
  * with DSG_EOVERFLOW if (iterations + 1) * max_degree could reach 2^31.
  * Asynchronous: returns once the work is enqueued. */
@@ -125,7 +135,7 @@ dsg_status dsg_get_loads(dsg_graph* g, int64_t* h_loads);
 dsg_status dsg_get_iter_densities(dsg_graph* g, int64_t* h_edges, int64_t* h_verts, int32_t* h_index, int32_t cap,
                                   int32_t* count);
 
-/* Order of the last iteration: h_round[v] = its peeling round (DSG_PEEL) or
+/* Order of the last iteration: h_round[v] = its peeling round (DSG_PEEL, DSG_PEEL_MONO) or
  * its position (DSG_SEQ, DSG_SORT), h_pos[v] = its position.  Either
  * pointer may be NULL.  *n_rounds gets the number of rounds of that
  * iteration (n for DSG_SEQ and DSG_SORT). */
@@ -251,7 +261,7 @@ dsg_status dsg_par_workspace_bytes(int32_t n, int64_t nnz, int32_t T, int64_t* b
 
 /* Runs the framework on the symmetric int32 CSR (d_offsets, d_adj) (device,
  * not modified), with T refinement iterations of `variant` (eps_num/eps_den
- * used by DSG_PEEL).  flags: DSG_VALIDATE checks the input CSR as
+ * used by DSG_PEEL and DSG_PEEL_MONO).  flags: DSG_VALIDATE checks the input CSR as
  * dsg_graph_create does.  Synchronous on the context's stream.  Host
  * outputs, each optional (NULL to skip): per iteration t = 1..T the edges,
  * vertices and index of S' (h_iter_edges, h_iter_verts, h_iter_index) and

@@ -24,7 +24,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdsg.so")
 _lib = None
 
-VARIANTS = {"seq": 0, "peel": 1, "sort": 2}
+VARIANTS = {"seq": 0, "peel": 1, "sort": 2, "peel_mono": 3}
 STATUS = {0: "DSG_OK", -1: "DSG_EINVAL", -2: "DSG_ENOMEM", -3: "DSG_EDEVICE", -4: "DSG_EOVERFLOW",
           -5: "DSG_ESTATE", -6: "DSG_EBUSY"}
 VALIDATE = 1

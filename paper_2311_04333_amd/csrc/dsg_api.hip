@@ -338,10 +338,12 @@ dsg_status dsg_run(dsg_graph* g, int32_t T, int32_t eps_num, int32_t eps_den, ds
     if (!g) return fail(DSG_EINVAL, "graph is NULL");
     if (T < 0) return fail(DSG_EINVAL, "T must be >= 0");
     if (eps_num < 0 || eps_den < 1) return fail(DSG_EINVAL, "eps must be eps_num >= 0, eps_den >= 1");
-    if (variant != DSG_SEQ && variant != DSG_PEEL && variant != DSG_SORT) return fail(DSG_EINVAL, "unknown variant");
+    if (variant != DSG_SEQ && variant != DSG_PEEL && variant != DSG_SORT && variant != DSG_PEEL_MONO)
+        return fail(DSG_EINVAL, "unknown variant");
     if ((long long)g->recorded + T > g->t_cap) return fail(DSG_EINVAL, "T exceeds the history capacity t_cap");
     if (variant == DSG_SEQ && g->d.n > dsg::SEQ_MAX_N) return fail(DSG_EINVAL, "DSG_SEQ supports n <= 16000");
-    if (variant == DSG_PEEL && g->d.n >= dsg::PEEL_MAX_N) return fail(DSG_EINVAL, "DSG_PEEL supports n < 2^26");
+    if ((variant == DSG_PEEL || variant == DSG_PEEL_MONO) && g->d.n >= dsg::PEEL_MAX_N)
+        return fail(DSG_EINVAL, "DSG_PEEL and DSG_PEEL_MONO support n < 2^26");
     // loads grow by at most max_degree per iteration; priorities add one more
     if (g->load_bound + ((long long)T + 1) * (long long)g->d.max_deg >= (1LL << 31))
         return fail(DSG_EOVERFLOW, "loads could exceed 31 bits");
@@ -363,10 +365,10 @@ dsg_status dsg_run(dsg_graph* g, int32_t T, int32_t eps_num, int32_t eps_den, ds
             hipEvent_t ea = timed ? g->kev[2 * t] : nullptr;
             hipEvent_t eb = timed ? g->kev[2 * t + 1] : nullptr;
             hipError_t e;
-            if (variant == DSG_PEEL) {
+            if (variant == DSG_PEEL || variant == DSG_PEEL_MONO) {
                 e = dsg::enqueue_iter_peel(g->d, slot, eps_num, eps_den, g->ctx->peel_grid, g->bkt_min_e,
                                            g->coarse_min_e >= 0 ? g->coarse_min_e : dsg::PEEL_DEFAULT_COARSE_MIN_E,
-                                           g->peel_mono, qs, ea, eb);
+                                           g->peel_mono || variant == DSG_PEEL_MONO, qs, ea, eb);
             } else if (variant == DSG_SORT) {
                 long long bound = g->load_bound + (long long)t * (long long)g->d.max_deg;
                 int bits = 0;
@@ -799,7 +801,8 @@ dsg_status dsg_par_run(dsg_ctx* ctx, int32_t n, int64_t nnz, const int32_t* d_of
     if (nnz < 0 || nnz > dsg::MAX_NNZ) return fail(DSG_EINVAL, "nnz must be in [0, 2^31 - 2^16]");
     if (T < 0) return fail(DSG_EINVAL, "T must be >= 0");
     if (eps_num < 0 || eps_den < 1) return fail(DSG_EINVAL, "eps must be eps_num >= 0, eps_den >= 1");
-    if (variant != DSG_SEQ && variant != DSG_PEEL && variant != DSG_SORT) return fail(DSG_EINVAL, "unknown variant");
+    if (variant != DSG_SEQ && variant != DSG_PEEL && variant != DSG_SORT && variant != DSG_PEEL_MONO)
+        return fail(DSG_EINVAL, "unknown variant");
     const int tcap = T > 0 ? T : 1;
     const long long need = carve_par(n, nnz, tcap, nullptr, nullptr);
     if (workspace_bytes < need) return fail(DSG_EINVAL, "workspace too small (dsg_par_workspace_bytes)");

@@ -41,6 +41,15 @@ def test_binding_covers_the_header():
     assert sorted(n for n, _, _ in dsg.SIGNATURES) == declared_functions()
 
 
+def test_variant_codes_match_the_header():
+    """The binding's variant names map to the codes of the header's dsg_variant enum, one to one."""
+    import paper_2311_04333_amd as dsg
+
+    body = re.search(r"typedef enum \{([^}]*)\} dsg_variant;", open(HEADER).read()).group(1)
+    codes = {name: int(v) for name, v in re.findall(r"(DSG_\w+)\s*=\s*(\d+)", body)}
+    assert codes == {"DSG_" + k.upper(): v for k, v in dsg.VARIANTS.items()}
+
+
 def test_workspace_bytes_host_logic(lib):
     import paper_2311_04333_amd as dsg
 

@@ -55,7 +55,7 @@ def _cases():
     return cases
 
 
-VARIANTS = [("peel", (1, 10)), ("peel", (0, 1)), ("sort", (0, 1))]
+VARIANTS = [("peel", (1, 10)), ("peel", (0, 1)), ("sort", (0, 1)), ("peel_mono", (1, 20))]
 
 
 @pytest.mark.parametrize("name", list(_cases().keys()))

@@ -18,7 +18,8 @@ from pins import _small_graphs
 
 pytestmark = pytest.mark.gpu
 
-VARIANTS = [("seq", (0, 1)), ("peel", (1, 10)), ("peel", (0, 1)), ("peel", (1, 20)), ("sort", (0, 1))]
+VARIANTS = [("seq", (0, 1)), ("peel", (1, 10)), ("peel", (0, 1)), ("peel", (1, 20)), ("sort", (0, 1)),
+            ("peel_mono", (0, 1)), ("peel_mono", (1, 10))]
 
 
 @pytest.fixture(scope="module")
@@ -104,7 +105,8 @@ def test_ragged_multi_tile(dsg, ctx, n, m):
 def test_rmat_skewed(dsg, ctx, scale):
     """R-MAT (hubs, many isolated vertices) with the configuration's quadrant probabilities."""
     o, a = graphgen.rmat(3, scale, 16 << scale)
-    for variant, eps in [("peel", (1, 10)), ("peel", (1, 20)), ("peel", (0, 1)), ("sort", (0, 1))]:
+    for variant, eps in [("peel", (1, 10)), ("peel", (1, 20)), ("peel", (0, 1)), ("sort", (0, 1)),
+                         ("peel_mono", (0, 1)), ("peel_mono", (1, 20))]:
         log(f"rmat scale={scale} variant={variant} eps={eps}")
         g, ref = run_both(dsg, ctx, o, a, 5, variant, eps)
         assert_same(g, ref, f"rmat{scale}/{variant}/{eps}")
@@ -115,7 +117,7 @@ def test_rmat_large_slices(dsg, ctx):
     """R-MAT scale 20 (1M vertices): each of the 256 round-loop blocks owns more than 4096 alive vertices in the
     first rounds, so the select phase runs several full tiles per block."""
     o, a = graphgen.rmat(4, 20, 16 << 20)
-    for variant, eps in [("peel", (1, 10)), ("sort", (0, 1))]:
+    for variant, eps in [("peel", (1, 10)), ("sort", (0, 1)), ("peel_mono", (1, 10))]:
         log(f"rmat scale=20 variant={variant}")
         g, ref = run_both(dsg, ctx, o, a, 3, variant, eps)
         assert_same(g, ref, f"rmat20/{variant}")
@@ -125,7 +127,7 @@ def test_rmat_large_slices(dsg, ctx):
 def test_chunglu_small(dsg, ctx):
     """Chung-Lu power law (the shape of the 40M-vertex configuration) at n=200k."""
     o, a = graphgen.chunglu(5, 200_000, 2.1, 30.0, 10_000.0)
-    for variant, eps in [("peel", (1, 20)), ("sort", (0, 1))]:
+    for variant, eps in [("peel", (1, 20)), ("sort", (0, 1)), ("peel_mono", (1, 20))]:
         log(f"chunglu n=200k variant={variant}")
         g, ref = run_both(dsg, ctx, o, a, 3, variant, eps)
         assert_same(g, ref, f"chunglu/{variant}")
@@ -138,7 +140,7 @@ def test_resume_and_mixed_variants(dsg, ctx):
     g = dsg.Graph(ctx, o, a, t_cap=32)
     ref = None
     for T, variant, eps in [(2, "peel", (1, 10)), (3, "sort", (0, 1)), (1, "seq", (0, 1)), (2, "peel", (1, 20)),
-                            (0, "peel", (1, 10)), (2, "peel", (1, 10))]:
+                            (0, "peel", (1, 10)), (2, "peel_mono", (0, 1)), (2, "peel", (1, 10))]:
         log(f"resume step T={T} variant={variant}")
         g.run(T, eps, variant)
         ref = oracle.run(o, a, T, variant, eps, state=ref)
@@ -171,14 +173,14 @@ def test_kernel_timing(dsg, ctx, variant):
     assert_same(g, oracle.run(o, a, 5, variant, (1, 10)), f"untimed {variant} after timed")
 
 
-@pytest.mark.parametrize("variant", ["peel", "sort", "seq"])
+@pytest.mark.parametrize("variant", ["peel", "sort", "seq", "peel_mono"])
 def test_bounds_against_exact_density(dsg, ctx, variant):
     """Independent of the oracle: on config 1 and R-MAT scale 11 the GPU's best density never exceeds the exact
     rho* (Goldberg's min cut), rho* <= max load / T holds after every iteration, and sequential Greedy++
     reaches rho* within 20 iterations."""
     from exact_density import densest_exact
 
-    eps = (1, 10) if variant == "peel" else (0, 1)
+    eps = (1, 10) if variant in ("peel", "peel_mono") else (0, 1)
     for name, (o, a) in [("config1", graphgen.config1(1)), ("rmat11", graphgen.rmat(3, 11, 16 << 11))]:
         r, _ = densest_exact(o, a)
         es, vs = r.numerator, r.denominator
@@ -194,11 +196,11 @@ def test_bounds_against_exact_density(dsg, ctx, variant):
         g.close()
 
 
-@pytest.mark.parametrize("variant", ["peel", "sort", "seq"])
+@pytest.mark.parametrize("variant", ["peel", "sort", "seq", "peel_mono"])
 def test_graph_replay(dsg, ctx, variant):
     """A run captured into a HIP graph and replayed gives the oracle's results on every replay, with other eager work
     and synchronisations between the replays; a different T, or a run continuing the history, captures anew."""
-    eps = (1, 10) if variant == "peel" else (0, 1)
+    eps = (1, 10) if variant in ("peel", "peel_mono") else (0, 1)
     o, a = graphgen.er_planted(23, 3000, 24000, 40, 1, 2)
     ref = oracle.run(o, a, 4, variant, eps)
     other = dsg.Graph(ctx, *graphgen.rmat(4, 12, 16 << 12), t_cap=4)

@@ -1,4 +1,4 @@
-"""Seeded random sweep: many small graphs of every generator family, random T and eps, all three orderings and one
+"""Seeded random sweep: many small graphs of every generator family, random T and eps, all four orderings and one
 batch, each against the oracle bit for bit.
 
 The hand-picked parity cases cover the known edge cases; this sweep is for the unknown ones (ties between rounds,
@@ -75,8 +75,8 @@ def ctx(dsg):
 @pytest.mark.parametrize("seed", [101, 202, 404, 505])
 def test_random_graphs_all_orderings(dsg, ctx, seed):
     for name, o, a, T, eps in random_graphs(seed, 60):
-        for variant in ("peel", "sort", "seq"):
-            e = eps if variant == "peel" else (0, 1)
+        for variant in ("peel", "sort", "seq", "peel_mono"):
+            e = eps if variant in ("peel", "peel_mono") else (0, 1)
             log(f"random sweep {name} {variant}")
             g = dsg.Graph(ctx, o, a, t_cap=T)
             g.run(T, e, variant)
