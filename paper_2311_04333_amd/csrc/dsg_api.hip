@@ -131,7 +131,7 @@ long long carve(int n, long long nnz, int t_cap, char* base, GraphDev* g) {
     long long o_bkt = L.add(rshift >= 0 ? 4 * nnz : 0), o_bf = L.add(4 * dsg::BKT_MAX_NR);
     long long o_cb = L.add(4 * ((N + 7) / 8 + 1)), o_crb = L.add(4 * 16), o_crs = L.add(4 * (1 << 17));
     long long o_crt = L.add(8 * ((1 << 17) / 1024));
-    long long o_seg = L.add(4 * 4 * dsg::PEEL_BLK);
+    long long o_seg = L.add(4 * 6 * dsg::PEEL_BLK);
     if (base && g) {
         g->cr_samp = reinterpret_cast<int*>(base + o_crs);
         g->cr_tsum = reinterpret_cast<long long*>(base + o_crt);

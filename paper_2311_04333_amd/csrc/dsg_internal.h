@@ -83,7 +83,8 @@ struct PeelArgs {
     int nr;                // ranges; 0 = bucketed path off
     long long bkt_min_e;   // frontier edges from which a round is bucketed
     long long coarse_min_e;  // frontier edges from which a round sweeps coarse chunks
-    int* seg;              // alive-list segments per block, by round parity: [2][start | len][PEEL_BLK]
+    int* seg;              // per block, by round parity: [2][alive start | alive len | frontier len][PEEL_BLK]
+    int* order;            // order[position] = vertex, written round by round
 };
 
 struct SweepArgs {

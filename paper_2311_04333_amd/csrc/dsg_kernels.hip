@@ -192,19 +192,8 @@ constexpr int RITEMS = 16;
 constexpr int RTILE = RBLK * RITEMS;
 constexpr int RBINS = 256;
 
-// Pass activity: for the PEEL sort by round the number of significant bits
-// is known only on the device (ctl->nrounds); a pass above it is inactive
-// and becomes a plain copy so the result lands in the same buffer.
-__device__ __forceinline__ bool pass_active(const Ctl* ctl, int shift, int dyn) {
-    if (!dyn || shift == 0) return true;
-    unsigned int maxkey = (unsigned int)max(ctl->nrounds - 1, 0);
-    return (maxkey >> shift) != 0;
-}
-
 __global__ __launch_bounds__(RBLK) void k_radix_hist(const int* __restrict__ keys, int n, int shift,
-                                                     int* __restrict__ hist, int ntiles, const Ctl* ctl,
-                                                     int dyn) {
-    if (!pass_active(ctl, shift, dyn)) return;
+                                                     int* __restrict__ hist, int ntiles) {
     __shared__ int h[RBINS];
     h[threadIdx.x] = 0;
     __syncthreads();
@@ -221,9 +210,7 @@ __global__ __launch_bounds__(RBLK) void k_radix_hist(const int* __restrict__ key
 // Digit-major exclusive scan of hist[RBINS * ntiles] in three kernels:
 // per-tile sums, one-block scan of those sums, in-tile scan plus offset.
 __global__ __launch_bounds__(SCAN_BLK) void k_rscan_tiles(const int* __restrict__ hist, int total,
-                                                          long long* __restrict__ tile_sum, const Ctl* ctl, int shift,
-                                                          int dyn) {
-    if (!pass_active(ctl, shift, dyn)) return;
+                                                          long long* __restrict__ tile_sum) {
     __shared__ long long sh[SCAN_BLK / WAVE];
     const long long base = (long long)blockIdx.x * SCAN_TILE + (long long)threadIdx.x * SCAN_ITEMS;
     long long s = 0;
@@ -236,9 +223,7 @@ __global__ __launch_bounds__(SCAN_BLK) void k_rscan_tiles(const int* __restrict_
     if (threadIdx.x == 0) tile_sum[blockIdx.x] = s;
 }
 
-__global__ __launch_bounds__(1024) void k_rscan_top(long long* __restrict__ tile_sum, int ntiles, const Ctl* ctl,
-                                                    int shift, int dyn) {
-    if (!pass_active(ctl, shift, dyn)) return;
+__global__ __launch_bounds__(1024) void k_rscan_top(long long* __restrict__ tile_sum, int ntiles) {
     __shared__ long long sh[1024 / WAVE];
     long long carry = 0;
     for (int base = 0; base < ntiles; base += 1024) {
@@ -252,9 +237,7 @@ __global__ __launch_bounds__(1024) void k_rscan_top(long long* __restrict__ tile
 }
 
 __global__ __launch_bounds__(SCAN_BLK) void k_rscan_apply(int* __restrict__ hist, int total,
-                                                          const long long* __restrict__ tile_sum, const Ctl* ctl,
-                                                          int shift, int dyn) {
-    if (!pass_active(ctl, shift, dyn)) return;
+                                                          const long long* __restrict__ tile_sum) {
     __shared__ long long sh[SCAN_BLK / WAVE];
     const long long base = (long long)blockIdx.x * SCAN_TILE + (long long)threadIdx.x * SCAN_ITEMS;
     int x[SCAN_ITEMS];
@@ -276,26 +259,15 @@ __global__ __launch_bounds__(SCAN_BLK) void k_rscan_apply(int* __restrict__ hist
 }
 
 // keys_in: key of item i; vals_in: value of item i (nullptr = i itself).
-// keys_out may be nullptr (last pass).  Inactive pass: copy.
+// keys_out may be nullptr (last pass).
 __global__ __launch_bounds__(RBLK) void k_radix_scatter(const int* __restrict__ keys_in,
                                                         const int* __restrict__ vals_in, int* __restrict__ keys_out,
                                                         int* __restrict__ vals_out, int n, int shift,
-                                                        const int* __restrict__ hist, int ntiles, const Ctl* ctl,
-                                                        int dyn) {
+                                                        const int* __restrict__ hist, int ntiles) {
     const int tid = threadIdx.x;
     const int lane = tid & (WAVE - 1);
     const int wid = tid / WAVE;
     const int base = blockIdx.x * RTILE;
-    if (!pass_active(ctl, shift, dyn)) {
-        for (int k = 0; k < RITEMS; k++) {
-            int i = base + k * RBLK + tid;
-            if (i < n) {
-                if (keys_out) keys_out[i] = keys_in[i];
-                vals_out[i] = vals_in ? vals_in[i] : i;
-            }
-        }
-        return;
-    }
     __shared__ int wcnt[RBLK / WAVE][RBINS];
     __shared__ int tbase[RBINS];
     for (int d = tid; d < RBINS * (RBLK / WAVE); d += RBLK) (&wcnt[0][0])[d] = 0;
@@ -748,28 +720,32 @@ constexpr unsigned long long FCNT_MASK = (1ull << FCNT_SHIFT) - 1;
 // VGPRs) on R-MAT scale 22; at 8 (56 spilled) it is 35% slower.
 constexpr int SEL_U = 2;
 // Packed per-tile item scan value: [edges: bits 0-31][items: 45-63]; the
-// select's per-tile survivor and item counts share a 32-bit word (16 bits each).
+// select's per-tile survivor and item counts share a 32-bit word (16 bits
+// each), and its frontier count is the tile's entries less its survivors.
 constexpr int TITEM_SHIFT = 45;
 static_assert(PEEL_BLK * SEL_U < (1 << 16), "tile counts must fit their packed fields");
 
 // Persistent round loop of one PEEL iteration (cooperative launch, one block
 // per CU).  Per round r:
-//   select: mn = ring.mn[r]; thr = floor((q + p) mn / q).  Block b owns a
-//     contiguous slice of the alive list L_r.  A counting pass classifies
-//     the slice: alive vertices with prio <= thr form the frontier and are
-//     marked round r; the others survive.  One atomic per counter reserves
-//     the block's output ranges.  The frontier items' count and edge total
-//     share one packed 64-bit atomic, so item order and edge offsets agree.
-//     A writing pass then appends the frontier vertices that have edges to
-//     the item list (vertex, edge start, row base, chunk markers) and the
-//     survivors to L_{r+1}.  Survivors bid their priority for ring.mn[r+1].
+//   select: mn = ring.mn[r]; thr = floor((q + p) mn / q) (MONO: at least the
+//     previous round's thr).  Block b owns a contiguous slice of the alive
+//     list L_r.  One pass classifies it: alive vertices with prio <= thr form
+//     the frontier and are marked round r; the others survive.  Survivors go
+//     to the head of the block's own segment of L_{r+1}, frontier vertices to
+//     its tail, with no global reservation.  The frontier vertices with edges
+//     then go to the item list (vertex, edge start, row base, chunk markers)
+//     at a range reserved by one packed 64-bit atomic holding their count and
+//     edge total, so item order and edge offsets agree.  Survivors bid their
+//     priority for ring.mn[r+1].
 //   grid sync
 //   sweep: edge-balanced over the round's items (PeelEdgeOp).  In rounds
 //     with many frontier edges the aggregated decrements go to owner-range
 //     buckets, and after one more grid sync each block applies its ranges'
 //     buckets (global atomics run at about 27 G/s on random targets, which
 //     bounded those rounds).
-//   grid sync
+//   grid sync, in two halves: between them each block builds its map of
+//     L_{r+1} from the segment table and copies its frontier to the order
+//     (positions by round, ascending id inside a round).
 // L_0 is implicit (all vertices).  The loop ends when L_r is empty.  Every
 // block reads the same counters after a grid sync, so all leave together.
 template <bool MONO>
@@ -846,15 +822,16 @@ __global__ __launch_bounds__(PEEL_BLK, PEEL_BLOCKS_PER_CU) void k_peel_rounds(Pe
         // segments the blocks wrote in round r - 1 (segment j starts at
         // seg[start][j] of Lin and holds seg[len][j] entries); L_0 is all
         // vertices.  Block b writes its survivors to Lout[beg, beg + S) and
-        // its frontier vertices that have edges to the tail Lout[end - I,
-        // end), both in one pass without any global reservation, so only the
-        // frontier is read again to place it in the item list.
+        // its frontier vertices to the tail Lout[end - F, end) (in reverse),
+        // both in one pass without any global reservation, so only the
+        // frontier is read again: to place the ones with edges in the item
+        // list, and to write all of them to the order.
         const int per = (Lc + (int)nblocks - 1) / (int)nblocks;
         const int beg = min(Lc, (int)blockIdx.x * per), end = min(Lc, beg + per);
         constexpr int TILE = PEEL_BLK * SEL_U;
         unsigned int lmin = 0xFFFFFFFFu;
         unsigned long long my_edges = 0;
-        int* __restrict__ seg_out = a.seg + (r & 1) * 2 * PEEL_BLK;  // [start | len]
+        int* __restrict__ seg_out = a.seg + (r & 1) * 3 * PEEL_BLK;  // [start | len | frontier len]
         // lds.spref / lds.sstart / s_segtot were filled from the previous
         // round's table inside the round-end barrier.  The segments hold
         // exactly the alive count (both are sums of the same per-block
@@ -887,7 +864,7 @@ __global__ __launch_bounds__(PEEL_BLK, PEEL_BLOCKS_PER_CU) void k_peel_rounds(Pe
         int u[SEL_U], pu[SEL_U], o0[SEL_U], o1[SEL_U];
 #pragma unroll
         for (int k = 0; k < SEL_U; k++) u[k] = -1;  // an empty slice leaves no entries
-        int s_run = 0, i_run = 0;  // survivors and tail items written so far (uniform)
+        int s_run = 0, f_run = 0, i_run = 0;  // survivors, frontier and items so far (uniform)
         for (int base = beg; base < end; base += TILE) {
 #pragma unroll
             for (int k = 0; k < SEL_U; k++) {
@@ -922,18 +899,23 @@ __global__ __launch_bounds__(PEEL_BLK, PEEL_BLOCKS_PER_CU) void k_peel_rounds(Pe
             }
             unsigned int tot;
             const unsigned int ex = block_excl_scan<PEEL_BLK>(val, &tot, shm);
+            // every entry of the tile is a survivor or a frontier vertex (none
+            // is read when the map failed its check)
+            const int tile_n = map_ok ? min(TILE, end - base) : 0;
+            const int before = min((int)threadIdx.x * SEL_U, tile_n);
             int sr = beg + s_run + (int)(ex & 0xFFFFu);
-            int ir = end - 1 - (i_run + (int)(ex >> 16));
+            int fr = end - 1 - (f_run + before - (int)(ex & 0xFFFFu));
 #pragma unroll
             for (int k = 0; k < SEL_U; k++) {
                 if (u[k] < 0) continue;
                 if ((long long)pu[k] > thr) {
                     Lout[sr++] = u[k];
-                } else if (!one_tile && o1[k] > o0[k]) {
-                    Lout[ir--] = u[k];
+                } else {
+                    Lout[fr--] = u[k];
                 }
             }
             s_run += (int)(tot & 0xFFFFu);
+            f_run += tile_n - (int)(tot & 0xFFFFu);
             i_run += (int)(tot >> 16);
         }
         {
@@ -944,25 +926,26 @@ __global__ __launch_bounds__(PEEL_BLK, PEEL_BLOCKS_PER_CU) void k_peel_rounds(Pe
                 if (s_run) atomicAdd(&ctl->lcnt[nslot], (unsigned int)s_run);
                 seg_out[blockIdx.x] = beg;
                 seg_out[PEEL_BLK + blockIdx.x] = s_run;
+                seg_out[2 * PEEL_BLK + blockIdx.x] = f_run;
             }
             __syncthreads();  // also orders the tail writes before the reads below
         }
         unsigned long long fb = s_fbase;
         // item pass: the frontier vertices with edges, from registers (one
         // tile) or from the tail, placed at the reserved item range
-        const int item_end = one_tile ? (end > beg ? 1 : 0) : i_run;  // one register pass, or the tail
+        const int item_end = one_tile ? (end > beg ? 1 : 0) : f_run;  // one register pass, or the tail
         for (int base = 0; base < item_end; base += TILE) {
             if (!one_tile) {
 #pragma unroll
                 for (int k = 0; k < SEL_U; k++) {
                     const int j = base + (int)threadIdx.x * SEL_U + k;
-                    u[k] = j < i_run ? Lout[end - 1 - j] : -1;
+                    u[k] = j < f_run ? Lout[end - 1 - j] : -1;
                 }
 #pragma unroll
                 for (int k = 0; k < SEL_U; k++) {
                     o0[k] = u[k] >= 0 ? a.off[u[k]] : 0;
                     o1[k] = u[k] >= 0 ? a.off[u[k] + 1] : 0;
-                    pu[k] = 0;  // every tail entry is a frontier vertex
+                    pu[k] = 0;  // every tail entry is a frontier vertex (those without edges are skipped)
                 }
             }
             unsigned long long val = 0;
@@ -1055,19 +1038,37 @@ __global__ __launch_bounds__(PEEL_BLK, PEEL_BLOCKS_PER_CU) void k_peel_rounds(Pe
             // the select, so the next round's mapping is built while the
             // round-end barrier completes: the loads share the barrier's wait
             // for outstanding memory operations, the scan runs between its
-            // halves.
-            const int* __restrict__ seg_next = a.seg + (r & 1) * 2 * PEEL_BLK;
+            // halves.  The same scan gives this block's place in the round's
+            // frontier: positions follow rounds, and ascending id inside a
+            // round, which is block order and then slice order; the vertices
+            // peeled before this round hold the first n - Lc positions.
+            const int* __restrict__ seg_next = a.seg + (r & 1) * 3 * PEEL_BLK;
             const int j = (int)threadIdx.x;
             const int len = j < (int)nblocks ? seg_next[PEEL_BLK + j] : 0;
             const int st = j < (int)nblocks ? seg_next[j] : 0;
+            const int fl = j < (int)nblocks ? seg_next[2 * PEEL_BLK + j] : 0;
             grid_arrive(bar);
             unsigned long long tot;
-            const unsigned long long ex = block_excl_scan<PEEL_BLK>((unsigned long long)len, &tot, shs);
+            // [alive entries: bits 0-31][frontier: 32-63]; each sum is below 2^31
+            const unsigned long long ex = block_excl_scan<PEEL_BLK>(
+                ((unsigned long long)(unsigned int)fl << 32) | (unsigned int)len, &tot, shs);
             if (j < (int)nblocks) {
-                lds.spref[j] = (int)ex;
+                lds.spref[j] = (int)(ex & 0xFFFFFFFFull);
                 lds.sstart[j] = st;
             }
-            if (j == 0) s_segtot = tot;
+            if (j == 0) s_segtot = tot & 0xFFFFFFFFull;
+            if (j == (int)blockIdx.x) s_fbase = (unsigned long long)(a.n - Lc) + (ex >> 32);
+            __syncthreads();
+            const long long fb0 = (long long)s_fbase;
+            for (int i = j; i < f_run; i += PEEL_BLK) {
+                const long long p = fb0 + i;
+                if (p < a.n) {
+                    a.order[p] = Lout[end - 1 - i];
+                } else if (i == j) {
+                    atomicAdd(&ctl->err_count, 1);
+                    ctl->err_code = ERR_INTERNAL;
+                }
+            }
             grid_wait(bar);
         }
     }
@@ -1896,9 +1897,8 @@ hipError_t launch_reset_state(const GraphDev& g, hipStream_t s) {
 }
 
 // Stable LSD radix sort of the n vertex ids by key_src[v] over `passes`
-// 8-bit digits; the sorted ids land in g.order.  dyn = 1: passes above the
-// device-known key range (ctl->nrounds) become copies.
-static hipError_t enqueue_radix(const GraphDev& g, const int* key_src, int passes, int dyn, hipStream_t s) {
+// 8-bit digits; the sorted ids land in g.order.
+static hipError_t enqueue_radix(const GraphDev& g, const int* key_src, int passes, hipStream_t s) {
     const int rt = ceil_div(g.n, RTILE);
     for (int p = 0; p < passes; p++) {
         const int shift = 8 * p;
@@ -1908,11 +1908,11 @@ static hipError_t enqueue_radix(const GraphDev& g, const int* key_src, int passe
         int* vout = p == passes - 1 ? g.order : (p & 1 ? g.vB : g.vA);
         const int total = RBINS * rt;
         const int st = ceil_div(total, SCAN_TILE);
-        k_radix_hist<<<rt, RBLK, 0, s>>>(kin, g.n, shift, g.rhist, rt, g.ctl, dyn);
-        k_rscan_tiles<<<st, SCAN_BLK, 0, s>>>(g.rhist, total, g.tile_off, g.ctl, shift, dyn);
-        k_rscan_top<<<1, 1024, 0, s>>>(g.tile_off, st, g.ctl, shift, dyn);
-        k_rscan_apply<<<st, SCAN_BLK, 0, s>>>(g.rhist, total, g.tile_off, g.ctl, shift, dyn);
-        k_radix_scatter<<<rt, RBLK, 0, s>>>(kin, vin, kout, vout, g.n, shift, g.rhist, rt, g.ctl, dyn);
+        k_radix_hist<<<rt, RBLK, 0, s>>>(kin, g.n, shift, g.rhist, rt);
+        k_rscan_tiles<<<st, SCAN_BLK, 0, s>>>(g.rhist, total, g.tile_off);
+        k_rscan_top<<<1, 1024, 0, s>>>(g.tile_off, st);
+        k_rscan_apply<<<st, SCAN_BLK, 0, s>>>(g.rhist, total, g.tile_off);
+        k_radix_scatter<<<rt, RBLK, 0, s>>>(kin, vin, kout, vout, g.n, shift, g.rhist, rt);
     }
     return hipGetLastError();
 }
@@ -1929,12 +1929,6 @@ static hipError_t enqueue_alg3(const GraphDev& g, int slot, int nrounds_static, 
     k_finalize<<<grid_for(g.n, 256, 2048), 256, 0, s>>>(g.n, g.load, g.inc, g.rnd, g.order, g.best_order, g.ctl,
                                                         g.digest + slot, g.hist_w + slot, g.hist_lmax + slot);
     return hipGetLastError();
-}
-
-static int bits_for(long long maxval) {
-    int b = 0;
-    while (b < 62 && (maxval >> b) != 0) b++;
-    return b;
 }
 
 hipError_t enqueue_iter_peel(const GraphDev& g, int slot, int eps_num, int eps_den, int peel_grid,
@@ -1971,6 +1965,7 @@ hipError_t enqueue_iter_peel(const GraphDev& g, int slot, int eps_num, int eps_d
     a.bkt_min_e = bkt_min_e;
     a.coarse_min_e = coarse_min_e;
     a.seg = g.seg;
+    a.order = g.order;
     if (peel_grid > PEEL_BLK) return hipErrorInvalidValue;  // one segment per thread of a block
     void* args[] = {&a};
     if (ev_a && (e = hipEventRecord(ev_a, s)) != hipSuccess) return e;
@@ -1979,11 +1974,7 @@ hipError_t enqueue_iter_peel(const GraphDev& g, int slot, int eps_num, int eps_d
                                    dim3(peel_grid), dim3(PEEL_BLK), args, 0, s);
     if (e != hipSuccess) return e;
     if (ev_b && (e = hipEventRecord(ev_b, s)) != hipSuccess) return e;
-    // rounds <= n, so ceil(bits(n-1)/8) digit passes cover every round index
-    int passes = (bits_for(g.n > 1 ? g.n - 1 : 1) + 7) / 8;
-    if (passes < 1) passes = 1;
-    e = enqueue_radix(g, g.rnd, passes, 1, s);
-    if (e != hipSuccess) return e;
+    // the round loop wrote the order (by round, ascending id inside a round)
     return enqueue_alg3(g, slot, 0, s);
 }
 
@@ -1992,7 +1983,7 @@ hipError_t enqueue_iter_sort(const GraphDev& g, int slot, int key_bits, int sort
     k_iter_begin<<<1, 64, 0, s>>>(g.ctl, nullptr, nullptr, 0);
     int passes = (key_bits + 7) / 8;
     if (passes < 1) passes = 1;
-    hipError_t e = enqueue_radix(g, g.load, passes, 0, s);
+    hipError_t e = enqueue_radix(g, g.load, passes, s);
     if (e != hipSuccess) return e;
     coarse = coarse && g.nnz > 0;
     const int sshift = cr_shift(g.n);
