@@ -1475,9 +1475,9 @@ __global__ __launch_bounds__(256) void k_finalize(int n, int* __restrict__ load,
 // iterations with block barriers only.  The grid-wide round loop is for one
 // large graph.  The per-round rule, same-round edge ownership and
 // Algorithm 3 bookkeeping are the same as in the grid-wide path.  Because
-// one block owns a graph, the alive list is compacted in id order with block
-// scans alone, so each round's frontier comes out in ascending id and its
-// positions follow from one running count.
+// one block owns a graph, the alive list can be compacted in id order, so
+// each round's frontier comes out in ascending id and positions are assigned
+// directly: no sort by round is needed.
 template <int SLOTS>
 struct DecTableT {
     int key[SLOTS];
