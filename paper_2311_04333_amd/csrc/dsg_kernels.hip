@@ -865,11 +865,19 @@ __global__ __launch_bounds__(PEEL_BLK, PEEL_BLOCKS_PER_CU) void k_peel_rounds(Pe
 #pragma unroll
         for (int k = 0; k < SEL_U; k++) u[k] = -1;  // an empty slice leaves no entries
         int s_run = 0, f_run = 0, i_run = 0;  // survivors, frontier and items so far (uniform)
+        // the tile's entries; a tile's successor is loaded before the tile is
+        // classified, so its round trip overlaps the classification
+        auto entry = [&](int idx) -> int {
+            return (idx < end && map_ok) ? ((r == 0) ? idx : Lin[phys(idx)]) : -1;
+        };
+        int un[SEL_U];
+#pragma unroll
+        for (int k = 0; k < SEL_U; k++) un[k] = entry(beg + (int)threadIdx.x * SEL_U + k);
         for (int base = beg; base < end; base += TILE) {
 #pragma unroll
             for (int k = 0; k < SEL_U; k++) {
-                const int idx = base + (int)threadIdx.x * SEL_U + k;
-                u[k] = (idx < end && map_ok) ? ((r == 0) ? idx : Lin[phys(idx)]) : -1;
+                u[k] = un[k];
+                un[k] = entry(base + TILE + (int)threadIdx.x * SEL_U + k);
             }
 #pragma unroll
             for (int k = 0; k < SEL_U; k++) pu[k] = u[k] >= 0 ? a.prio[u[k]] : 0;
@@ -1475,9 +1483,9 @@ __global__ __launch_bounds__(256) void k_finalize(int n, int* __restrict__ load,
 // iterations with block barriers only.  The grid-wide round loop is for one
 // large graph.  The per-round rule, same-round edge ownership and
 // Algorithm 3 bookkeeping are the same as in the grid-wide path.  Because
-// one block owns a graph, the alive list can be compacted in id order, so
-// each round's frontier comes out in ascending id and positions are assigned
-// directly: no sort by round is needed.
+// one block owns a graph, the alive list is compacted in id order with block
+// scans alone, so each round's frontier comes out in ascending id and its
+// positions follow from one running count.
 template <int SLOTS>
 struct DecTableT {
     int key[SLOTS];
