@@ -47,7 +47,6 @@ struct dsg_graph {
     long long bkt_min_e;           // PEEL rounds with at least this many frontier edges use owner buckets
     long long coarse_min_e;        // ... and coarse sweep chunks; -1 = default
     int sort_coarse;               // SORT coarse ranks: -1 = by size, 0 = off, 1 = on
-    int peel_mono;                 // internal: monotone round thresholds (Coreness by buckets)
     // graph replay (dsg_set_graph_replay): the launches of one dsg_run are
     // captured on a private stream into a HIP graph, which later calls with
     // the same key replay on the context's stream
@@ -55,7 +54,7 @@ struct dsg_graph {
     int replay_state;              // 1 = a run is captured, 0 = none yet, -1 = capture refused (eager from then on)
     hipStream_t cap_stream;
     hipGraphExec_t gexec;
-    long long gkey[10];
+    long long gkey[9];
 };
 
 struct dsg_batch {
@@ -368,7 +367,7 @@ dsg_status dsg_run(dsg_graph* g, int32_t T, int32_t eps_num, int32_t eps_den, ds
             if (variant == DSG_PEEL || variant == DSG_PEEL_MONO) {
                 e = dsg::enqueue_iter_peel(g->d, slot, eps_num, eps_den, g->ctx->peel_grid, g->bkt_min_e,
                                            g->coarse_min_e >= 0 ? g->coarse_min_e : dsg::PEEL_DEFAULT_COARSE_MIN_E,
-                                           g->peel_mono || variant == DSG_PEEL_MONO, qs, ea, eb);
+                                           variant == DSG_PEEL_MONO, qs, ea, eb);
             } else if (variant == DSG_SORT) {
                 long long bound = g->load_bound + (long long)t * (long long)g->d.max_deg;
                 int bits = 0;
@@ -390,8 +389,8 @@ dsg_status dsg_run(dsg_graph* g, int32_t T, int32_t eps_num, int32_t eps_den, ds
     bool launched = false;
     if (g->replay && !g->ktime && g->replay_state >= 0 && T > 0) {
         // everything the launches depend on besides the device state
-        const long long key[10] = {T, eps_num, eps_den, (long long)variant, g->recorded, g->load_bound,
-                                   g->bkt_min_e, g->coarse_min_e, g->sort_coarse, g->peel_mono};
+        const long long key[9] = {T, eps_num, eps_den, (long long)variant, g->recorded, g->load_bound,
+                                  g->bkt_min_e, g->coarse_min_e, g->sort_coarse};
         if (!(g->gexec && memcmp(key, g->gkey, sizeof key) == 0)) {
             hipGraph_t graph = nullptr;
             hipGraphExec_t ex = nullptr;
@@ -710,8 +709,8 @@ dsg_status par_cut(dsg_graph* g, const ParWs& w, const int* oldid, int level, in
     return DSG_OK;
 }
 
-// Coreness of the input CSR into w.core / w.kmax: one PEEL pass with zero
-// loads, eps = 0 and monotone thresholds.  Leaves the input graph alive in
+// Coreness of the input CSR into w.core / w.kmax: one DSG_PEEL_MONO pass
+// with zero loads and eps = 0.  Leaves the input graph alive in
 // *gout (its static items serve the first cut).
 dsg_status par_coreness(dsg_ctx* ctx, const ParWs& w, int n, long long nnz, const int32_t* d_offsets,
                         const int32_t* d_adj, int tcap, int flags, bool timed, dsg_graph** gout, int* nrounds_out,
@@ -720,10 +719,8 @@ dsg_status par_coreness(dsg_ctx* ctx, const ParWs& w, int n, long long nnz, cons
     dsg_status st = dsg_graph_create(ctx, n, nnz, d_offsets, d_adj, w.gws, w.gws_bytes, tcap, flags, &g);
     if (st != DSG_OK) return st;
     hipStream_t s = ctx->stream;
-    g->peel_mono = 1;
     if (timed) dsg_set_kernel_timing(g, 1);
-    st = dsg_run(g, 1, 0, 1, DSG_PEEL);
-    g->peel_mono = 0;
+    st = dsg_run(g, 1, 0, 1, DSG_PEEL_MONO);
     if (st != DSG_OK) {
         dsg_graph_destroy(g);
         return st;
