@@ -90,7 +90,7 @@ def main():
                     help="run one plain device copy of this many MiB first (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+        print(f"bench.py: the library runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU sharding is a design, not an implementation", file=sys.stderr)
         sys.exit(2)
 
@@ -497,7 +497,9 @@ def bench_par(args):
         f"({core_rounds} rounds)")
     check = None
     cpu = None
-    if not args.no_check or args.cpu_iters > 0:
+    if args.cpu_iters > 0:
+        # the CPU-baseline leg: the oracle's run of the whole framework, whose
+        # result also serves as the check (no oracle run without this leg)
         from oracle import prune
 
         t2 = time.perf_counter()
