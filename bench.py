@@ -1,28 +1,40 @@
 #!/usr/bin/env python
 """Benchmark: Greedy++ peeling (PaRGreedy++ ordering) on one MI355X.
 
-Workload: R-MAT scale 22 with edge factor 16 and (a,b,c,d) = (.57,.19,.19,.05).
-After symmetrising and deduplicating it has n = 4,194,304 vertices and
-m = 64,156,259 edges.  The run is round-synchronous peeling with
-eps = 1/10 for T = 20 iterations.  One step is one full run of the hot path:
-reset the state, then 20 iterations.  Each iteration does init, the round
-loop with its sweeps, the sort by round, Algorithm 3, and the load and best
-updates.  The graph is resident in HBM before timing starts.
+Default workload: the Chung-Lu power-law graph with n = 40,000,000 vertices,
+degree exponent 2.1, mean degree 30 and degrees capped at 2M (m = 555,487,662
+edges after deduplication; a 4.4 GB int32 CSR resident in HBM).  One step is
+one full run of the hot path: reset the state, then T = 50 Greedy++
+iterations of round-synchronous peeling with eps = 1/20.  Each iteration
+does init, the persistent round loop (select, sweep with the charges and the
+delayed degree decrements, the order by round), Algorithm 3, and the load
+and best updates.  `--workload rmat22` runs R-MAT scale 22 with PEEL
+eps = 1/10, T = 20 per step instead.
 
 Metric: edge-visits/s = 2m * T * steps / wall time of the timed steps.
 
 Also printed, on the same JSON line:
   roofline      the dominant kernel (the persistent round loop).  Its
                 average launch time comes from HIP events recorded on the
-                library's stream during the timed steps.  Its algorithmic
-                bytes per launch are 16m + 16n: each CSR entry read once plus
-                one 4-byte neighbour-state access, and four int32 arrays of
-                length n.  These are divided by that time and compared with
-                8 TB/s.
+                library's stream around every launch of the timed steps.
+                Its algorithmic bytes per launch are 16m + 16n: each CSR
+                entry read once (8m) plus one 4-byte neighbour-state access
+                per entry (8m), and four int32 per-vertex accesses (priority,
+                row bounds, round, order).  The iteration's other 16n
+                (degree init, loads, Algorithm 3's A and suffix scan) are in
+                the smaller kernels; `iteration` gives 16m + 32n over the
+                whole iteration time beside it.  `traffic` is the HBM bytes
+                per launch from committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+                summaries, while they match the kernel sources.
   cpu_baseline  the CPU oracle (single thread) timed on a bounded sample of
-                the same workload: the first iterations of the same run.
+                the same workload (see --cpu-*).
+  legs          (default workload) the sort-based ordering on the same graph
+                and both orderings with exact k-core pruning, one timed run
+                each, with the best density each reaches.
+  check         sum of loads = T*m, the best set's size, and, at the stored
+                sizes, equality with the oracle's stored results.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--variant peel|sort]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3|rmat22|batch|serve|par]
 """
 import argparse
 import hashlib
@@ -52,7 +64,7 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(workload: str, kernel: str, launches_bytes_alg: float):
+def load_traffic(workload: str, kernel: str):
     """HBM bytes per launch from committed rocprofv3 PMC summaries, if they match the current kernel sources."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_pmc.json")
     if not os.path.exists(path):
@@ -65,24 +77,87 @@ def load_traffic(workload: str, kernel: str, launches_bytes_alg: float):
     return p.get("hbm_bytes_per_launch")
 
 
+def host_info():
+    """Cores, CPU model and memory of the host the oracle runs on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    mem = None
+    try:
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemTotal"):
+                    mem = round(int(line.split()[1]) / 2 ** 20, 1)
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"nproc": usable, "cpu_model": model, "mem_gib": mem}
+
+
+def sha(a) -> str:
+    import numpy as np
+
+    return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
+
+
+def golden_check(g, gd, T):
+    """Compare a finished run with a stored oracle result (tests/golden/*.json)."""
+    import numpy as np
+
+    loads = g.loads()
+    digests, rounds = g.digests()
+    dens = g.iter_densities()
+    rnd, pos, _ = g.order()
+    return bool([list(x[:2]) for x in dens] == gd["hist"] and [x[2] for x in dens] == gd["hist_idx"] and
+                [str(d) for d in digests] == gd["digests"] and rounds == gd["rounds"] and
+                list(g.best()) == gd["best"] and sha(loads.astype(np.int64)) == gd["loads_sha256"] and
+                sha(g.best_mask().astype(np.uint8)) == gd["best_mask_sha256"] and
+                sha(rnd.astype(np.int32)) == gd["last_round_sha256"] and
+                sha(pos.astype(np.int32)) == gd["last_pos_sha256"] and int(loads.sum()) == T * (g.nnz // 2))
+
+
+def read_golden(name):
+    path = os.path.join(ROOT, "tests", "golden", name + ".json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        return json.load(f)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="rmat22", choices=["rmat22", "batch", "serve", "par", "c3"],
-                    help="rmat22: one R-MAT scale-22 graph (default); batch: the 4096-graph batched mix; "
-                         "serve: Poisson request stream through the continuous-batching server; par: "
-                         "Pruning-and-Refining (exact k-core pruning) on the R-MAT scale-22 graph")
-    ap.add_argument("--rates", default="100,300,1000,3000", help="serve: offered request rates (req/s)")
+    ap.add_argument("--workload", default="c3", choices=["c3", "rmat22", "batch", "serve", "par"],
+                    help="c3: the 40M-vertex Chung-Lu graph, PEEL eps=1/20, T=50 (default); rmat22: one R-MAT "
+                         "scale-22 graph, PEEL eps=1/10, T=20; batch: the 4096-graph batched mix; serve: Poisson "
+                         "request stream through the continuous-batching server; par: Pruning-and-Refining (exact "
+                         "k-core pruning) on the R-MAT scale-22 graph")
+    ap.add_argument("--rates", default="100,300,1000,3000,5000", help="serve: offered request rates (req/s)")
     ap.add_argument("--window", type=float, default=3.0, help="serve: seconds of Poisson arrivals per rate")
     ap.add_argument("--variant", default="peel", choices=["peel", "sort"])
     ap.add_argument("--count", type=int, default=4096, help="graphs in the batched mix")
     ap.add_argument("--plain-sample", type=int, default=256, help="graphs of the mix timed on the plain path")
-    ap.add_argument("--T", type=int, default=20)
+    ap.add_argument("--T", type=int, default=None, help="iterations per step (default: 50 for c3, 20 otherwise)")
     ap.add_argument("--scale", type=int, default=22)
-    ap.add_argument("--cpu-iters", type=int, default=8,
-                    help="single graph: oracle iterations timed for cpu_baseline (0 = skip)")
+    ap.add_argument("--no-legs", action="store_true", help="c3: skip the SORT and pruned legs")
+    ap.add_argument("--cpu-iters", type=int, default=None,
+                    help="single graph: oracle iterations timed for cpu_baseline (default 6 for c3 on the "
+                         "sample graph, 8 for rmat22; 0 = skip)")
+    ap.add_argument("--cpu-sample-n", type=int, default=4_000_000,
+                    help="c3: vertices of the Chung-Lu sample graph the oracle is timed on (same generator, "
+                         "exponent and mean degree as the 40M-vertex graph, degree cap scaled with n)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="batch: oracle runs of whole graphs (T iterations each) until this much CPU time (0 = skip)")
     ap.add_argument("--no-check", action="store_true")
@@ -90,9 +165,11 @@ def main():
                     help="run one plain device copy of this many MiB first (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: the library runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU sharding is a design, not an implementation", file=sys.stderr)
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); how the path would "
+              "shard over several GPUs is described, not built", file=sys.stderr)
         sys.exit(2)
+    if args.T is None:
+        args.T = 50 if args.workload == "c3" else 20
 
     if args.workload == "batch":
         return bench_batch(args)
@@ -100,22 +177,34 @@ def main():
         return bench_serve(args)
     if args.workload == "par":
         return bench_par(args)
-    if args.workload == "c3":
-        return bench_c3(args)
+    return bench_graph(args)
 
+
+def bench_graph(args):
     import numpy as np
     import torch
 
     import graphgen
     import paper_2311_04333_amd as dsg
 
-    eps = (1, 10) if args.variant == "peel" else (0, 1)
+    c3 = args.workload == "c3"
+    if args.variant == "peel":
+        eps = (1, 20) if c3 else (1, 10)
+    else:
+        eps = (0, 1)
     T = args.T
     t0 = time.time()
-    offsets, adj = graphgen.rmat(1, args.scale, 16 << args.scale, 57, 19, 19)
+    if c3:
+        log("generating Chung-Lu n=40M (one to two minutes)")
+        offsets, adj = graphgen.config3(1)
+        name = f"chunglu40m_{args.variant}"
+        desc = "Chung-Lu n=40M, degree exponent 2.1, mean degree 30, degree cap 2M"
+    else:
+        offsets, adj = graphgen.rmat(1, args.scale, 16 << args.scale, 57, 19, 19)
+        name = f"rmat{args.scale}_{args.variant}"
+        desc = f"R-MAT scale {args.scale}, edge factor 16, (a,b,c,d)=(.57,.19,.19,.05)"
     n, m = len(offsets) - 1, len(adj) // 2
-    workload = f"rmat{args.scale}_{args.variant}"
-    log(f"generated R-MAT scale {args.scale}: n={n} m={m} in {time.time() - t0:.1f}s")
+    log(f"generated {desc}: n={n} m={m} in {time.time() - t0:.1f}s")
 
     if args.copy_calib_mib > 0:
         src = torch.ones(args.copy_calib_mib << 18, dtype=torch.int32, device="cuda")
@@ -125,7 +214,9 @@ def main():
         del src, dst
 
     ctx = dsg.Context(0)
-    g = dsg.Graph(ctx, offsets, adj, t_cap=T)
+    o_dev = torch.from_numpy(offsets).cuda()
+    a_dev = torch.from_numpy(adj).cuda()
+    g = dsg.Graph(ctx, o_dev, a_dev, t_cap=T, validate=False)
     g.set_kernel_timing(True)
     torch.cuda.synchronize()
 
@@ -145,17 +236,19 @@ def main():
     g.sync()
 
     ms_per_step = 1e3 * elapsed / max(args.steps, 1)
-    edge_visits = 2.0 * m * T * args.steps
-    value = edge_visits / elapsed
+    value = 2.0 * m * T * args.steps / elapsed
     kernel = "k_peel_rounds" if args.variant == "peel" else "k_sweep_sort"
-    # algorithmic bytes per launch of the dominant kernel
+    # algorithmic bytes per launch of the dominant kernel, and per iteration
     if args.variant == "peel":
-        alg_bytes = 16.0 * m + 16.0 * n
+        alg_bytes, alg_model = 16.0 * m + 16.0 * n, "16m+16n"
+        it_bytes, it_model = 16.0 * m + 32.0 * n, "16m+32n"
     else:
-        alg_bytes = 16.0 * m + 12.0 * n
+        alg_bytes, alg_model = 16.0 * m + 12.0 * n, "16m+12n"
+        it_bytes, it_model = 16.0 * m + 88.0 * n, "16m+(16P+24)n, P=4 radix passes"
     avg_launch_s = (kern_ms / launches) / 1e3 if launches else float("nan")
     achieved = alg_bytes / avg_launch_s / 1e9
-    traffic = load_traffic(workload, kernel, alg_bytes)
+    traffic = load_traffic(name, kernel)
+    iter_s = elapsed / max(args.steps, 1) / T
     log(f"timed {args.steps} steps: {ms_per_step:.2f} ms/step (last run {run_ms:.2f} ms device), "
         f"{kernel}: {kern_ms / max(launches, 1):.3f} ms/launch over {launches} launches")
 
@@ -164,33 +257,22 @@ def main():
         loads = g.loads()
         best = g.best()
         mask = g.best_mask()
-        ok = int(loads.sum()) == T * m and int(mask.sum()) == best[1]
         check = {"sum_loads_eq_Tm": bool(int(loads.sum()) == T * m), "best_set_size_ok": bool(mask.sum() == best[1])}
-        golden = os.path.join(ROOT, "tests", "golden", f"config2{'' if args.variant == 'peel' else '_sort'}.json")
-        if args.scale == 22 and T == 20 and os.path.exists(golden):
-            with open(golden) as f:
-                gd = json.load(f)
-            digests, rounds = g.digests()
-            dens = g.iter_densities()
-            match = ([list(x[:2]) for x in dens] == gd["hist"] and [str(d) for d in digests] == gd["digests"] and
-                     rounds == gd["rounds"] and list(best) == gd["best"] and
-                     hashlib.sha256(loads.astype(np.int64).tobytes()).hexdigest() == gd["loads_sha256"])
-            check["matches_oracle_golden"] = bool(match)
-            ok = ok and match
-        if not ok:
+        gname = ("config3" + ("_peel" if args.variant == "peel" else "_sort")) if c3 else \
+            ("config2" + ("" if args.variant == "peel" else "_sort"))
+        gd = read_golden(gname)
+        if gd is not None and gd["n"] == n and gd["m"] == m and gd["T"] == T and tuple(gd["eps"]) == eps \
+                and gd["variant"] == args.variant:
+            check["matches_oracle_golden"] = golden_check(g, gd, T)
+        if not all(check.values()):
             log(f"RESULT CHECK FAILED: {check}")
+    g.close()
 
-    cpu = None
-    if args.cpu_iters > 0:
-        import oracle
+    legs = None
+    if c3 and not args.no_legs:
+        legs = c3_legs(args, dsg, ctx, o_dev, a_dev, n, m, T)
 
-        t1 = time.perf_counter()
-        oracle.run(offsets, adj, args.cpu_iters, args.variant, eps)
-        cpu_s = time.perf_counter() - t1
-        cpu = {"value": 2.0 * m * args.cpu_iters / cpu_s, "unit": "edge-visits/s", "cores": 1, "kind": "oracle",
-               "sample": f"first {args.cpu_iters} of the {T} iterations of the same run (same graph, single thread, "
-                         f"{cpu_s:.1f} s)"}
-        log(f"cpu oracle: {args.cpu_iters} iterations in {cpu_s:.1f}s")
+    cpu = cpu_baseline_graph(args, c3, offsets, adj, n, m, T, eps)
 
     line = {
         "metric": "edge-visits/s per Greedy++ iteration (PaRGreedy++ peeling)" if args.variant == "peel"
@@ -206,15 +288,86 @@ def main():
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic",
-        "config": {"workload": f"R-MAT scale {args.scale} (n={n}, m={m}), {args.variant} "
-                               f"eps={eps[0]}/{eps[1]}, T={T} per step"},
+        "config": {"workload": f"{desc} (n={n}, m={m}), {args.variant} eps={eps[0]}/{eps[1]}, T={T} per step"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kernel,
-                     "avg_launch_ms": kern_ms / max(launches, 1), "alg_bytes_per_launch": alg_bytes},
+                     "avg_launch_ms": kern_ms / max(launches, 1), "launches": launches,
+                     "alg_bytes_per_launch": alg_bytes, "alg_bytes_model": alg_model,
+                     "iteration": {"alg_bytes": it_bytes, "alg_bytes_model": it_model, "ms": iter_s * 1e3,
+                                   "achieved": it_bytes / iter_s / 1e9,
+                                   "frac": it_bytes / iter_s / 1e9 / HBM_PEAK_GBS}},
         "cpu_baseline": cpu,
+        "legs": legs,
         "check": check,
     }
+    ctx.close()
     print(json.dumps(line), flush=True)
+
+
+def c3_legs(args, dsg, ctx, o_dev, a_dev, n, m, T):
+    """The sort-based ordering on the same graph, and both orderings with exact k-core pruning (Algorithm 1): one
+    run each after one warm-up iteration, with the best density each reaches."""
+    import torch
+
+    out = {}
+    g = dsg.Graph(ctx, o_dev, a_dev, t_cap=T, validate=False)
+    g.run(1, (0, 1), "sort")
+    g.sync()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    g.reset().run(T, (0, 1), "sort")
+    g.sync()
+    sec = time.perf_counter() - t1
+    e, v = g.best()[:2]
+    rec = {"seconds": sec, "edge_visits_per_s": 2.0 * m * T / sec, "best": [e, v], "density": e / v}
+    gd = read_golden("config3_sort")
+    if gd is not None and gd["n"] == n and gd["T"] == T:
+        rec["matches_oracle_golden"] = golden_check(g, gd, T)
+    g.close()
+    out["sort"] = rec
+    log(f"sort leg: {sec:.2f} s for T={T} ({2.0 * m * T / sec / 1e9:.1f} G edge-visits/s), best {e}/{v}")
+    ws = torch.empty(dsg.par_workspace_bytes(n, int(a_dev.numel()), T) + 256, dtype=torch.uint8, device="cuda")
+    for variant, eps in (("sort", (0, 1)), ("peel", (1, 20))):
+        dsg.par_run(ctx, o_dev, a_dev, 1, eps, variant, validate=False, workspace=ws)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        r = dsg.par_run(ctx, o_dev, a_dev, T, eps, variant, validate=False, workspace=ws)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t1
+        out["par_" + variant] = {"seconds": sec, "best": list(r.best[:2]), "density": r.best[0] / r.best[1],
+                                 "k_max": r.kmax, "first_cut": r.sizes[0] if r.sizes else None,
+                                 "last_cut": r.final_size}
+        log(f"par {variant} leg: {sec:.2f} s for T={T}, best {r.best[0]}/{r.best[1]}, k_max {r.kmax}, "
+            f"cuts {r.sizes[0] if r.sizes else None} -> {r.final_size}")
+    del ws
+    return out
+
+
+def cpu_baseline_graph(args, c3, offsets, adj, n, m, T, eps):
+    """The oracle, single thread, on a bounded sample of the workload.  For the 40M-vertex graph one oracle PEEL
+    iteration takes minutes, so the sample is a smaller graph from the same generator with the same exponent and
+    mean degree (degree cap scaled with n); for R-MAT scale 22 it is the first iterations of the same run."""
+    iters = args.cpu_iters if args.cpu_iters is not None else (6 if c3 else 8)
+    if iters <= 0:
+        return None
+    import graphgen
+    import oracle
+
+    if c3:
+        ns = args.cpu_sample_n
+        o, a = graphgen.config3(1, n=ns, max_deg=2_000_000.0 * ns / 40_000_000)
+        sample = (f"Chung-Lu n={len(o) - 1} (m={len(a) // 2}; same generator, exponent and mean degree as the timed "
+                  f"graph, degree cap scaled with n), {iters} {args.variant} iteration(s)")
+    else:
+        o, a = offsets, adj
+        sample = f"first {iters} of the {T} iterations of the same run (same graph)"
+    t1 = time.perf_counter()
+    oracle.run(o, a, iters, args.variant, eps)
+    cpu_s = time.perf_counter() - t1
+    log(f"cpu oracle: {iters} iterations in {cpu_s:.1f}s")
+    info = host_info()
+    return {"value": 2.0 * (len(a) // 2) * iters / cpu_s, "unit": "edge-visits/s", "cores": 1, "kind": "oracle",
+            "sample": f"{sample}, single thread, {cpu_s:.1f} s", "host": info}
 
 
 def bench_batch(args):
@@ -536,76 +689,6 @@ def bench_par(args):
                      "avg_launch_ms": core_ms, "rounds": core_rounds, "alg_bytes_per_launch": alg_bytes},
         "cpu_baseline": cpu,
         "check": check,
-    }
-    print(json.dumps(line), flush=True)
-
-
-def bench_c3(args):
-    """Config 3: the sort-based ordering against round-synchronous peeling on the 40M-vertex Chung-Lu graph
-    (gamma 2.1, mean degree 30, degrees capped at 2M), T = 50, eps = 1/20 for PEEL, each with and without exact
-    k-core pruning.  One timed run of each, after one warm-up iteration; the line's value is the SORT time and the
-    others sit beside it with the best density each reaches."""
-    from fractions import Fraction
-
-    import torch
-
-    import graphgen
-    import paper_2311_04333_amd as dsg
-
-    T, eps_peel = 50, (1, 20)
-    t0 = time.time()
-    log("generating Chung-Lu n=40M (about two minutes)")
-    offsets, adj = graphgen.config3(1)
-    n, m = len(offsets) - 1, len(adj) // 2
-    log(f"generated n={n} m={m} in {time.time() - t0:.1f}s")
-    ctx = dsg.Context(0)
-    o_dev = torch.from_numpy(offsets).cuda()
-    a_dev = torch.from_numpy(adj).cuda()
-    out = {}
-    for variant, eps in (("sort", (0, 1)), ("peel", eps_peel)):
-        g = dsg.Graph(ctx, o_dev, a_dev, t_cap=T, validate=False)
-        g.reset().run(1, eps, variant)
-        g.sync()
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        g.reset().run(T, eps, variant)
-        g.sync()
-        sec = time.perf_counter() - t1
-        e, v = g.best()[:2]
-        out[variant] = {"seconds": sec, "edge_visits_per_s": 2.0 * m * T / sec, "best": [e, v],
-                        "density": float(Fraction(e, v))}
-        log(f"{variant}: {sec:.2f} s for T={T} ({2.0 * m * T / sec / 1e9:.1f} G edge-visits/s), best {e}/{v}")
-        g.close()
-    ws = torch.empty(dsg.par_workspace_bytes(n, len(adj), T) + 256, dtype=torch.uint8, device="cuda")
-    for variant, eps in (("sort", (0, 1)), ("peel", eps_peel)):
-        dsg.par_run(ctx, o_dev, a_dev, 1, eps, variant, validate=False, workspace=ws)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        r = dsg.par_run(ctx, o_dev, a_dev, T, eps, variant, validate=False, workspace=ws)
-        torch.cuda.synchronize()
-        sec = time.perf_counter() - t1
-        out["par_" + variant] = {"seconds": sec, "best": list(r.best[:2]),
-                                 "density": float(Fraction(r.best[0], r.best[1])), "k_max": r.kmax,
-                                 "first_cut": r.sizes[0] if r.sizes else None, "last_cut": r.final_size}
-        log(f"par {variant}: {sec:.2f} s for T={T}, best {r.best[0]}/{r.best[1]}, k_max {r.kmax}, "
-            f"cuts {r.sizes[0] if r.sizes else None} -> {r.final_size}")
-    line = {
-        "metric": "config 3: seconds for T iterations, SORT vs PEEL, with and without exact k-core pruning",
-        "value": out["sort"]["seconds"],
-        "unit": "s",
-        "n_gpus": 1,
-        "steps": 1,
-        "warmup": 1,
-        "ms_per_step": out["sort"]["seconds"] * 1e3,
-        "higher_is_better": False,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "int32",
-        "data": "synthetic",
-        "config": {"workload": f"Chung-Lu n={n} m={m} (gamma 2.1, mean degree 30, max degree 2M), T={T}, "
-                               f"PEEL eps=1/20"},
-        "runs": out,
-        "peel_over_sort_time": out["peel"]["seconds"] / out["sort"]["seconds"],
     }
     print(json.dumps(line), flush=True)
 

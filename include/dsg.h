@@ -277,6 +277,47 @@ dsg_status dsg_par_run(dsg_ctx* ctx, int32_t n, int64_t nnz, const int32_t* d_of
                        int64_t* h_iter_verts, int32_t* h_iter_index, int32_t* h_iter_n, int64_t* h_iter_nnz,
                        int32_t* h_iter_level, uint8_t* h_best_mask, int32_t* h_core);
 
+/* Approximate k-core pruning (Definition "c-Approx k-Core Decomposition",
+ * Corollary apxkmax, and the frameworks PaRApxSorting++ and PaRApxGreedy++
+ * of Section 4, "Implementations").  The paper cites the decomposition it
+ * uses without describing it; here it is round-synchronous peeling with a
+ * monotone geometric bound, the Coreness pass run with eps = c - 1: round r
+ * peels every alive vertex whose degree is at most
+ *   D_r = max(D_{r-1}, floor(c * minimum degree among the alive vertices)),
+ * and khat(v) = D at v's round.  Then core(v) <= khat(v) <= c * core(v)
+ * (the first vertex of the core(v)-core to go has degree >= core(v) when it
+ * goes; every vertex alive at a round has core number >= that round's
+ * minimum degree), so it is a c-approximate decomposition.  c = 3/2 is the
+ * ratio the paper's experiments use.
+ *   first cut: L <- ceil(khat_max / (2c)) = ceil(khat_max * c_den / (2 c_num)),
+ *              G <- {v : khat(v) >= L}, which holds every densest subgraph;
+ *   then_exact = 0 (PaRApxSorting++ with DSG_SORT): the re-cuts of Algorithm 1
+ *              use khat at level ceil(L) (valid since khat >= core);
+ *   then_exact = 1 (PaRApxGreedy++ with DSG_PEEL): exact core numbers of the
+ *              cut graph (equal to the input's at every level >= L), then the
+ *              cut to max(L, ceil(k_max / 2)) and exact re-cuts, so every
+ *              refined graph, and every result, is that of dsg_par_run; only
+ *              the exact Coreness pass runs on the smaller graph.
+ * result->kmax is khat_max (then_exact = 0) or the exact k_max; h_core holds
+ * the core numbers the cuts use, in input ids (khat, or the exact numbers of
+ * the cut graph with 0 outside it); h_apx_core (n int32, optional) holds
+ * khat.  1 < c_num / c_den, c_num <= 2^20.  Other arguments, workspace,
+ * outputs and errors as dsg_par_run. */
+typedef struct {
+    int32_t apx_kmax;   /* largest approximate core number */
+    int32_t apx_level;  /* level of the first (approximate) cut */
+    int32_t apx_n;      /* vertices of the approximate cut */
+    int32_t pad;
+    int64_t apx_nnz;    /* adjacency entries of the approximate cut */
+} dsg_par_apx;
+
+dsg_status dsg_par_run_apx(dsg_ctx* ctx, int32_t n, int64_t nnz, const int32_t* d_offsets, const int32_t* d_adj,
+                           void* d_workspace, int64_t workspace_bytes, int32_t T, int32_t eps_num, int32_t eps_den,
+                           dsg_variant variant, int32_t flags, int32_t then_exact, int32_t c_num, int32_t c_den,
+                           dsg_par_result* result, dsg_par_apx* apx, int64_t* h_iter_edges, int64_t* h_iter_verts,
+                           int32_t* h_iter_index, int32_t* h_iter_n, int64_t* h_iter_nnz, int32_t* h_iter_level,
+                           uint8_t* h_best_mask, int32_t* h_core, int32_t* h_apx_core);
+
 /* ------------------------------------------------------------------ batches
  * Many independent graphs peeled in one persistent launch (DSG_PEEL rule).
  * Each graph's results are bit-identical to running it alone through
@@ -359,7 +400,9 @@ dsg_status dsg_server_footprint(int32_t n, int64_t nnz, int32_t T, int64_t* byte
 
 /* Launch the persistent kernel (cfg 0 = 256 threads / 1024-edge chunks,
  * 1 = 512 / 2048; blocks_per_cu >= 1).  It exits on dsg_server_stop, after
- * idle_seconds with nothing to do, or after max_seconds in total. */
+ * idle_seconds with nothing to do, or after max_seconds in total.  A request
+ * that was admitted but never claimed (published just as an idle kernel
+ * exited) is run by the next dsg_server_start, oldest first. */
 dsg_status dsg_server_start(dsg_server* s, int32_t cfg, int32_t blocks_per_cu, double idle_seconds,
                             double max_seconds);
 

@@ -16,6 +16,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import sys
 from fractions import Fraction
 
 import numpy as np
@@ -54,6 +55,8 @@ SIGNATURES = [
     ("dsg_par_workspace_bytes", ctypes.c_int, [_I32, _I64, _I32, _P]),
     ("dsg_par_run", ctypes.c_int, [_P, _I32, _I64, _P, _P, _P, _I64, _I32, _I32, _I32, _I32, _I32, _P, _P, _P, _P, _P,
                                    _P, _P, _P, _P]),
+    ("dsg_par_run_apx", ctypes.c_int, [_P, _I32, _I64, _P, _P, _P, _I64, _I32, _I32, _I32, _I32, _I32, _I32, _I32,
+                                       _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     ("dsg_set_peel_tuning", ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int64]),
     ("dsg_set_sort_tuning", ctypes.c_int, [_P, _I32]),
     ("dsg_set_graph_replay", ctypes.c_int, [_P, _I32]),
@@ -138,6 +141,18 @@ def _check(status: int):
         raise DsgError(status, msg.decode() if msg else "")
 
 
+def _finalize(obj):
+    """Garbage-collection release of a handle.  At interpreter exit the HIP
+    runtime (and any profiler attached to it) may already be torn down, so no
+    library call is made then: close handles explicitly before exiting."""
+    if sys.is_finalizing():
+        return
+    try:
+        obj.close()
+    except Exception:
+        pass
+
+
 def parse_eps(eps) -> tuple[int, int]:
     """eps as an exact rational (num, den); a decimal string or float literal is read exactly."""
     if isinstance(eps, tuple):
@@ -181,10 +196,7 @@ class Context:
             self._h = ctypes.c_void_p()
 
     def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
+        _finalize(self)
 
 
 class Graph:
@@ -345,10 +357,7 @@ class Graph:
             self._h = ctypes.c_void_p()
 
     def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
+        _finalize(self)
 
 
 class Batch:
@@ -465,10 +474,7 @@ class Batch:
             self._h = ctypes.c_void_p()
 
     def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
+        _finalize(self)
 
 
 class BatchGraphView:
@@ -598,16 +604,18 @@ class Server:
             self._h = ctypes.c_void_p()
 
     def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
+        _finalize(self)
 
 
 class _ParResultC(ctypes.Structure):
     _fields_ = [("best_edges", ctypes.c_int64), ("best_verts", ctypes.c_int64), ("best_iter", ctypes.c_int32),
                 ("kmax", ctypes.c_int32), ("level", ctypes.c_int32), ("prunes", ctypes.c_int32),
                 ("final_n", ctypes.c_int32), ("pad", ctypes.c_int32), ("final_nnz", ctypes.c_int64)]
+
+
+class _ParApxC(ctypes.Structure):
+    _fields_ = [("apx_kmax", ctypes.c_int32), ("apx_level", ctypes.c_int32), ("apx_n", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("apx_nnz", ctypes.c_int64)]
 
 
 class ParResult:
@@ -627,6 +635,10 @@ class ParResult:
         self.levels = levels
         self.best_mask = best_mask
         self.core = core
+        self.apx_core = None
+        self.apx_kmax = 0
+        self.apx_level = 0
+        self.apx_size = None
 
 
 def par_workspace_bytes(n: int, nnz: int, T: int) -> int:
@@ -636,9 +648,13 @@ def par_workspace_bytes(n: int, nnz: int, T: int) -> int:
 
 
 def par_run(ctx: Context, offsets, adj, T: int, eps=(0, 1), variant: str = "peel", validate: bool = True,
-            workspace=None) -> ParResult:
-    """dsg_par_run on a CSR (numpy arrays or int32 device tensors).  `workspace` (a uint8 device tensor of at least
-    par_workspace_bytes + 256 bytes) may be passed to reuse one allocation across calls."""
+            workspace=None, prune: str = "exact", c=(3, 2)) -> ParResult:
+    """dsg_par_run (prune="exact") or dsg_par_run_apx (prune="apx": approximate k-core pruning only; "apx_exact":
+    approximate, then exact) on a CSR (numpy arrays or int32 device tensors).  `c` is the approximation ratio
+    c_num / c_den.  `workspace` (a uint8 device tensor of at least par_workspace_bytes + 256 bytes) may be passed to
+    reuse one allocation across calls."""
+    if prune not in ("exact", "apx", "apx_exact"):
+        raise ValueError(f"unknown pruning {prune!r}")
     import torch
 
     dev = ctx.torch_device
@@ -650,7 +666,6 @@ def par_run(ctx: Context, offsets, adj, T: int, eps=(0, 1), variant: str = "peel
         workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
     base = workspace.data_ptr()
     aligned = (base + 255) // 256 * 256
-    c = _ParResultC()
     he = np.zeros(max(T, 1), dtype=np.int64)
     hv = np.zeros(max(T, 1), dtype=np.int64)
     hi = np.zeros(max(T, 1), dtype=np.int32)
@@ -660,14 +675,32 @@ def par_run(ctx: Context, offsets, adj, T: int, eps=(0, 1), variant: str = "peel
     mask = np.zeros(n, dtype=np.uint8)
     core = np.zeros(n, dtype=np.int32)
     num, den = parse_eps(eps)
-    _check(library().dsg_par_run(ctx.handle, n, nnz, ctypes.c_void_p(o.data_ptr()),
-                                 ctypes.c_void_p(a.data_ptr() if nnz > 0 else 0), ctypes.c_void_p(aligned), nbytes, T,
-                                 num, den, VARIANTS[variant], VALIDATE if validate else 0, ctypes.addressof(c),
-                                 he.ctypes.data, hv.ctypes.data, hi.ctypes.data, hn.ctypes.data, hm.ctypes.data,
-                                 hl.ctypes.data, mask.ctypes.data, core.ctypes.data))
+    res = _ParResultC()
+    d_off = ctypes.c_void_p(o.data_ptr())
+    d_adj = ctypes.c_void_p(a.data_ptr() if nnz > 0 else 0)
+    outs = (he.ctypes.data, hv.ctypes.data, hi.ctypes.data, hn.ctypes.data, hm.ctypes.data, hl.ctypes.data,
+            mask.ctypes.data, core.ctypes.data)
+    flags = VALIDATE if validate else 0
+    apx = None
+    if prune == "exact":
+        _check(library().dsg_par_run(ctx.handle, n, nnz, d_off, d_adj, ctypes.c_void_p(aligned), nbytes, T, num, den,
+                                     VARIANTS[variant], flags, ctypes.addressof(res), *outs))
+    else:
+        apx = _ParApxC()
+        apx_core = np.zeros(n, dtype=np.int32)
+        _check(library().dsg_par_run_apx(ctx.handle, n, nnz, d_off, d_adj, ctypes.c_void_p(aligned), nbytes, T, num,
+                                         den, VARIANTS[variant], flags, 1 if prune == "apx_exact" else 0, int(c[0]),
+                                         int(c[1]), ctypes.addressof(res), ctypes.addressof(apx), *outs,
+                                         apx_core.ctypes.data))
     hist = [(int(he[t]), int(hv[t])) for t in range(T)]
-    return ParResult(c, hist, [int(x) for x in hi[:T]], [(int(hn[t]), int(hm[t])) for t in range(T)],
-                     [int(x) for x in hl[:T]], mask.astype(bool), core)
+    r = ParResult(res, hist, [int(x) for x in hi[:T]], [(int(hn[t]), int(hm[t])) for t in range(T)],
+                  [int(x) for x in hl[:T]], mask.astype(bool), core)
+    if apx is not None:
+        r.apx_core = apx_core
+        r.apx_kmax = int(apx.apx_kmax)
+        r.apx_level = int(apx.apx_level)
+        r.apx_size = (int(apx.apx_n), int(apx.apx_nnz) // 2)
+    return r
 
 
 def coreness(ctx: Context, offsets, adj, validate: bool = True, timed: bool = False):

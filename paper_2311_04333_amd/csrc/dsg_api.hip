@@ -54,7 +54,7 @@ struct dsg_graph {
     int replay_state;              // 1 = a run is captured, 0 = none yet, -1 = capture refused (eager from then on)
     hipStream_t cap_stream;
     hipGraphExec_t gexec;
-    long long gkey[9];
+    long long gkey[10];
 };
 
 struct dsg_batch {
@@ -389,8 +389,9 @@ dsg_status dsg_run(dsg_graph* g, int32_t T, int32_t eps_num, int32_t eps_den, ds
     bool launched = false;
     if (g->replay && !g->ktime && g->replay_state >= 0 && T > 0) {
         // everything the launches depend on besides the device state
-        const long long key[9] = {T, eps_num, eps_den, (long long)variant, g->recorded, g->load_bound,
-                                  g->bkt_min_e, g->coarse_min_e, g->sort_coarse};
+        const long long key[10] = {T, eps_num, eps_den, (long long)variant, g->recorded, g->load_bound,
+                                   g->bkt_min_e, g->coarse_min_e, g->sort_coarse,
+                                   (long long)reinterpret_cast<uintptr_t>(g->d.rmin)};
         if (!(g->gexec && memcmp(key, g->gkey, sizeof key) == 0)) {
             hipGraph_t graph = nullptr;
             hipGraphExec_t ex = nullptr;
@@ -643,6 +644,8 @@ struct ParWs {
     int* core;
     int* rv;
     int* kmax;
+    int* apx;    // approximate core numbers, input ids
+    int* core1;  // exact core numbers of the approximate cut, its own ids
     int* off[2];
     int* adj[2];
     int* oldid[2];
@@ -663,6 +666,7 @@ long long carve_par(int n, long long nnz, int T, char* base, ParWs* w) {
     const long long gb = carve(n, nnz, T, nullptr, nullptr);
     long long o_g = L.add(gb);
     long long o_core = L.add(4 * N), o_rv = L.add(4 * (N + 1)), o_km = L.add(16);
+    long long o_apx = L.add(4 * N), o_core1 = L.add(4 * N);
     long long o_off0 = L.add(4 * (N + 1)), o_adj0 = L.add(4 * (E > 0 ? E : 1));
     long long o_off1 = L.add(4 * (N + 1)), o_adj1 = L.add(4 * (E > 0 ? E : 1));
     long long o_id0 = L.add(4 * N), o_id1 = L.add(4 * N), o_iota = L.add(4 * N), o_load = L.add(4 * N);
@@ -675,6 +679,8 @@ long long carve_par(int n, long long nnz, int T, char* base, ParWs* w) {
         w->core = reinterpret_cast<int*>(base + o_core);
         w->rv = reinterpret_cast<int*>(base + o_rv);
         w->kmax = reinterpret_cast<int*>(base + o_km);
+        w->apx = reinterpret_cast<int*>(base + o_apx);
+        w->core1 = reinterpret_cast<int*>(base + o_core1);
         w->off[0] = reinterpret_cast<int*>(base + o_off0);
         w->adj[0] = reinterpret_cast<int*>(base + o_adj0);
         w->off[1] = reinterpret_cast<int*>(base + o_off1);
@@ -694,10 +700,11 @@ long long carve_par(int n, long long nnz, int T, char* base, ParWs* w) {
     return L.total;
 }
 
-// Cut the `level`-core out of graph g into CSR buffer `dst`; returns the new
-// sizes.  Loads of the kept vertices go to w.load.
-dsg_status par_cut(dsg_graph* g, const ParWs& w, const int* oldid, int level, int dst, int* n_out, long long* nnz_out) {
-    dsg::CoreCut c{oldid, w.core, level, w.keep, w.newid, w.f, w.fs, w.tiles,
+// Cut {x : core[oldid[x]] >= level} out of graph g into CSR buffer `dst`;
+// returns the new sizes.  Loads of the kept vertices go to w.load.
+dsg_status par_cut(dsg_graph* g, const ParWs& w, const int* core, const int* oldid, int level, int dst, int* n_out,
+                   long long* nnz_out) {
+    dsg::CoreCut c{oldid, core, level, w.keep, w.newid, w.f, w.fs, w.tiles,
                    w.off[dst], w.adj[dst], w.oldid[dst], w.load, w.counts};
     hipError_t e = dsg::launch_get_core(g->d, c, g->ctx->stream);
     if (e != hipSuccess) return hip_fail(e, "getCore");
@@ -709,18 +716,21 @@ dsg_status par_cut(dsg_graph* g, const ParWs& w, const int* oldid, int level, in
     return DSG_OK;
 }
 
-// Coreness of the input CSR into w.core / w.kmax: one DSG_PEEL_MONO pass
-// with zero loads and eps = 0.  Leaves the input graph alive in
-// *gout (its static items serve the first cut).
+// Core numbers of a CSR into core_out / w.kmax: one DSG_PEEL_MONO pass with
+// zero loads and eps = eps_num / eps_den: exact with eps = 0, otherwise the
+// (1 + eps)-approximate decomposition (core <= khat <= (1 + eps) core).
+// Leaves the graph alive in *gout (its static items serve the next cut).
 dsg_status par_coreness(dsg_ctx* ctx, const ParWs& w, int n, long long nnz, const int32_t* d_offsets,
-                        const int32_t* d_adj, int tcap, int flags, bool timed, dsg_graph** gout, int* nrounds_out,
-                        int* kmax_out, float* ms_out) {
+                        const int32_t* d_adj, int tcap, int flags, bool timed, int eps_num, int eps_den, int* core_out,
+                        dsg_graph** gout, int* nrounds_out, int* kmax_out, float* ms_out) {
     dsg_graph* g = nullptr;
     dsg_status st = dsg_graph_create(ctx, n, nnz, d_offsets, d_adj, w.gws, w.gws_bytes, tcap, flags, &g);
     if (st != DSG_OK) return st;
     hipStream_t s = ctx->stream;
     if (timed) dsg_set_kernel_timing(g, 1);
-    st = dsg_run(g, 1, 0, 1, DSG_PEEL_MONO);
+    g->d.rmin = w.rv;  // the round loop records each round's minimum (at most n rounds)
+    st = dsg_run(g, 1, eps_num, eps_den, DSG_PEEL_MONO);
+    g->d.rmin = nullptr;
     if (st != DSG_OK) {
         dsg_graph_destroy(g);
         return st;
@@ -736,7 +746,7 @@ dsg_status par_coreness(dsg_ctx* ctx, const ParWs& w, int n, long long nnz, cons
     hipError_t e;
     if ((e = hipStreamSynchronize(s)) != hipSuccess ||
         (e = hipMemcpy(&nrounds, g->d.rounds, sizeof(int), hipMemcpyDeviceToHost)) != hipSuccess ||
-        (e = dsg::launch_core_numbers(g->d, nrounds, w.rv, w.core, w.kmax, s)) != hipSuccess ||
+        (e = dsg::launch_core_numbers(g->d, nrounds, w.rv, core_out, w.kmax, s)) != hipSuccess ||
         (e = hipStreamSynchronize(s)) != hipSuccess ||
         (e = hipMemcpy(&kmax, w.kmax, sizeof(int), hipMemcpyDeviceToHost)) != hipSuccess) {
         dsg_graph_destroy(g);
@@ -767,8 +777,8 @@ dsg_status dsg_coreness(dsg_ctx* ctx, int32_t n, int64_t nnz, const int32_t* d_o
     dsg_graph* g = nullptr;
     int nr = 0, km = 0;
     float ms = 0.f;
-    dsg_status st = par_coreness(ctx, w, n, nnz, d_offsets, d_adj, 1, flags, round_loop_ms != nullptr, &g, &nr, &km,
-                                 &ms);
+    dsg_status st = par_coreness(ctx, w, n, nnz, d_offsets, d_adj, 1, flags, round_loop_ms != nullptr, 0, 1, w.core,
+                                 &g, &nr, &km, &ms);
     if (st != DSG_OK) return st;
     dsg_graph_destroy(g);
     *kmax = km;
@@ -787,11 +797,18 @@ dsg_status dsg_par_workspace_bytes(int32_t n, int64_t nnz, int32_t T, int64_t* b
     return DSG_OK;
 }
 
-dsg_status dsg_par_run(dsg_ctx* ctx, int32_t n, int64_t nnz, const int32_t* d_offsets, const int32_t* d_adj,
-                       void* d_workspace, int64_t workspace_bytes, int32_t T, int32_t eps_num, int32_t eps_den,
-                       dsg_variant variant, int32_t flags, dsg_par_result* result, int64_t* h_iter_edges,
-                       int64_t* h_iter_verts, int32_t* h_iter_index, int32_t* h_iter_n, int64_t* h_iter_nnz,
-                       int32_t* h_iter_level, uint8_t* h_best_mask, int32_t* h_core) {
+}  // extern "C"
+
+namespace {
+
+// Algorithm 1 with exact (prune 0), approximate (1) or approximate-then-exact
+// (2) pruning; see dsg_par_run and dsg_par_run_apx.
+dsg_status par_run_impl(dsg_ctx* ctx, int32_t n, int64_t nnz, const int32_t* d_offsets, const int32_t* d_adj,
+                        void* d_workspace, int64_t workspace_bytes, int32_t T, int32_t eps_num, int32_t eps_den,
+                        dsg_variant variant, int32_t flags, int prune, int c_num, int c_den, dsg_par_result* result,
+                        dsg_par_apx* apx_out, int64_t* h_iter_edges, int64_t* h_iter_verts, int32_t* h_iter_index,
+                        int32_t* h_iter_n, int64_t* h_iter_nnz, int32_t* h_iter_level, uint8_t* h_best_mask,
+                        int32_t* h_core, int32_t* h_apx_core) {
     if (!ctx || !d_offsets || !d_workspace || !result) return fail(DSG_EINVAL, "NULL argument");
     if (nnz > 0 && !d_adj) return fail(DSG_EINVAL, "d_adj is NULL");
     if (n < 1 || n >= dsg::PEEL_MAX_N) return fail(DSG_EINVAL, "n must be in [1, 2^26)");
@@ -800,6 +817,8 @@ dsg_status dsg_par_run(dsg_ctx* ctx, int32_t n, int64_t nnz, const int32_t* d_of
     if (eps_num < 0 || eps_den < 1) return fail(DSG_EINVAL, "eps must be eps_num >= 0, eps_den >= 1");
     if (variant != DSG_SEQ && variant != DSG_PEEL && variant != DSG_SORT && variant != DSG_PEEL_MONO)
         return fail(DSG_EINVAL, "unknown variant");
+    if (prune != 0 && (c_den < 1 || c_num <= c_den || c_num > (1 << 20)))
+        return fail(DSG_EINVAL, "the approximation ratio c = c_num / c_den must be > 1 (c_num <= 2^20)");
     const int tcap = T > 0 ? T : 1;
     const long long need = carve_par(n, nnz, tcap, nullptr, nullptr);
     if (workspace_bytes < need) return fail(DSG_EINVAL, "workspace too small (dsg_par_workspace_bytes)");
@@ -812,23 +831,65 @@ dsg_status dsg_par_run(dsg_ctx* ctx, int32_t n, int64_t nnz, const int32_t* d_of
         if (g) dsg_graph_destroy(g);
         return st;
     };
-    // Coreness of the input graph (Coreness by buckets on the PEEL round loop)
-    int nrounds = 0, kmax = 0;
-    dsg_status st = par_coreness(ctx, w, n, nnz, d_offsets, d_adj, tcap, flags, false, &g, &nrounds, &kmax, nullptr);
-    if (st != DSG_OK) return st;
+    const int created_flags = flags & ~DSG_VALIDATE;  // a cut of a valid graph is valid
+    hipError_t e;
+    int cur = 0, nc = 0, kmax = 0, level = 0, nrounds = 0;
+    long long mc = 0;
+    const int* cut_core = w.core;  // the core numbers (input ids) the cuts use
+    dsg_par_apx apx{};
+    dsg_status st;
+    if (prune == 0) {
+        // Coreness of the input graph (Coreness by buckets on the PEEL round loop),
+        // then the ceil(k_max / 2)-core
+        st = par_coreness(ctx, w, n, nnz, d_offsets, d_adj, tcap, flags, false, 0, 1, w.core, &g, &nrounds, &kmax,
+                          nullptr);
+        if (st != DSG_OK) return st;
+        level = (kmax + 1) / 2;
+        if ((e = dsg::launch_iota(w.iota, n, s)) != hipSuccess) return bail(hip_fail(e, "iota"));
+        if ((st = par_cut(g, w, w.core, w.iota, level, cur, &nc, &mc)) != DSG_OK) return bail(st);
+    } else {
+        // the c-approximate decomposition (the round loop with eps = c - 1),
+        // then the ceil(khat_max / 2c)-approximate core (Corollary apxkmax)
+        st = par_coreness(ctx, w, n, nnz, d_offsets, d_adj, tcap, flags, false, c_num - c_den, c_den, w.apx, &g,
+                          &nrounds, &apx.apx_kmax, nullptr);
+        if (st != DSG_OK) return st;
+        apx.apx_level = (int)(((long long)apx.apx_kmax * c_den + 2LL * c_num - 1) / (2LL * c_num));
+        if ((e = dsg::launch_iota(w.iota, n, s)) != hipSuccess) return bail(hip_fail(e, "iota"));
+        if ((st = par_cut(g, w, w.apx, w.iota, apx.apx_level, cur, &nc, &mc)) != DSG_OK) return bail(st);
+        apx.apx_n = nc;
+        apx.apx_nnz = mc;
+        level = apx.apx_level;
+        kmax = apx.apx_kmax;
+        cut_core = w.apx;
+        if (prune == 2) {
+            // exact core numbers of the cut graph: at every level >= the
+            // approximate one its cores are the input's
+            dsg_graph_destroy(g);
+            g = nullptr;
+            st = par_coreness(ctx, w, nc, mc, w.off[cur], w.adj[cur], tcap, created_flags, false, 0, 1, w.core1, &g,
+                              &nrounds, &kmax, nullptr);
+            if (st != DSG_OK) return st;
+            if ((e = dsg::launch_scatter(w.core1, w.oldid[cur], nc, w.core, n, s)) != hipSuccess)
+                return bail(hip_fail(e, "core numbers to input ids"));
+            cut_core = w.core;
+            // the exact max(L, ceil(k_max / 2))-core of the cut graph (it may
+            // drop vertices even when the level stays: the approximate cut
+            // keeps some vertices whose core number is below it)
+            const int lv = (kmax + 1) / 2;
+            if (lv > level) level = lv;
+            int nn = 0;
+            long long mm = 0;
+            if ((st = par_cut(g, w, w.core, w.oldid[cur], level, 1 - cur, &nn, &mm)) != DSG_OK) return bail(st);
+            cur = 1 - cur;
+            nc = nn;
+            mc = mm;
+        }
+    }
     if (((long long)T + 1) * (long long)g->d.max_deg >= (1LL << 31))
         return bail(fail(DSG_EOVERFLOW, "loads could exceed 31 bits: (T + 1) * max_degree >= 2^31"));
-    hipError_t e;
-    // initial prune to the ceil(k_max / 2)-core, loads zero
-    int level = (kmax + 1) / 2;
-    if ((st = dsg_reset(g)) != DSG_OK) return bail(st);
-    if ((e = dsg::launch_iota(w.iota, n, s)) != hipSuccess) return bail(hip_fail(e, "iota"));
-    int cur = 0, nc = 0;
-    long long mc = 0;
-    if ((st = par_cut(g, w, w.iota, level, cur, &nc, &mc)) != DSG_OK) return bail(st);
     dsg_graph_destroy(g);
     g = nullptr;
-    const int created_flags = flags & ~DSG_VALIDATE;  // a cut of a valid graph is valid
+    // S <- G: the first refined graph, loads zero
     if ((st = dsg_graph_create(ctx, nc, mc, w.off[cur], w.adj[cur], w.gws, w.gws_bytes, tcap, created_flags, &g)) !=
         DSG_OK)
         return st;
@@ -863,7 +924,7 @@ dsg_status dsg_par_run(dsg_ctx* ctx, int32_t n, int64_t nnz, const int32_t* d_of
                 prunes++;
                 int nn = 0;
                 long long mm = 0;
-                if ((st = par_cut(g, w, w.oldid[cur], level, 1 - cur, &nn, &mm)) != DSG_OK) return bail(st);
+                if ((st = par_cut(g, w, cut_core, w.oldid[cur], level, 1 - cur, &nn, &mm)) != DSG_OK) return bail(st);
                 const long long lb = g->load_bound;
                 dsg_graph_destroy(g);
                 g = nullptr;
@@ -890,10 +951,38 @@ dsg_status dsg_par_run(dsg_ctx* ctx, int32_t n, int64_t nnz, const int32_t* d_of
     result->prunes = prunes;
     result->final_n = nc;
     result->final_nnz = mc;
+    if (apx_out) *apx_out = apx;
     if (h_best_mask) DSG_HIP(hipMemcpy(h_best_mask, w.mask, (size_t)n, hipMemcpyDeviceToHost), "hipMemcpy(mask)");
-    if (h_core) DSG_HIP(hipMemcpy(h_core, w.core, sizeof(int) * (size_t)n, hipMemcpyDeviceToHost), "hipMemcpy(core)");
+    if (h_core) DSG_HIP(hipMemcpy(h_core, cut_core, sizeof(int) * (size_t)n, hipMemcpyDeviceToHost), "hipMemcpy(core)");
+    if (h_apx_core && prune != 0)
+        DSG_HIP(hipMemcpy(h_apx_core, w.apx, sizeof(int) * (size_t)n, hipMemcpyDeviceToHost), "hipMemcpy(apx core)");
     dsg_graph_destroy(g);
     return DSG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+dsg_status dsg_par_run(dsg_ctx* ctx, int32_t n, int64_t nnz, const int32_t* d_offsets, const int32_t* d_adj,
+                       void* d_workspace, int64_t workspace_bytes, int32_t T, int32_t eps_num, int32_t eps_den,
+                       dsg_variant variant, int32_t flags, dsg_par_result* result, int64_t* h_iter_edges,
+                       int64_t* h_iter_verts, int32_t* h_iter_index, int32_t* h_iter_n, int64_t* h_iter_nnz,
+                       int32_t* h_iter_level, uint8_t* h_best_mask, int32_t* h_core) {
+    return par_run_impl(ctx, n, nnz, d_offsets, d_adj, d_workspace, workspace_bytes, T, eps_num, eps_den, variant,
+                        flags, 0, 1, 1, result, nullptr, h_iter_edges, h_iter_verts, h_iter_index, h_iter_n,
+                        h_iter_nnz, h_iter_level, h_best_mask, h_core, nullptr);
+}
+
+dsg_status dsg_par_run_apx(dsg_ctx* ctx, int32_t n, int64_t nnz, const int32_t* d_offsets, const int32_t* d_adj,
+                           void* d_workspace, int64_t workspace_bytes, int32_t T, int32_t eps_num, int32_t eps_den,
+                           dsg_variant variant, int32_t flags, int32_t then_exact, int32_t c_num, int32_t c_den,
+                           dsg_par_result* result, dsg_par_apx* apx, int64_t* h_iter_edges, int64_t* h_iter_verts,
+                           int32_t* h_iter_index, int32_t* h_iter_n, int64_t* h_iter_nnz, int32_t* h_iter_level,
+                           uint8_t* h_best_mask, int32_t* h_core, int32_t* h_apx_core) {
+    return par_run_impl(ctx, n, nnz, d_offsets, d_adj, d_workspace, workspace_bytes, T, eps_num, eps_den, variant,
+                        flags, then_exact ? 2 : 1, c_num, c_den, result, apx, h_iter_edges, h_iter_verts,
+                        h_iter_index, h_iter_n, h_iter_nnz, h_iter_level, h_best_mask, h_core, h_apx_core);
 }
 
 
@@ -1377,10 +1466,20 @@ dsg_status dsg_server_start(dsg_server* s, int32_t cfg, int32_t blocks_per_cu, d
     if (e != hipSuccess) return hip_fail(e, "clear error flag");
     const unsigned long long idle = (unsigned long long)(idle_seconds * 1e8);  // 100 MHz wall clock
     const unsigned long long maxt = (unsigned long long)(max_seconds * 1e8);
-    // requests published before a restart are never replayed: the claim
-    // counter restarts at the current tail
-    const unsigned long long tail = __atomic_load_n(&s->hctl->tail, __ATOMIC_ACQUIRE);
-    e = dsg::launch_serve(s->hctl_dev, s->ring_dev, s->ring_size, s->dhead, tail, s->derr, cfg, blocks_per_cu,
+    // The claim counter restarts at the oldest published request that has
+    // not finished.  A block always finishes the request it claimed before it
+    // looks at the queue again, so once the previous kernel has exited every
+    // claimed ticket is done and every unfinished one was never claimed: a
+    // request published just as the last block left (after the submit's
+    // running check) is run now instead of holding its ring slot and pool
+    // regions for good.  Tickets are claimed in order, so the unfinished ones
+    // are exactly [head0, tail).
+    unsigned long long head0 = __atomic_load_n(&s->hctl->tail, __ATOMIC_ACQUIRE);
+    for (const ServeReq& r : s->reqs) {
+        const dsg::ServeSlot* sl = &s->ring[r.ticket % (uint64_t)s->ring_size];
+        if (__atomic_load_n(&sl->done, __ATOMIC_ACQUIRE) != r.ticket + 1 && r.ticket < head0) head0 = r.ticket;
+    }
+    e = dsg::launch_serve(s->hctl_dev, s->ring_dev, s->ring_size, s->dhead, head0, s->derr, cfg, blocks_per_cu,
                           s->ctx->num_cu, idle, maxt, s->kstream);
     if (e != hipSuccess) return hip_fail(e, "serve launch");
     s->running = true;

@@ -85,6 +85,7 @@ struct PeelArgs {
     long long coarse_min_e;  // frontier edges from which a round sweeps coarse chunks
     int* seg;              // per block, by round parity: [2][alive start | alive len | frontier len][PEEL_BLK]
     int* order;            // order[position] = vertex, written round by round
+    int* rmin;             // optional: rmin[r] = round r's priority bound thr (room for n rounds)
 };
 
 struct SweepArgs {
@@ -157,6 +158,7 @@ struct GraphDev {
     int* cr_samp;      // degrees at the sampled positions
     int* seg;          // PEEL alive-list segments (4 * PEEL_BLK ints)
     long long* cr_tsum;  // sampled degree mass per tile of 1024 samples
+    int* rmin;         // optional, set by the caller for one run: per-round priority bound (n ints)
     int n_items;  // vertices with degree > 0
     int max_deg;
 };

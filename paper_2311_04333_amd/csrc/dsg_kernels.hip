@@ -795,6 +795,9 @@ __global__ __launch_bounds__(PEEL_BLK, PEEL_BLOCKS_PER_CU) void k_peel_rounds(Pe
             __syncthreads();
             if (threadIdx.x == 0) s_thr = thr;
         }
+        // the round's bound (with zero loads and eps = 0 it is the core number
+        // of every vertex the round peels; with eps > 0 an approximate one)
+        if (a.rmin && blockIdx.x == 0 && threadIdx.x == 0) a.rmin[r] = (int)min(thr, 0x7FFFFFFFLL);
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             const int zs = (r + 2) & 3;
             ctl->mn[zs] = 0xFFFFFFFFu;
@@ -1974,6 +1977,7 @@ hipError_t enqueue_iter_peel(const GraphDev& g, int slot, int eps_num, int eps_d
     a.coarse_min_e = coarse_min_e;
     a.seg = g.seg;
     a.order = g.order;
+    a.rmin = g.rmin;
     if (peel_grid > PEEL_BLK) return hipErrorInvalidValue;  // one segment per thread of a block
     void* args[] = {&a};
     if (ev_a && (e = hipEventRecord(ev_a, s)) != hipSuccess) return e;

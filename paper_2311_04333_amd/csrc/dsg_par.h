@@ -9,13 +9,15 @@ namespace dsg {
 // Exclusive-scan scratch: one int64 per 4096-element tile.
 long long par_scan_tiles(long long count);
 
-// Core numbers from a finished PEEL iteration run with zero loads, eps = 0
-// and monotone thresholds on graph `g`: round r peels every alive vertex
-// whose degree is at most D_r = max(D_{r-1}, round minimum), and a peeled
-// vertex's priority stays at its degree when peeled, so core(v) is the
-// running maximum of the round minima up to v's round (Coreness, Section 2,
-// by buckets).  `rv` holds `nrounds` ints of scratch.  Writes core[0..n)
-// and *kmax_dev (one int).
+// Core numbers from a finished PEEL iteration run with zero loads and
+// monotone thresholds on graph `g`: round r peels every alive vertex whose
+// degree is at most D_r = max(D_{r-1}, floor((1 + eps) * round minimum)),
+// and core(v) = D at v's round.  With eps = 0 these are the exact core
+// numbers (Coreness, Section 2, by buckets); with eps > 0 they are a
+// (1 + eps)-approximate decomposition with core <= khat <= (1 + eps) core.
+// `rv` holds the round bounds, written by the round loop (GraphDev::rmin);
+// their running maximum is taken in place (they are already monotone).
+// Writes core[0..n) and *kmax_dev (one int).
 hipError_t launch_core_numbers(const GraphDev& g, int nrounds, int* rv, int* core, int* kmax_dev, hipStream_t s);
 
 // Subgraph of the current graph `g` induced by {x : core[oldid[x]] >= level}
@@ -52,5 +54,9 @@ hipError_t launch_vertex_mask(int n, const int* oldid, unsigned char* mask, long
 
 // out[i] = i for i < n.
 hipError_t launch_iota(int* out, int n, hipStream_t s);
+
+// dst[0..n_dst) = 0, then dst[idx[x]] = src[x] for x < n_src (core numbers of
+// a cut graph, moved to input ids).
+hipError_t launch_scatter(const int* src, const int* idx, int n_src, int* dst, long long n_dst, hipStream_t s);
 
 }  // namespace dsg

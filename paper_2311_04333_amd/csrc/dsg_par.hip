@@ -102,16 +102,6 @@ __global__ void k_par_fill(int* __restrict__ p, int v, long long cnt) {
         p[i] = v;
 }
 
-// rv[r] = the smallest priority among the vertices peeled in round r (the
-// round minimum: a peeled vertex's priority stays at its value when peeled)
-__global__ void k_round_value(int n, int nrounds, const int* __restrict__ rnd, const int* __restrict__ prio,
-                              int* __restrict__ rv) {
-    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
-        const int r = rnd[v];
-        if (r >= 0 && r < nrounds) atomicMin(&rv[r], prio[v]);
-    }
-}
-
 // rv[r] = max(rv[0..r]) in place; *kmax = rv[nrounds - 1] (0 without rounds)
 __global__ __launch_bounds__(PBLK) void k_prefix_max(int* __restrict__ rv, int nrounds, int* __restrict__ kmax) {
     __shared__ int sh[PBLK];
@@ -145,10 +135,6 @@ __global__ void k_core_from_rounds(int n, int nrounds, const int* __restrict__ r
 }
 
 hipError_t launch_core_numbers(const GraphDev& g, int nrounds, int* rv, int* core, int* kmax_dev, hipStream_t s) {
-    if (nrounds > 0) {
-        k_par_fill<<<grid_cap(nrounds, 256, 2048), 256, 0, s>>>(rv, 0x7FFFFFFF, nrounds);
-        k_round_value<<<grid_cap(g.n, 256, 2048), 256, 0, s>>>(g.n, nrounds, g.rnd, g.prio, rv);
-    }
     k_prefix_max<<<1, PBLK, 0, s>>>(rv, nrounds, kmax_dev);
     k_core_from_rounds<<<grid_cap(g.n, 256, 2048), 256, 0, s>>>(g.n, nrounds, g.rnd, rv, core);
     return hipGetLastError();
@@ -281,6 +267,16 @@ __global__ void k_iota(int* __restrict__ out, int n) {
 
 hipError_t launch_iota(int* out, int n, hipStream_t s) {
     if (n > 0) k_iota<<<grid_cap(n, 256, 4096), 256, 0, s>>>(out, n);
+    return hipGetLastError();
+}
+
+__global__ void k_scatter(const int* __restrict__ src, const int* __restrict__ idx, int n, int* __restrict__ dst) {
+    for (int x = blockIdx.x * blockDim.x + threadIdx.x; x < n; x += gridDim.x * blockDim.x) dst[idx[x]] = src[x];
+}
+
+hipError_t launch_scatter(const int* src, const int* idx, int n_src, int* dst, long long n_dst, hipStream_t s) {
+    if (n_dst > 0) k_par_fill<<<grid_cap(n_dst, 256, 4096), 256, 0, s>>>(dst, 0, n_dst);
+    if (n_src > 0) k_scatter<<<grid_cap(n_src, 256, 4096), 256, 0, s>>>(src, idx, n_src, dst);
     return hipGetLastError();
 }
 

@@ -3,7 +3,9 @@
 Calls only the CPU oracle (oracle/) on graphs from the seeded generators
 (graphgen/); nothing here touches the GPU path.  Usage:
 
-    python tests/golden/make_golden.py config2      # R-MAT scale 22, PEEL eps=1/10, T=20 (~2 min)
+    python tests/golden/make_golden.py config2       # R-MAT scale 22, PEEL eps=1/10, T=20 (~2 min)
+    python tests/golden/make_golden.py config3_sort  # Chung-Lu n=40M, SORT, T=50
+    python tests/golden/make_golden.py config3_peel  # Chung-Lu n=40M, PEEL eps=1/20, T=50
 
 Each file records the workload, a hash of the generated CSR (so a generator
 change is caught separately from a peeling mismatch), the per-iteration
@@ -35,6 +37,10 @@ WORKLOADS = {
                     desc="R-MAT scale 22, edge factor 16, (a,b,c,d)=(.57,.19,.19,.05), seed 1; PEEL eps=1/10, T=20"),
     "config2_sort": dict(gen=lambda: graphgen.config2(1), T=20, variant="sort", eps=(0, 1),
                          desc="R-MAT scale 22 as above; SORT, T=20"),
+    "config3_sort": dict(gen=lambda: graphgen.config3(1), T=50, variant="sort", eps=(0, 1),
+                         desc="Chung-Lu n=40M, gamma 2.1, mean weight 30, weight cap 2M, seed 1; SORT, T=50"),
+    "config3_peel": dict(gen=lambda: graphgen.config3(1), T=50, variant="peel", eps=(1, 20),
+                         desc="Chung-Lu n=40M as above; PEEL eps=1/20, T=50"),
 }
 
 

@@ -122,3 +122,49 @@ def test_coreness_chunglu_40m(dsg, ctx):
     log(f"coreness: k_max={kmax}, {rounds} rounds, {ms:.1f} ms; oracle")
     ref, rk = oracle.coreness(o, a)
     assert kmax == rk and np.array_equal(core, ref)
+
+
+# ------------------------------------------------------------------ approximate k-core pruning
+def assert_apx_same(g, r, what):
+    assert_par_same(g, r, what)
+    assert np.array_equal(g.apx_core, r.apx_core), \
+        f"{what}: approximate core numbers differ at {np.flatnonzero(g.apx_core != r.apx_core)[:10]}"
+    assert (g.apx_kmax, g.apx_level, g.apx_size) == (r.apx_kmax, r.apx_level, r.apx_size), \
+        f"{what}: approximate cut {(g.apx_kmax, g.apx_level, g.apx_size)} vs {(r.apx_kmax, r.apx_level, r.apx_size)}"
+
+
+APX_CASES = ["single_vertex", "no_edges_n7", "one_edge", "triangle", "K40", "star_3000", "path_50", "isolated_mix",
+             "two_cliques", "gnp_8", "config1_s1", "config1_s2", "ragged_12289", "rmat12", "rmat16", "chunglu_200k"]
+
+
+@pytest.mark.parametrize("name", APX_CASES)
+def test_par_apx_against_oracle(dsg, ctx, name):
+    """PaRApxSorting++ (approximate pruning, SORT) and PaRApxGreedy++ (approximate then exact pruning, PEEL), plus
+    the crossed pairs, at c = 3/2 and c = 2, against the oracle's frameworks bit for bit, including the approximate
+    core numbers of every vertex."""
+    o, a = _cases()[name]
+    for prune_mode, variant, eps in [("apx", "sort", (0, 1)), ("apx_exact", "peel", (1, 10)),
+                                     ("apx", "peel", (1, 20)), ("apx_exact", "sort", (0, 1))]:
+        for c in [(3, 2), (2, 1)]:
+            log(f"par apx case={name} prune={prune_mode} variant={variant} eps={eps} c={c}")
+            ref = prune.par_run(o, a, 8, variant, eps, prune=prune_mode, c=c)
+            g = dsg.par_run(ctx, o, a, 8, eps, variant, prune=prune_mode, c=c)
+            assert_apx_same(g, ref, f"{name}/{prune_mode}/{variant}/{c}")
+
+
+def test_par_apx_rmat22_full_size(dsg, ctx):
+    """R-MAT scale 22: PaRApxGreedy++ (PEEL eps = 1/10) and PaRApxSorting++ (SORT), c = 3/2, T = 20."""
+    log("par apx: generating R-MAT scale 22")
+    o, a = graphgen.config2(1)
+    for prune_mode, variant, eps in [("apx_exact", "peel", (1, 10)), ("apx", "sort", (0, 1))]:
+        log(f"par apx rmat22: oracle {prune_mode}/{variant}")
+        ref = prune.par_run(o, a, 20, variant, eps, prune=prune_mode, c=(3, 2))
+        g = dsg.par_run(ctx, o, a, 20, eps, variant, prune=prune_mode, c=(3, 2))
+        assert_apx_same(g, ref, f"rmat22/{prune_mode}/{variant}")
+
+
+def test_par_apx_invalid_ratio(dsg, ctx):
+    o, a = graphgen.complete(5)
+    for c in [(1, 1), (2, 3), (3, 0)]:
+        with pytest.raises(dsg.DsgError):
+            dsg.par_run(ctx, o, a, 2, (1, 10), "peel", prune="apx", c=c)

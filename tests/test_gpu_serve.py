@@ -196,3 +196,56 @@ def test_serve_register_validation(dsg, ctx):
         assert srv.register(*graphgen.rmat(5, 14, 16 << 14), validate=True) == 0
     finally:
         srv.close()
+
+
+def test_serve_restart_runs_unclaimed(dsg, ctx):
+    """A kernel that leaves when idle, and requests submitted around its exits.
+
+    With a very short idle limit the persistent kernel keeps exiting between
+    bursts; a submit then reports DSG_ESTATE and the server is started again.
+    A request published just as the last block left (after the submit's
+    running check) was never claimed: the next start must run it, so every
+    ticket handed out finishes and matches the oracle.
+    """
+    graphs = small_mix(41, 12, nmax=3000)
+    srv = dsg.Server(ctx, 1 << 30, ring_size=32)
+    srv.start(cfg=1, blocks_per_cu=1, idle_seconds=0.002, max_seconds=60)
+    tickets, pending, results, restarts = {}, set(), {}, 0
+    try:
+        for burst in range(30):
+            for k in range(2):
+                i = (2 * burst + k) % len(graphs)
+                o, a = graphs[i]
+                while True:
+                    try:
+                        t = srv.submit(o, a, 2, (1, 10))
+                    except dsg.DsgError as e:
+                        assert e.status == -5, e  # the kernel left: start it again
+                        srv.start(cfg=1, blocks_per_cu=1, idle_seconds=0.002, max_seconds=60)
+                        restarts += 1
+                        continue
+                    break
+                if t is None:  # ring or pool full: collect results first
+                    drain(srv, pending, results, timeout=60)
+                    continue
+                tickets[t] = i
+                pending.add(t)
+            time.sleep(0.001 * (burst % 4))
+            for t in srv.poll():
+                results[t] = srv.fetch(t, loads=True)
+                srv.release(t)
+                pending.discard(t)
+        # whatever is still unclaimed runs once the server is started again
+        try:
+            srv.stop()
+        except dsg.DsgError:
+            pass
+        srv.start(cfg=1, blocks_per_cu=1, idle_seconds=5, max_seconds=60)
+        drain(srv, pending, results, timeout=60)
+    finally:
+        srv.stop()
+        srv.close()
+    log(f"restart test: {len(tickets)} requests, {restarts} restarts")
+    for t, i in tickets.items():
+        o, a = graphs[i]
+        check_result(results[t], o, a, 2, (1, 10), f"ticket {t} graph {i}")
