@@ -48,7 +48,9 @@
  *     are allowed.
  *   - The library allocates no device memory.  All device state lives in
  *     one caller-provided workspace of dsg_workspace_bytes() bytes, which
- *     must stay alive (with the CSR) until dsg_graph_destroy.
+ *     must stay alive (with the CSR) until dsg_graph_destroy.  The one
+ *     exception is dsg_par_run_noalloc, which uses a static device array of
+ *     the library instead of a workspace.
  *   - Work is enqueued asynchronously on the context's HIP stream.  The
  *     dsg_get_* calls synchronise that stream before reading.
  *   - Handles are not thread-safe; use one context per host thread.
@@ -317,6 +319,30 @@ dsg_status dsg_par_run_apx(dsg_ctx* ctx, int32_t n, int64_t nnz, const int32_t* 
                            dsg_par_result* result, dsg_par_apx* apx, int64_t* h_iter_edges, int64_t* h_iter_verts,
                            int32_t* h_iter_index, int32_t* h_iter_n, int64_t* h_iter_nnz, int32_t* h_iter_level,
                            uint8_t* h_best_mask, int32_t* h_core, int32_t* h_apx_core);
+
+/* For callers that cannot allocate device memory (code under HIP stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): dsg_par_run
+ * without a workspace.  Its kernels use a static device array of
+ * DSG_NOALLOC_SCRATCH_BYTES instead, one per GPU, which the library holds from
+ * its load until the process ends.  The call allocates nothing: no device or
+ * pinned memory, no streams or events, no handles (the HIP objects of the
+ * context excepted, made by dsg_ctx_create).  The graph must satisfy
+ * dsg_par_workspace_bytes(n, nnz, T) <= DSG_NOALLOC_SCRATCH_BYTES, else
+ * DSG_ENOMEM with the needed size in the message (e.g. n = 2^18 with 8.4M
+ * CSR entries at T = 50 fits; n = 2^20 with 16.8M does not).  Every call on one
+ * GPU shares that GPU's scratch and leaves its contents behind; each call
+ * initialises what it reads, so calls in sequence are independent, but calls
+ * that overlap on one GPU (two host threads, or two contexts on different
+ * streams) race and give undefined results.  Arguments, outputs, results and
+ * other errors as dsg_par_run; DSG_EDEVICE if the scratch address could not be
+ * resolved on the context's device. */
+#define DSG_NOALLOC_SCRATCH_BYTES (256LL << 20)
+
+dsg_status dsg_par_run_noalloc(dsg_ctx* ctx, int32_t n, int64_t nnz, const int32_t* d_offsets, const int32_t* d_adj,
+                               int32_t T, int32_t eps_num, int32_t eps_den, dsg_variant variant, int32_t flags,
+                               dsg_par_result* result, int64_t* h_iter_edges, int64_t* h_iter_verts,
+                               int32_t* h_iter_index, int32_t* h_iter_n, int64_t* h_iter_nnz, int32_t* h_iter_level,
+                               uint8_t* h_best_mask, int32_t* h_core);
 
 /* ------------------------------------------------------------------ batches
  * Many independent graphs peeled in one persistent launch (DSG_PEEL rule).

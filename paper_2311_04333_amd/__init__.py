@@ -57,6 +57,8 @@ SIGNATURES = [
                                    _P, _P, _P, _P]),
     ("dsg_par_run_apx", ctypes.c_int, [_P, _I32, _I64, _P, _P, _P, _I64, _I32, _I32, _I32, _I32, _I32, _I32, _I32,
                                        _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    ("dsg_par_run_noalloc", ctypes.c_int, [_P, _I32, _I64, _P, _P, _I32, _I32, _I32, _I32, _I32, _P, _P, _P, _P, _P,
+                                           _P, _P, _P, _P]),
     ("dsg_set_peel_tuning", ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int64]),
     ("dsg_set_sort_tuning", ctypes.c_int, [_P, _I32]),
     ("dsg_set_graph_replay", ctypes.c_int, [_P, _I32]),
@@ -701,6 +703,41 @@ def par_run(ctx: Context, offsets, adj, T: int, eps=(0, 1), variant: str = "peel
         r.apx_level = int(apx.apx_level)
         r.apx_size = (int(apx.apx_n), int(apx.apx_nnz) // 2)
     return r
+
+
+NOALLOC_SCRATCH_BYTES = 256 << 20  # DSG_NOALLOC_SCRATCH_BYTES of include/dsg.h
+
+
+def par_run_noalloc(ctx: Context, offsets, adj, T: int, eps=(0, 1), variant: str = "peel",
+                    validate: bool = True) -> ParResult:
+    """dsg_par_run_noalloc: dsg_par_run on the library's static device scratch, for callers that cannot allocate.
+    `offsets` and `adj` must already be int32 tensors on the context's device (this call copies nothing to the
+    device); outputs land in host arrays."""
+    import torch
+
+    for x in (offsets, adj):
+        if not (isinstance(x, torch.Tensor) and x.dtype == torch.int32 and x.device == ctx.torch_device
+                and x.is_contiguous()):
+            raise ValueError("par_run_noalloc takes contiguous int32 CSR tensors on the context's device")
+    n, nnz = int(offsets.numel()) - 1, int(adj.numel())
+    he = np.zeros(max(T, 1), dtype=np.int64)
+    hv = np.zeros(max(T, 1), dtype=np.int64)
+    hi = np.zeros(max(T, 1), dtype=np.int32)
+    hn = np.zeros(max(T, 1), dtype=np.int32)
+    hm = np.zeros(max(T, 1), dtype=np.int64)
+    hl = np.zeros(max(T, 1), dtype=np.int32)
+    mask = np.zeros(n, dtype=np.uint8)
+    core = np.zeros(n, dtype=np.int32)
+    num, den = parse_eps(eps)
+    res = _ParResultC()
+    _check(library().dsg_par_run_noalloc(ctx.handle, n, nnz, ctypes.c_void_p(offsets.data_ptr()),
+                                         ctypes.c_void_p(adj.data_ptr() if nnz > 0 else 0), T, num, den,
+                                         VARIANTS[variant], VALIDATE if validate else 0, ctypes.addressof(res),
+                                         he.ctypes.data, hv.ctypes.data, hi.ctypes.data, hn.ctypes.data,
+                                         hm.ctypes.data, hl.ctypes.data, mask.ctypes.data, core.ctypes.data))
+    hist = [(int(he[t]), int(hv[t])) for t in range(T)]
+    return ParResult(res, hist, [int(x) for x in hi[:T]], [(int(hn[t]), int(hm[t])) for t in range(T)],
+                     [int(x) for x in hl[:T]], mask.astype(bool), core)
 
 
 def coreness(ctx: Context, offsets, adj, validate: bool = True, timed: bool = False):

@@ -10,6 +10,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -20,6 +21,13 @@
 #include "dsg_par.h"
 
 using dsg::GraphDev;
+
+// Static device scratch of dsg_par_run_noalloc.  Each GPU the library runs on
+// holds its own copy from module load until the process ends.  In host code
+// the name `scratch` is only a stand-in: its device address on each GPU comes
+// from hipGetSymbolAddress (resolved once per device, at dsg_ctx_create) and
+// only that address is ever passed to kernels or copies.
+static __device__ __align__(256) unsigned char scratch[DSG_NOALLOC_SCRATCH_BYTES];
 
 struct dsg_ctx {
     int device;
@@ -78,6 +86,26 @@ struct dsg_batch {
 namespace {
 
 thread_local std::string g_err;
+
+// The device scratch of dsg_par_run_noalloc is `scratch` (file scope, above
+// this namespace); its per-device addresses are kept here.
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+bool g_scratch_done[SCRATCH_MAX_DEVICES];
+void* g_scratch_ptr[SCRATCH_MAX_DEVICES];
+hipError_t g_scratch_err[SCRATCH_MAX_DEVICES];
+
+// Resolves the scratch address on `device` (which must be current), once.
+void resolve_scratch(int device) {
+    if (device < 0 || device >= SCRATCH_MAX_DEVICES) return;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_done[device]) return;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    g_scratch_err[device] = e;
+    g_scratch_ptr[device] = e == hipSuccess ? p : nullptr;
+    g_scratch_done[device] = true;
+}
 
 dsg_status fail(dsg_status st, const std::string& msg) {
     g_err = msg;
@@ -229,6 +257,7 @@ dsg_status dsg_ctx_create(int device, void* hip_stream, dsg_ctx** out) {
     DSG_HIP(hipGetDeviceCount(&ndev), "hipGetDeviceCount");
     if (device < 0 || device >= ndev) return fail(DSG_EDEVICE, "no such device");
     DSG_HIP(hipSetDevice(device), "hipSetDevice");
+    resolve_scratch(device);  // a failure is reported by dsg_par_run_noalloc only
     hipDeviceProp_t prop;
     DSG_HIP(hipGetDeviceProperties(&prop, device), "hipGetDeviceProperties");
     if (!prop.cooperativeLaunch) return fail(DSG_EDEVICE, "device lacks cooperative launch");
@@ -261,11 +290,19 @@ dsg_status dsg_workspace_bytes(int32_t n, int64_t nnz, int32_t t_cap, int64_t* b
     return DSG_OK;
 }
 
-dsg_status dsg_graph_create(dsg_ctx* ctx, int32_t n, int64_t nnz, const int32_t* d_offsets, const int32_t* d_adj,
-                            void* d_workspace, int64_t workspace_bytes, int32_t t_cap, int32_t flags,
-                            dsg_graph** out) {
-    if (!ctx || !out || !d_offsets || !d_workspace) return fail(DSG_EINVAL, "NULL argument");
-    *out = nullptr;
+}  // extern "C"
+
+namespace {
+
+// Binds a device CSR to caller storage *g (value-initialised): carves the
+// workspace, checks the CSR, builds the static items and resets the state.
+// `events`: create the two events that time each dsg_run.  Graphs made inside
+// the library (Pruning-and-Refining) skip them, so those calls create no HIP
+// objects.  On failure *g holds nothing to release.
+dsg_status graph_init(dsg_graph* g, dsg_ctx* ctx, int32_t n, int64_t nnz, const int32_t* d_offsets,
+                      const int32_t* d_adj, void* d_workspace, int64_t workspace_bytes, int32_t t_cap, int32_t flags,
+                      bool events) {
+    if (!ctx || !d_offsets || !d_workspace) return fail(DSG_EINVAL, "NULL argument");
     if (n < 1) return fail(DSG_EINVAL, "n must be >= 1");
     if (nnz < 0 || nnz > dsg::MAX_NNZ) return fail(DSG_EINVAL, "nnz must be in [0, 2^31 - 2^16]");
     if (nnz > 0 && !d_adj) return fail(DSG_EINVAL, "adj is NULL");
@@ -274,8 +311,6 @@ dsg_status dsg_graph_create(dsg_ctx* ctx, int32_t n, int64_t nnz, const int32_t*
     long long need = carve(n, nnz, t_cap, nullptr, nullptr);
     if (workspace_bytes < need) return fail(DSG_ENOMEM, "workspace smaller than dsg_workspace_bytes()");
     DSG_HIP(hipSetDevice(ctx->device), "hipSetDevice");
-    dsg_graph* g = new (std::nothrow) dsg_graph();
-    if (!g) return fail(DSG_ENOMEM, "host allocation failed");
     g->ctx = ctx;
     g->ws = static_cast<char*>(d_workspace);
     g->ws_bytes = workspace_bytes;
@@ -290,44 +325,80 @@ dsg_status dsg_graph_create(dsg_ctx* ctx, int32_t n, int64_t nnz, const int32_t*
     g->d.adj = d_adj;
     carve(n, nnz, t_cap, g->ws, &g->d);
     hipStream_t s = ctx->stream;
-    auto bail = [&](dsg_status st) {
-        delete g;
-        return st;
-    };
     hipError_t e;
-    if ((e = dsg::launch_zero_ctl(g->d, s)) != hipSuccess) return bail(hip_fail(e, "zero ctl"));
-    if ((e = dsg::launch_check_offsets(g->d, s)) != hipSuccess) return bail(hip_fail(e, "check offsets"));
+    if ((e = dsg::launch_zero_ctl(g->d, s)) != hipSuccess) return hip_fail(e, "zero ctl");
+    if ((e = dsg::launch_check_offsets(g->d, s)) != hipSuccess) return hip_fail(e, "check offsets");
     dsg_status st = check_errors(g, "offsets");
-    if (st != DSG_OK) return bail(st);
-    if ((e = dsg::launch_check_range(g->d, s)) != hipSuccess) return bail(hip_fail(e, "check range"));
+    if (st != DSG_OK) return st;
+    if ((e = dsg::launch_check_range(g->d, s)) != hipSuccess) return hip_fail(e, "check range");
     st = check_errors(g, "entries");
-    if (st != DSG_OK) return bail(st);
+    if (st != DSG_OK) return st;
     // offsets and entries are in range now, so the static item list (which
     // the row check walks) can be built
-    if ((e = dsg::launch_build_static_items(g->d, s)) != hipSuccess) return bail(hip_fail(e, "static items"));
+    if ((e = dsg::launch_build_static_items(g->d, s)) != hipSuccess) return hip_fail(e, "static items");
     dsg::Ctl c;
     st = read_ctl(g, &c);
-    if (st != DSG_OK) return bail(st);
+    if (st != DSG_OK) return st;
     long long items = 0;
     if ((e = hipMemcpy(&items, g->d.tile_off, sizeof(long long), hipMemcpyDeviceToHost)) != hipSuccess)
-        return bail(hip_fail(e, "hipMemcpy(items)"));
+        return hip_fail(e, "hipMemcpy(items)");
     g->d.n_items = (int)items;
     g->d.max_deg = c.max_deg;
     if (flags & DSG_VALIDATE) {
-        if ((e = dsg::launch_check_rows(g->d, s)) != hipSuccess) return bail(hip_fail(e, "check rows"));
+        if ((e = dsg::launch_check_rows(g->d, s)) != hipSuccess) return hip_fail(e, "check rows");
         st = check_errors(g, "rows");
-        if (st != DSG_OK) return bail(st);
+        if (st != DSG_OK) return st;
     }
-    if ((e = dsg::launch_reset_state(g->d, s)) != hipSuccess) return bail(hip_fail(e, "reset"));
-    if ((e = hipEventCreate(&g->ev0)) != hipSuccess) return bail(hip_fail(e, "hipEventCreate"));
-    if ((e = hipEventCreate(&g->ev1)) != hipSuccess) {
-        (void)hipEventDestroy(g->ev0);
-        return bail(hip_fail(e, "hipEventCreate"));
+    if ((e = dsg::launch_reset_state(g->d, s)) != hipSuccess) return hip_fail(e, "reset");
+    if (events) {
+        if ((e = hipEventCreate(&g->ev0)) != hipSuccess) {
+            g->ev0 = nullptr;
+            return hip_fail(e, "hipEventCreate");
+        }
+        if ((e = hipEventCreate(&g->ev1)) != hipSuccess) {
+            (void)hipEventDestroy(g->ev0);
+            g->ev0 = g->ev1 = nullptr;
+            return hip_fail(e, "hipEventCreate");
+        }
     }
     if ((e = hipStreamSynchronize(s)) != hipSuccess) {
-        (void)hipEventDestroy(g->ev0);
-        (void)hipEventDestroy(g->ev1);
-        return bail(hip_fail(e, "hipStreamSynchronize"));
+        if (g->ev0) (void)hipEventDestroy(g->ev0);
+        if (g->ev1) (void)hipEventDestroy(g->ev1);
+        g->ev0 = g->ev1 = nullptr;
+        return hip_fail(e, "hipStreamSynchronize");
+    }
+    return DSG_OK;
+}
+
+// Releases the HIP objects a graph holds (not its storage or workspace).
+void graph_fini(dsg_graph* g) {
+    for (hipEvent_t ev : g->kev) (void)hipEventDestroy(ev);
+    g->kev.clear();
+    if (g->ev0) (void)hipEventDestroy(g->ev0);
+    if (g->ev1) (void)hipEventDestroy(g->ev1);
+    g->ev0 = g->ev1 = nullptr;
+    if (g->gexec) (void)hipGraphExecDestroy(g->gexec);
+    if (g->cap_stream) (void)hipStreamDestroy(g->cap_stream);
+    g->gexec = nullptr;
+    g->cap_stream = nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+dsg_status dsg_graph_create(dsg_ctx* ctx, int32_t n, int64_t nnz, const int32_t* d_offsets, const int32_t* d_adj,
+                            void* d_workspace, int64_t workspace_bytes, int32_t t_cap, int32_t flags,
+                            dsg_graph** out) {
+    if (!out) return fail(DSG_EINVAL, "NULL argument");
+    *out = nullptr;
+    dsg_graph* g = new (std::nothrow) dsg_graph();
+    if (!g) return fail(DSG_ENOMEM, "host allocation failed");
+    const dsg_status st = graph_init(g, ctx, n, nnz, d_offsets, d_adj, d_workspace, workspace_bytes, t_cap, flags,
+                                     true);
+    if (st != DSG_OK) {
+        delete g;
+        return st;
     }
     *out = g;
     return DSG_OK;
@@ -385,7 +456,7 @@ dsg_status dsg_run(dsg_graph* g, int32_t T, int32_t eps_num, int32_t eps_den, ds
         }
         return hipSuccess;
     };
-    DSG_HIP(hipEventRecord(g->ev0, s), "hipEventRecord");
+    if (g->ev0) DSG_HIP(hipEventRecord(g->ev0, s), "hipEventRecord");
     bool launched = false;
     if (g->replay && !g->ktime && g->replay_state >= 0 && T > 0) {
         // everything the launches depend on besides the device state
@@ -425,8 +496,8 @@ dsg_status dsg_run(dsg_graph* g, int32_t T, int32_t eps_num, int32_t eps_den, ds
         const hipError_t e = enqueue_run(s, g->ktime);
         if (e != hipSuccess) return hip_fail(e, "enqueue iteration");
     }
-    DSG_HIP(hipEventRecord(g->ev1, s), "hipEventRecord");
-    g->timed = true;
+    if (g->ev1) DSG_HIP(hipEventRecord(g->ev1, s), "hipEventRecord");
+    g->timed = g->ev1 != nullptr;
     g->recorded += T;
     g->iters_done += T;
     g->load_bound += (long long)T * (long long)g->d.max_deg;
@@ -623,11 +694,7 @@ dsg_status dsg_get_iter_digests(dsg_graph* g, uint64_t* h_digest, int32_t* h_rou
 
 dsg_status dsg_graph_destroy(dsg_graph* g) {
     if (!g) return DSG_OK;
-    for (hipEvent_t ev : g->kev) (void)hipEventDestroy(ev);
-    (void)hipEventDestroy(g->ev0);
-    (void)hipEventDestroy(g->ev1);
-    if (g->gexec) (void)hipGraphExecDestroy(g->gexec);
-    if (g->cap_stream) (void)hipStreamDestroy(g->cap_stream);
+    graph_fini(g);
     delete g;
     return DSG_OK;
 }
@@ -722,17 +789,18 @@ dsg_status par_cut(dsg_graph* g, const ParWs& w, const int* core, const int* old
 // Leaves the graph alive in *gout (its static items serve the next cut).
 dsg_status par_coreness(dsg_ctx* ctx, const ParWs& w, int n, long long nnz, const int32_t* d_offsets,
                         const int32_t* d_adj, int tcap, int flags, bool timed, int eps_num, int eps_den, int* core_out,
-                        dsg_graph** gout, int* nrounds_out, int* kmax_out, float* ms_out) {
-    dsg_graph* g = nullptr;
-    dsg_status st = dsg_graph_create(ctx, n, nnz, d_offsets, d_adj, w.gws, w.gws_bytes, tcap, flags, &g);
+                        dsg_graph* gb, dsg_graph** gout, int* nrounds_out, int* kmax_out, float* ms_out) {
+    *gb = dsg_graph();
+    dsg_status st = graph_init(gb, ctx, n, nnz, d_offsets, d_adj, w.gws, w.gws_bytes, tcap, flags, false);
     if (st != DSG_OK) return st;
+    dsg_graph* g = gb;
     hipStream_t s = ctx->stream;
     if (timed) dsg_set_kernel_timing(g, 1);
     g->d.rmin = w.rv;  // the round loop records each round's minimum (at most n rounds)
     st = dsg_run(g, 1, eps_num, eps_den, DSG_PEEL_MONO);
     g->d.rmin = nullptr;
     if (st != DSG_OK) {
-        dsg_graph_destroy(g);
+        graph_fini(g);
         return st;
     }
     int nrounds = 0, kmax = 0;
@@ -749,7 +817,7 @@ dsg_status par_coreness(dsg_ctx* ctx, const ParWs& w, int n, long long nnz, cons
         (e = dsg::launch_core_numbers(g->d, nrounds, w.rv, core_out, w.kmax, s)) != hipSuccess ||
         (e = hipStreamSynchronize(s)) != hipSuccess ||
         (e = hipMemcpy(&kmax, w.kmax, sizeof(int), hipMemcpyDeviceToHost)) != hipSuccess) {
-        dsg_graph_destroy(g);
+        graph_fini(g);
         return hip_fail(e, "core numbers");
     }
     *gout = g;
@@ -774,13 +842,14 @@ dsg_status dsg_coreness(dsg_ctx* ctx, int32_t n, int64_t nnz, const int32_t* d_o
     DSG_HIP(hipSetDevice(ctx->device), "hipSetDevice");
     ParWs w;
     carve_par(n, nnz, 1, static_cast<char*>(d_workspace), &w);
+    dsg_graph gb{};
     dsg_graph* g = nullptr;
     int nr = 0, km = 0;
     float ms = 0.f;
     dsg_status st = par_coreness(ctx, w, n, nnz, d_offsets, d_adj, 1, flags, round_loop_ms != nullptr, 0, 1, w.core,
-                                 &g, &nr, &km, &ms);
+                                 &gb, &g, &nr, &km, &ms);
     if (st != DSG_OK) return st;
-    dsg_graph_destroy(g);
+    graph_fini(g);
     *kmax = km;
     if (rounds) *rounds = nr;
     if (round_loop_ms) *round_loop_ms = ms;
@@ -826,12 +895,24 @@ dsg_status par_run_impl(dsg_ctx* ctx, int32_t n, int64_t nnz, const int32_t* d_o
     ParWs w;
     carve_par(n, nnz, tcap, static_cast<char*>(d_workspace), &w);
     hipStream_t s = ctx->stream;
+    const int created_flags = flags & ~DSG_VALIDATE;  // a cut of a valid graph is valid
+    // one graph is bound at a time; it lives in this frame (no handle allocation)
+    dsg_graph gb{};
     dsg_graph* g = nullptr;
-    auto bail = [&](dsg_status st) {
-        if (g) dsg_graph_destroy(g);
+    auto drop = [&]() {
+        if (g) graph_fini(g);
+        g = nullptr;
+    };
+    auto make = [&](int nn, long long mm, const int32_t* o, const int32_t* a) -> dsg_status {
+        gb = dsg_graph();
+        const dsg_status st = graph_init(&gb, ctx, nn, mm, o, a, w.gws, w.gws_bytes, tcap, created_flags, false);
+        if (st == DSG_OK) g = &gb;
         return st;
     };
-    const int created_flags = flags & ~DSG_VALIDATE;  // a cut of a valid graph is valid
+    auto bail = [&](dsg_status st) {
+        drop();
+        return st;
+    };
     hipError_t e;
     int cur = 0, nc = 0, kmax = 0, level = 0, nrounds = 0;
     long long mc = 0;
@@ -841,8 +922,8 @@ dsg_status par_run_impl(dsg_ctx* ctx, int32_t n, int64_t nnz, const int32_t* d_o
     if (prune == 0) {
         // Coreness of the input graph (Coreness by buckets on the PEEL round loop),
         // then the ceil(k_max / 2)-core
-        st = par_coreness(ctx, w, n, nnz, d_offsets, d_adj, tcap, flags, false, 0, 1, w.core, &g, &nrounds, &kmax,
-                          nullptr);
+        st = par_coreness(ctx, w, n, nnz, d_offsets, d_adj, tcap, flags, false, 0, 1, w.core, &gb, &g, &nrounds,
+                          &kmax, nullptr);
         if (st != DSG_OK) return st;
         level = (kmax + 1) / 2;
         if ((e = dsg::launch_iota(w.iota, n, s)) != hipSuccess) return bail(hip_fail(e, "iota"));
@@ -850,8 +931,8 @@ dsg_status par_run_impl(dsg_ctx* ctx, int32_t n, int64_t nnz, const int32_t* d_o
     } else {
         // the c-approximate decomposition (the round loop with eps = c - 1),
         // then the ceil(khat_max / 2c)-approximate core (Corollary apxkmax)
-        st = par_coreness(ctx, w, n, nnz, d_offsets, d_adj, tcap, flags, false, c_num - c_den, c_den, w.apx, &g,
-                          &nrounds, &apx.apx_kmax, nullptr);
+        st = par_coreness(ctx, w, n, nnz, d_offsets, d_adj, tcap, flags, false, c_num - c_den, c_den, w.apx, &gb,
+                          &g, &nrounds, &apx.apx_kmax, nullptr);
         if (st != DSG_OK) return st;
         apx.apx_level = (int)(((long long)apx.apx_kmax * c_den + 2LL * c_num - 1) / (2LL * c_num));
         if ((e = dsg::launch_iota(w.iota, n, s)) != hipSuccess) return bail(hip_fail(e, "iota"));
@@ -864,10 +945,9 @@ dsg_status par_run_impl(dsg_ctx* ctx, int32_t n, int64_t nnz, const int32_t* d_o
         if (prune == 2) {
             // exact core numbers of the cut graph: at every level >= the
             // approximate one its cores are the input's
-            dsg_graph_destroy(g);
-            g = nullptr;
-            st = par_coreness(ctx, w, nc, mc, w.off[cur], w.adj[cur], tcap, created_flags, false, 0, 1, w.core1, &g,
-                              &nrounds, &kmax, nullptr);
+            drop();
+            st = par_coreness(ctx, w, nc, mc, w.off[cur], w.adj[cur], tcap, created_flags, false, 0, 1, w.core1,
+                              &gb, &g, &nrounds, &kmax, nullptr);
             if (st != DSG_OK) return st;
             if ((e = dsg::launch_scatter(w.core1, w.oldid[cur], nc, w.core, n, s)) != hipSuccess)
                 return bail(hip_fail(e, "core numbers to input ids"));
@@ -887,12 +967,9 @@ dsg_status par_run_impl(dsg_ctx* ctx, int32_t n, int64_t nnz, const int32_t* d_o
     }
     if (((long long)T + 1) * (long long)g->d.max_deg >= (1LL << 31))
         return bail(fail(DSG_EOVERFLOW, "loads could exceed 31 bits: (T + 1) * max_degree >= 2^31"));
-    dsg_graph_destroy(g);
-    g = nullptr;
+    drop();
     // S <- G: the first refined graph, loads zero
-    if ((st = dsg_graph_create(ctx, nc, mc, w.off[cur], w.adj[cur], w.gws, w.gws_bytes, tcap, created_flags, &g)) !=
-        DSG_OK)
-        return st;
+    if ((st = make(nc, mc, w.off[cur], w.adj[cur])) != DSG_OK) return st;
     long long be = mc / 2, bv = nc;
     int best_iter = 0, prunes = 0;
     if ((e = dsg::launch_vertex_mask(nc, w.oldid[cur], w.mask, n, s)) != hipSuccess) return bail(hip_fail(e, "mask"));
@@ -926,14 +1003,11 @@ dsg_status par_run_impl(dsg_ctx* ctx, int32_t n, int64_t nnz, const int32_t* d_o
                 long long mm = 0;
                 if ((st = par_cut(g, w, cut_core, w.oldid[cur], level, 1 - cur, &nn, &mm)) != DSG_OK) return bail(st);
                 const long long lb = g->load_bound;
-                dsg_graph_destroy(g);
-                g = nullptr;
+                drop();
                 cur = 1 - cur;
                 nc = nn;
                 mc = mm;
-                if ((st = dsg_graph_create(ctx, nc, mc, w.off[cur], w.adj[cur], w.gws, w.gws_bytes, tcap,
-                                           created_flags, &g)) != DSG_OK)
-                    return st;
+                if ((st = make(nc, mc, w.off[cur], w.adj[cur])) != DSG_OK) return st;
                 // the surviving vertices keep their loads (graph creation zeroed them), and so does the bound
                 // on them that sizes the SORT keys and the overflow guard
                 DSG_HIP(hipMemcpyAsync(g->d.load, w.load, sizeof(int) * (size_t)nc, hipMemcpyDeviceToDevice, s),
@@ -956,7 +1030,7 @@ dsg_status par_run_impl(dsg_ctx* ctx, int32_t n, int64_t nnz, const int32_t* d_o
     if (h_core) DSG_HIP(hipMemcpy(h_core, cut_core, sizeof(int) * (size_t)n, hipMemcpyDeviceToHost), "hipMemcpy(core)");
     if (h_apx_core && prune != 0)
         DSG_HIP(hipMemcpy(h_apx_core, w.apx, sizeof(int) * (size_t)n, hipMemcpyDeviceToHost), "hipMemcpy(apx core)");
-    dsg_graph_destroy(g);
+    drop();
     return DSG_OK;
 }
 
@@ -983,6 +1057,35 @@ dsg_status dsg_par_run_apx(dsg_ctx* ctx, int32_t n, int64_t nnz, const int32_t* 
     return par_run_impl(ctx, n, nnz, d_offsets, d_adj, d_workspace, workspace_bytes, T, eps_num, eps_den, variant,
                         flags, then_exact ? 2 : 1, c_num, c_den, result, apx, h_iter_edges, h_iter_verts,
                         h_iter_index, h_iter_n, h_iter_nnz, h_iter_level, h_best_mask, h_core, h_apx_core);
+}
+
+dsg_status dsg_par_run_noalloc(dsg_ctx* ctx, int32_t n, int64_t nnz, const int32_t* d_offsets, const int32_t* d_adj,
+                               int32_t T, int32_t eps_num, int32_t eps_den, dsg_variant variant, int32_t flags,
+                               dsg_par_result* result, int64_t* h_iter_edges, int64_t* h_iter_verts,
+                               int32_t* h_iter_index, int32_t* h_iter_n, int64_t* h_iter_nnz, int32_t* h_iter_level,
+                               uint8_t* h_best_mask, int32_t* h_core) {
+    if (!ctx) return fail(DSG_EINVAL, "NULL argument");
+    if (n < 1 || n >= dsg::PEEL_MAX_N) return fail(DSG_EINVAL, "n must be in [1, 2^26)");
+    if (nnz < 0 || nnz > dsg::MAX_NNZ) return fail(DSG_EINVAL, "nnz must be in [0, 2^31 - 2^16]");
+    if (T < 0) return fail(DSG_EINVAL, "T must be >= 0");
+    const long long need = carve_par(n, nnz, T > 0 ? T : 1, nullptr, nullptr);
+    if (need > DSG_NOALLOC_SCRATCH_BYTES) {
+        char buf[192];
+        snprintf(buf, sizeof buf, "graph needs %lld bytes of scratch; the static scratch holds %lld",
+                 need, (long long)DSG_NOALLOC_SCRATCH_BYTES);
+        return fail(DSG_ENOMEM, buf);
+    }
+    void* p = nullptr;
+    hipError_t e = hipErrorInvalidDevice;
+    if (ctx->device >= 0 && ctx->device < SCRATCH_MAX_DEVICES) {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        p = g_scratch_ptr[ctx->device];
+        e = g_scratch_done[ctx->device] ? g_scratch_err[ctx->device] : hipErrorNotInitialized;
+    }
+    if (!p) return hip_fail(e, "static scratch address (hipGetSymbolAddress)");
+    return par_run_impl(ctx, n, nnz, d_offsets, d_adj, p, DSG_NOALLOC_SCRATCH_BYTES, T, eps_num, eps_den, variant,
+                        flags, 0, 1, 1, result, nullptr, h_iter_edges, h_iter_verts, h_iter_index, h_iter_n,
+                        h_iter_nnz, h_iter_level, h_best_mask, h_core, nullptr);
 }
 
 

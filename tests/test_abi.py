@@ -104,3 +104,10 @@ def test_par_workspace_bytes_host_logic(lib):
         dsg.par_workspace_bytes(1 << 26, 10, 1)
     with pytest.raises(dsg.DsgError):
         dsg.par_workspace_bytes(10, 10, -1)
+
+
+def test_noalloc_scratch_size_matches_the_header():
+    import paper_2311_04333_amd as dsg
+
+    m = re.search(r"#define DSG_NOALLOC_SCRATCH_BYTES \((\d+)LL << (\d+)\)", open(HEADER).read())
+    assert m and int(m.group(1)) << int(m.group(2)) == dsg.NOALLOC_SCRATCH_BYTES
