@@ -362,12 +362,22 @@ def cpu_baseline_graph(args, c3, offsets, adj, n, m, T, eps):
         o, a = offsets, adj
         sample = f"first {iters} of the {T} iterations of the same run (same graph)"
     t1 = time.perf_counter()
-    oracle.run(o, a, iters, args.variant, eps)
+    ref = oracle.run(o, a, iters, args.variant, eps)
     cpu_s = time.perf_counter() - t1
     log(f"cpu oracle: {iters} iterations in {cpu_s:.1f}s")
     info = host_info()
+    # the multi-threaded timing build of the same iterations on every usable host core, checked equal to the oracle
+    cores = info["nproc"] or 1
+    t1 = time.perf_counter()
+    par = oracle.run_omp(o, a, iters, args.variant, eps, threads=cores)
+    par_s = time.perf_counter() - t1
+    same = par.hist == ref.hist and par.digests == ref.digests and list(par.best) == list(ref.best)
+    log(f"cpu timing build: {iters} iterations in {par_s:.1f}s on {cores} threads (equal to the oracle: {same})")
     return {"value": 2.0 * (len(a) // 2) * iters / cpu_s, "unit": "edge-visits/s", "cores": 1, "kind": "oracle",
-            "sample": f"{sample}, single thread, {cpu_s:.1f} s", "host": info}
+            "sample": f"{sample}, single thread, {cpu_s:.1f} s", "host": info,
+            "all_cores": {"value": 2.0 * (len(a) // 2) * iters / par_s, "unit": "edge-visits/s", "cores": cores,
+                          "kind": "OpenMP timing build of the oracle (oracle/timing_omp.c), same sample",
+                          "seconds": par_s, "equals_oracle": bool(same)}}
 
 
 def bench_batch(args):
@@ -650,7 +660,7 @@ def bench_par(args):
         f"({core_rounds} rounds)")
     check = None
     cpu = None
-    if args.cpu_iters > 0:
+    if args.cpu_iters is None or args.cpu_iters > 0:
         # the CPU-baseline leg: the oracle's run of the whole framework, whose
         # result also serves as the check (no oracle run without this leg)
         from oracle import prune

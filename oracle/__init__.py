@@ -27,6 +27,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "greedypp_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "_oracle.so")
 _lib = None
+_OMP_SRC = os.path.join(_HERE, "timing_omp.c")
+_OMP_PATH = os.path.join(_HERE, "_timing_omp.so")
+_omp = None
 
 VARIANTS = {"seq": 0, "peel": 1, "sort": 2, "peel_mono": 3}
 
@@ -39,6 +42,15 @@ def build(force: bool = True, extra_flags=(), out: str | None = None) -> str:
         subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-std=gnu11", *extra_flags, "-o", tmp, _SRC])
         os.replace(tmp, path)
     return path
+
+
+def build_omp(force: bool = True) -> str:
+    """Compile the multi-threaded timing build (timing_omp.c, gcc -O2 -fopenmp)."""
+    if force or not os.path.exists(_OMP_PATH):
+        tmp = _OMP_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=gnu11", "-o", tmp, _OMP_SRC])
+        os.replace(tmp, _OMP_PATH)
+    return _OMP_PATH
 
 
 def _bind(lib):
@@ -160,6 +172,47 @@ def run(offsets, adj, T: int, variant: str, eps=(0, 1), state: State | None = No
                      _ptr(lp), _ptr(lr))
     if rc != 0:
         raise RuntimeError("oracle run failed")
+    st.iters += T
+    st.hist += [(int(hist[2 * t]), int(hist[2 * t + 1])) for t in range(T)]
+    st.hist_idx += [int(x) for x in hidx[:T]]
+    st.digests += [int(x) for x in dig[:T]]
+    st.rounds += [int(x) for x in rnd[:T]]
+    st.width += [int(x) for x in wid[:T]]
+    if T > 0:
+        st.last_pos, st.last_round = lp, lr
+    return st
+
+
+def run_omp(offsets, adj, T: int, variant: str, eps=(0, 1), state: State | None = None, threads: int = 0) -> State:
+    """The multi-threaded timing build (timing_omp.c): the same outputs as ``run`` for "peel", "peel_mono" and
+    "sort", computed on ``threads`` OpenMP threads (0 = OpenMP's default).  Used to time the CPU baseline on all
+    host cores; the parity reference stays ``run``."""
+    global _omp
+    if _omp is None:
+        if not os.path.exists(_OMP_PATH):
+            build_omp(force=False)
+        _omp = ctypes.CDLL(_OMP_PATH)
+        P, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        _omp.orc_run_omp.restype = ctypes.c_int
+        _omp.orc_run_omp.argtypes = [i32, P, P, i32, i32, i64, i64, P, P, P, i32, P, P, P, P, P, P, P, i32]
+    if variant not in ("peel", "peel_mono", "sort"):
+        raise ValueError("the timing build offers peel, peel_mono and sort")
+    off, a = _csr(offsets, adj)
+    n = len(off) - 1
+    st = state or State.fresh(off)
+    num, den = parse_eps(eps)
+    hist = np.zeros(2 * max(T, 1), dtype=np.int64)
+    hidx = np.zeros(max(T, 1), dtype=np.int64)
+    dig = np.zeros(max(T, 1), dtype=np.uint64)
+    rnd = np.zeros(max(T, 1), dtype=np.int32)
+    wid = np.zeros(max(T, 1), dtype=np.int64)
+    lp = np.zeros(n, dtype=np.int32) if st.last_pos is None else st.last_pos
+    lr = np.zeros(n, dtype=np.int32) if st.last_round is None else st.last_round
+    rc = _omp.orc_run_omp(n, _ptr(off), _ptr(a), T, VARIANTS[variant], num, den, _ptr(st.loads), _ptr(st.best),
+                          _ptr(st.best_pos), st.iters, _ptr(hist), _ptr(hidx), _ptr(dig), _ptr(rnd), _ptr(wid),
+                          _ptr(lp), _ptr(lr), threads)
+    if rc != 0:
+        raise RuntimeError("timing build run failed")
     st.iters += T
     st.hist += [(int(hist[2 * t]), int(hist[2 * t + 1])) for t in range(T)]
     st.hist_idx += [int(x) for x in hidx[:T]]
