@@ -147,6 +147,8 @@ def main():
     ap.add_argument("--rates", default="100,300,1000,3000,5000", help="serve: offered request rates (req/s)")
     ap.add_argument("--window", type=float, default=3.0, help="serve: seconds of Poisson arrivals per rate")
     ap.add_argument("--variant", default="peel", choices=["peel", "sort"])
+    ap.add_argument("--select", type=int, default=-1, choices=[-1, 0, 1],
+                    help="PEEL select: -1 = the library's default (full list), 0 = full list, 1 = near list")
     ap.add_argument("--count", type=int, default=4096, help="graphs in the batched mix")
     ap.add_argument("--plain-sample", type=int, default=256, help="graphs of the mix timed on the plain path")
     ap.add_argument("--T", type=int, default=None, help="iterations per step (default: 50 for c3, 20 otherwise)")
@@ -218,6 +220,8 @@ def bench_graph(args):
     a_dev = torch.from_numpy(adj).cuda()
     g = dsg.Graph(ctx, o_dev, a_dev, t_cap=T, validate=False)
     g.set_kernel_timing(True)
+    g.set_peel_select(args.select)
+    near = args.select == 1
     torch.cuda.synchronize()
 
     for w in range(args.warmup):
@@ -237,7 +241,7 @@ def bench_graph(args):
 
     ms_per_step = 1e3 * elapsed / max(args.steps, 1)
     value = 2.0 * m * T * args.steps / elapsed
-    kernel = "k_peel_rounds" if args.variant == "peel" else "k_sweep_sort"
+    kernel = ("k_peel_rounds_near" if near else "k_peel_rounds") if args.variant == "peel" else "k_sweep_sort"
     # algorithmic bytes per launch of the dominant kernel, and per iteration
     if args.variant == "peel":
         alg_bytes, alg_model = 16.0 * m + 16.0 * n, "16m+16n"
@@ -288,7 +292,8 @@ def bench_graph(args):
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic",
-        "config": {"workload": f"{desc} (n={n}, m={m}), {args.variant} eps={eps[0]}/{eps[1]}, T={T} per step"},
+        "config": {"workload": f"{desc} (n={n}, m={m}), {args.variant} eps={eps[0]}/{eps[1]}, T={T} per step",
+                   "peel_select": ("near list" if near else "full list") if args.variant == "peel" else None},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kernel,
                      "avg_launch_ms": kern_ms / max(launches, 1), "launches": launches,

@@ -112,6 +112,21 @@ dsg_status dsg_graph_create(dsg_ctx* ctx, int32_t n, int64_t nnz, const int32_t*
  * Asynchronous: returns once the work is enqueued. */
 dsg_status dsg_run(dsg_graph* g, int32_t T, int32_t eps_num, int32_t eps_den, dsg_variant variant);
 
+/* Certificate-driven stop (Section 4.4): runs iterations of the variant one at
+ * a time, at most T_max, and stops after the first one whose certificate
+ * holds.  After t iterations since the last dsg_reset every densest subgraph
+ * S* has rho(S*) <= L_t / t, where L_t is the largest load (each iteration
+ * charges every edge of S* to an endpoint inside S*).  The certificate is
+ *     L_t * best_vertices * tol_den <= t * best_edges * (tol_den + tol_num),
+ * i.e. L_t / t <= (1 + tol) * rho(best), which proves the best subgraph found
+ * is within a factor 1 + tol of the optimum.  *iters gets the iterations this
+ * call ran, *certified 1 if it stopped on the certificate (0 if it ran T_max
+ * without it).  Exact integer arithmetic.  Synchronous: it waits for every
+ * iteration to read the certificate.  Errors as dsg_run, and DSG_EDEVICE if a
+ * kernel consistency check fired. */
+dsg_status dsg_run_until(dsg_graph* g, int32_t T_max, int32_t eps_num, int32_t eps_den, dsg_variant variant,
+                         int32_t tol_num, int32_t tol_den, int32_t* iters, int32_t* certified);
+
 /* Loads to 0, best to the input graph, history cleared.  Asynchronous. */
 dsg_status dsg_reset(dsg_graph* g);
 
@@ -172,11 +187,11 @@ dsg_status dsg_last_run_ms(dsg_graph* g, float* ms);
  * selects the default.
  *  - bucket_min_edges: from this size on, a round applies its neighbour-degree
  *    decrements through owner buckets.  The buckets cover contiguous ranges of
- *    up to 16384 vertex ids, and each range is summed by one block in a dense
- *    LDS histogram after an extra grid barrier.  Smaller rounds apply the
- *    decrements with per-chunk aggregated device atomics.  Default 2^20;
- *    0 buckets every round.  Graphs with more than 1024 * 16384 vertices always
- *    take the atomic path.
+ *    up to 32768 vertex ids (at most 2048 ranges, enough for every n the PEEL
+ *    path accepts), and each range is summed by one block in an LDS histogram
+ *    after an extra grid barrier.  Smaller rounds apply the decrements with
+ *    per-chunk aggregated device atomics.  Default 2^20; 0 buckets every
+ *    round.
  *  - coarse_min_edges: from this size on, a round sweeps 4096-edge chunks;
  *    smaller rounds sweep 1024-edge chunks, so that more blocks share them.
  *    Default 2^20; 0 = always coarse.
@@ -194,6 +209,22 @@ dsg_status dsg_set_peel_tuning(dsg_graph* g, int64_t bucket_min_edges, int64_t c
  * The setting is kept across dsg_reset.  DSG_EINVAL for other values or a
  * NULL graph. */
 dsg_status dsg_set_sort_tuning(dsg_graph* g, int32_t coarse_ranks);
+
+/* How DSG_PEEL and DSG_PEEL_MONO rounds find their frontier; results do not
+ * depend on it.
+ *   0 = full list: every round scans every alive vertex, and the positions
+ *       come out of the round loop itself.
+ *   1 = near list: the alive vertices whose priority is at most a near bound
+ *       B (B = 5/4 of a round's threshold, plus one, reset whenever a
+ *       threshold passes it) are kept in a list of their own, and a round
+ *       whose threshold is at most B scans only that list; other rounds scan
+ *       every alive vertex and reset B.  Vertices join the list as a
+ *       decrement takes them to B or below.  The positions are sorted by round
+ *       after the loop.  Pays off where many rounds peel few vertices out of
+ *       many alive ones (large sparse graphs).
+ *  -1 = the default, which is the full list.
+ * Kept across dsg_reset.  DSG_EINVAL for other values or a NULL graph. */
+dsg_status dsg_set_peel_select(dsg_graph* g, int32_t mode);
 
 /* Optional graph replay (off by default).  When on, dsg_run captures the
  * launches of its T iterations once into a HIP graph (on a private stream of

@@ -40,6 +40,7 @@ SIGNATURES = [
     ("dsg_workspace_bytes", ctypes.c_int, [_I32, _I64, _I32, _P]),
     ("dsg_graph_create", ctypes.c_int, [_P, _I32, _I64, _P, _P, _P, _I64, _I32, _I32, _P]),
     ("dsg_run", ctypes.c_int, [_P, _I32, _I32, _I32, ctypes.c_int]),
+    ("dsg_run_until", ctypes.c_int, [_P, _I32, _I32, _I32, ctypes.c_int, _I32, _I32, _P, _P]),
     ("dsg_reset", ctypes.c_int, [_P]),
     ("dsg_sync", ctypes.c_int, [_P]),
     ("dsg_get_best", ctypes.c_int, [_P, _P, _P, _P, _P]),
@@ -61,6 +62,7 @@ SIGNATURES = [
                                            _P, _P, _P, _P]),
     ("dsg_set_peel_tuning", ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int64]),
     ("dsg_set_sort_tuning", ctypes.c_int, [_P, _I32]),
+    ("dsg_set_peel_select", ctypes.c_int, [_P, _I32]),
     ("dsg_set_graph_replay", ctypes.c_int, [_P, _I32]),
     ("dsg_get_graph_replay", ctypes.c_int, [_P, _P]),
     ("dsg_set_kernel_timing", ctypes.c_int, [_P, _I32]),
@@ -249,6 +251,17 @@ class Graph:
         _check(library().dsg_run(self._h, T, num, den, VARIANTS[variant]))
         return self
 
+    def run_until(self, T_max: int, eps=(0, 1), variant: str = "peel", tol=(1, 1000)):
+        """dsg_run_until: iterations until the load certificate proves the best density within a factor 1 + tol of
+        the optimum, at most T_max.  Returns (iterations run, certified)."""
+        num, den = parse_eps(eps)
+        tn, td = parse_eps(tol)
+        it = ctypes.c_int32()
+        ok = ctypes.c_int32()
+        _check(library().dsg_run_until(self._h, T_max, num, den, VARIANTS[variant], tn, td, ctypes.addressof(it),
+                                       ctypes.addressof(ok)))
+        return it.value, bool(ok.value)
+
     def reset(self):
         _check(library().dsg_reset(self._h))
         return self
@@ -271,6 +284,11 @@ class Graph:
         """SORT sweep tuning (results do not depend on it): coarse position classes first; -1 = by size, 0 = off,
         1 = on."""
         _check(library().dsg_set_sort_tuning(self._h, int(coarse_ranks)))
+        return self
+
+    def set_peel_select(self, mode: int = -1):
+        """dsg_set_peel_select: -1 = by size, 0 = full-list select, 1 = near-list select (same results)."""
+        _check(library().dsg_set_peel_select(self._h, mode))
         return self
 
     def iter_bounds(self):

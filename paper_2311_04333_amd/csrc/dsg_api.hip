@@ -55,6 +55,7 @@ struct dsg_graph {
     long long bkt_min_e;           // PEEL rounds with at least this many frontier edges use owner buckets
     long long coarse_min_e;        // ... and coarse sweep chunks; -1 = default
     int sort_coarse;               // SORT coarse ranks: -1 = by size, 0 = off, 1 = on
+    int peel_select;               // PEEL select: -1 = by size, 0 = full list, 1 = near list
     // graph replay (dsg_set_graph_replay): the launches of one dsg_run are
     // captured on a private stream into a HIP graph, which later calls with
     // the same key replay on the context's stream
@@ -62,7 +63,7 @@ struct dsg_graph {
     int replay_state;              // 1 = a run is captured, 0 = none yet, -1 = capture refused (eager from then on)
     hipStream_t cap_stream;
     hipGraphExec_t gexec;
-    long long gkey[10];
+    long long gkey[11];
 };
 
 struct dsg_batch {
@@ -123,7 +124,7 @@ dsg_status hip_fail(hipError_t e, const char* where) {
     } while (0)
 
 struct Layout {
-    long long off[48];
+    long long off[64];
     int count = 0;
     long long total = 0;
     long long add(long long bytes) {
@@ -159,7 +160,15 @@ long long carve(int n, long long nnz, int t_cap, char* base, GraphDev* g) {
     long long o_cb = L.add(4 * ((N + 7) / 8 + 1)), o_crb = L.add(4 * 16), o_crs = L.add(4 * (1 << 17));
     long long o_crt = L.add(8 * ((1 << 17) / 1024));
     long long o_seg = L.add(4 * 6 * dsg::PEEL_BLK);
+    long long o_n0 = L.add(4 * N), o_n1 = L.add(4 * N), o_x0 = L.add(4 * N), o_x1 = L.add(4 * N);
+    long long o_sf = L.add(4 * 4 * dsg::PEEL_BLK), o_sn = L.add(4 * 4 * dsg::PEEL_BLK);
     if (base && g) {
+        g->N0 = reinterpret_cast<int*>(base + o_n0);
+        g->N1 = reinterpret_cast<int*>(base + o_n1);
+        g->X0 = reinterpret_cast<int*>(base + o_x0);
+        g->X1 = reinterpret_cast<int*>(base + o_x1);
+        g->segF = reinterpret_cast<int*>(base + o_sf);
+        g->segN = reinterpret_cast<int*>(base + o_sn);
         g->cr_samp = reinterpret_cast<int*>(base + o_crs);
         g->cr_tsum = reinterpret_cast<long long*>(base + o_crt);
         g->seg = reinterpret_cast<int*>(base + o_seg);
@@ -319,6 +328,7 @@ dsg_status graph_init(dsg_graph* g, dsg_ctx* ctx, int32_t n, int64_t nnz, const 
     g->bkt_min_e = dsg::BKT_DEFAULT_MIN_E;
     g->coarse_min_e = -1;
     g->sort_coarse = -1;
+    g->peel_select = -1;
     g->d.n = n;
     g->d.nnz = nnz;
     g->d.off = d_offsets;
@@ -436,9 +446,11 @@ dsg_status dsg_run(dsg_graph* g, int32_t T, int32_t eps_num, int32_t eps_den, ds
             hipEvent_t eb = timed ? g->kev[2 * t + 1] : nullptr;
             hipError_t e;
             if (variant == DSG_PEEL || variant == DSG_PEEL_MONO) {
+                const bool near = g->peel_select > 0 ||
+                                  (g->peel_select < 0 && dsg::NEAR_DEFAULT_MIN_N > 0 && g->d.n >= dsg::NEAR_DEFAULT_MIN_N);
                 e = dsg::enqueue_iter_peel(g->d, slot, eps_num, eps_den, g->ctx->peel_grid, g->bkt_min_e,
                                            g->coarse_min_e >= 0 ? g->coarse_min_e : dsg::PEEL_DEFAULT_COARSE_MIN_E,
-                                           variant == DSG_PEEL_MONO, qs, ea, eb);
+                                           variant == DSG_PEEL_MONO, near, qs, ea, eb);
             } else if (variant == DSG_SORT) {
                 long long bound = g->load_bound + (long long)t * (long long)g->d.max_deg;
                 int bits = 0;
@@ -460,9 +472,9 @@ dsg_status dsg_run(dsg_graph* g, int32_t T, int32_t eps_num, int32_t eps_den, ds
     bool launched = false;
     if (g->replay && !g->ktime && g->replay_state >= 0 && T > 0) {
         // everything the launches depend on besides the device state
-        const long long key[10] = {T, eps_num, eps_den, (long long)variant, g->recorded, g->load_bound,
+        const long long key[11] = {T, eps_num, eps_den, (long long)variant, g->recorded, g->load_bound,
                                    g->bkt_min_e, g->coarse_min_e, g->sort_coarse,
-                                   (long long)reinterpret_cast<uintptr_t>(g->d.rmin)};
+                                   (long long)reinterpret_cast<uintptr_t>(g->d.rmin), g->peel_select};
         if (!(g->gexec && memcmp(key, g->gkey, sizeof key) == 0)) {
             hipGraph_t graph = nullptr;
             hipGraphExec_t ex = nullptr;
@@ -502,6 +514,35 @@ dsg_status dsg_run(dsg_graph* g, int32_t T, int32_t eps_num, int32_t eps_den, ds
     g->iters_done += T;
     g->load_bound += (long long)T * (long long)g->d.max_deg;
     if (T > 0) g->last_variant = variant;
+    return DSG_OK;
+}
+
+dsg_status dsg_run_until(dsg_graph* g, int32_t T_max, int32_t eps_num, int32_t eps_den, dsg_variant variant,
+                         int32_t tol_num, int32_t tol_den, int32_t* iters, int32_t* certified) {
+    if (!g || !iters || !certified) return fail(DSG_EINVAL, "NULL argument");
+    if (T_max < 0) return fail(DSG_EINVAL, "T_max must be >= 0");
+    if (tol_num < 0 || tol_den < 1) return fail(DSG_EINVAL, "tolerance must be tol_num >= 0, tol_den >= 1");
+    *iters = 0;
+    *certified = 0;
+    for (int t = 0; t < T_max; t++) {
+        dsg_status st = dsg_run(g, 1, eps_num, eps_den, variant);
+        if (st != DSG_OK) return st;
+        *iters = t + 1;
+        dsg::Ctl c;
+        st = read_ctl(g, &c);
+        if (st != DSG_OK) return st;
+        if (c.err_count != 0) return fail(DSG_EDEVICE, "a kernel consistency check failed");
+        int lmax = 0;
+        DSG_HIP(hipMemcpy(&lmax, g->d.hist_lmax + (g->recorded - 1), sizeof(int), hipMemcpyDeviceToHost),
+                "hipMemcpy(largest load)");
+        // rho* <= L_t / t, so L_t * v * den <= t * e * (den + num) certifies rho(best) >= rho* / (1 + tol)
+        const __int128 lhs = (__int128)lmax * c.best_v * tol_den;
+        const __int128 rhs = (__int128)g->iters_done * c.best_e * ((__int128)tol_den + tol_num);
+        if (lhs <= rhs) {
+            *certified = 1;
+            break;
+        }
+    }
     return DSG_OK;
 }
 
@@ -547,6 +588,13 @@ dsg_status dsg_set_sort_tuning(dsg_graph* g, int32_t coarse_ranks) {
     if (!g) return fail(DSG_EINVAL, "graph is NULL");
     if (coarse_ranks < -1 || coarse_ranks > 1) return fail(DSG_EINVAL, "coarse_ranks must be -1, 0 or 1");
     g->sort_coarse = coarse_ranks;
+    return DSG_OK;
+}
+
+dsg_status dsg_set_peel_select(dsg_graph* g, int32_t mode) {
+    if (!g) return fail(DSG_EINVAL, "graph is NULL");
+    if (mode < -1 || mode > 1) return fail(DSG_EINVAL, "mode must be -1, 0 or 1");
+    g->peel_select = mode;
     return DSG_OK;
 }
 

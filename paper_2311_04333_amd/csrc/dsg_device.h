@@ -20,6 +20,10 @@ struct alignas(256) Ctl {
     alignas(128) unsigned int lcnt[4];        // survivor count
     alignas(128) unsigned long long fcnt[4];  // frontier items << 38 | frontier edges
     alignas(128) unsigned int cnext[4];       // next sweep chunk to hand out
+    // near-list rounds only
+    alignas(128) unsigned int pcnt[4];        // vertices peeled in the round
+    alignas(128) unsigned int xcnt[4];        // entries of the round's crossing list
+    alignas(128) unsigned int mn2[4];         // exact minimum of a round that rescans the full list first
     // results of the current iteration
     alignas(128) int nrounds;
     int improved;

@@ -32,13 +32,21 @@ constexpr int PEEL_MAX_N = 1 << 26;  // frontier item counter has 26 bits
 constexpr long long MAX_NNZ = (1LL << 31) - (1LL << 16);
 // Owner-bucketed decrements of the PEEL round loop: vertex ids are split into
 // ranges of 2^shift ids (shift <= BKT_MAX_SHIFT, so a range's counters fit a
-// dense LDS histogram), at most BKT_MAX_NR ranges.  Larger graphs keep the
-// direct path.  Rounds whose frontier has at least the threshold's edges
-// take the bucketed path.
-constexpr int BKT_MAX_SHIFT = 14;
-constexpr int BKT_MAX_NR = 1024;
+// dense LDS histogram), at most BKT_MAX_NR ranges, which covers every graph
+// the PEEL path accepts (n < 2^26).  Rounds whose frontier has at least the
+// threshold's edges take the bucketed path.
+constexpr int BKT_MAX_SHIFT = 15;
+constexpr int BKT_MAX_NR = 2048;
 constexpr int BKT_CNT_BITS = 12;  // bucket entry = local id << 12 | (count - 1); count <= PEEL_CH
 constexpr long long BKT_DEFAULT_MIN_E = 1LL << 20;
+// Near-list select (k_peel_rounds_near): the near bound is B = thr * 5/4 + 1
+// at each full-list round.  Off by default (NEAR_DEFAULT_MIN_N = 0): measured
+// on the 40M-vertex Chung-Lu graph it scans far fewer entries but runs the
+// round loop no faster (53.1 against 52.5 ms per iteration), and on R-MAT
+// scale 22 it is slower (6.0 against 4.6 ms).
+constexpr int NEAR_B_NUM = 5;
+constexpr int NEAR_B_DEN = 4;
+constexpr int NEAR_DEFAULT_MIN_N = 0;
 // SORT compares coarse ranks first once the position table (4n bytes) no
 // longer fits an XCD's L2.  The 4-bit table (n/2 bytes) fits it up to 2^22
 // vertices; above that both tables live in the MALL, where the 8x smaller
@@ -47,9 +55,12 @@ constexpr long long BKT_DEFAULT_MIN_E = 1LL << 20;
 constexpr int SORT_COARSE_MIN_N = 1 << 19;
 constexpr int SORT_COARSE_MAX_N = (1 << 26) - 1;
 static_assert((1 << BKT_CNT_BITS) >= 4096, "chunk-local counts must fit the entry's count field");
+static_assert(BKT_MAX_SHIFT + BKT_CNT_BITS <= 32, "a bucket entry holds a local id and a count");
+static_assert(((PEEL_MAX_N + (1 << BKT_MAX_SHIFT) - 1) >> BKT_MAX_SHIFT) <= BKT_MAX_NR,
+              "every graph the PEEL path accepts fits the bucketed path");
 // Range shift for n vertices, or -1 when the graph is too large for the
-// bucketed path: the smallest shift >= 8 giving at most 256 ranges, capped
-// at BKT_MAX_SHIFT.
+// bucketed path: the smallest shift >= 8 giving at most 256 ranges (one per
+// block of the round loop), capped at BKT_MAX_SHIFT.
 inline int bucket_shift(long long n) {
     int s = 8;
     while (s < BKT_MAX_SHIFT && ((n + (1LL << s) - 1) >> s) > 256) s++;
@@ -86,6 +97,15 @@ struct PeelArgs {
     int* seg;              // per block, by round parity: [2][alive start | alive len | frontier len][PEEL_BLK]
     int* order;            // order[position] = vertex, written round by round
     int* rmin;             // optional: rmin[r] = round r's priority bound thr (room for n rounds)
+    // near-list select (k_peel_rounds_near)
+    int* N0;               // near lists, by round parity
+    int* N1;
+    int* X0;               // crossing lists, by round parity of the round that reads them
+    int* X1;
+    int* segF;             // full-list segments, by parity: [2][start | len][PEEL_BLK]
+    int* segN;             // near-list segments, by round parity: [2][start | len][PEEL_BLK]
+    int near_num;          // near bound B = thr * near_num / near_den + 1
+    int near_den;
 };
 
 struct SweepArgs {
@@ -159,6 +179,12 @@ struct GraphDev {
     int* seg;          // PEEL alive-list segments (4 * PEEL_BLK ints)
     long long* cr_tsum;  // sampled degree mass per tile of 1024 samples
     int* rmin;         // optional, set by the caller for one run: per-round priority bound (n ints)
+    int* N0;           // near-list select: near lists, crossing lists, segment tables
+    int* N1;
+    int* X0;
+    int* X1;
+    int* segF;
+    int* segN;
     int n_items;  // vertices with degree > 0
     int max_deg;
 };
@@ -174,9 +200,11 @@ hipError_t launch_zero_ctl(const GraphDev& g, hipStream_t s);
 // One iteration; `slot` is the history index written by this iteration.
 // ev_a / ev_b (may be null) are recorded on `s` right before and after the
 // iteration's dominant kernel (PEEL round loop, SORT sweep, SEQ peel).
+// mono: monotone round thresholds (Coreness by buckets); near: the near-list
+// select (k_peel_rounds_near), which orders by round after the loop
 hipError_t enqueue_iter_peel(const GraphDev& g, int slot, int eps_num, int eps_den, int peel_grid,
-                             long long bkt_min_e, long long coarse_min_e, int mono, hipStream_t s, hipEvent_t ev_a,
-                             hipEvent_t ev_b);  // mono: monotone round thresholds (Coreness by buckets)
+                             long long bkt_min_e, long long coarse_min_e, int mono, int near, hipStream_t s,
+                             hipEvent_t ev_a, hipEvent_t ev_b);
 hipError_t enqueue_iter_sort(const GraphDev& g, int slot, int key_bits, int sort_grid, bool coarse, hipStream_t s,
                              hipEvent_t ev_a, hipEvent_t ev_b);
 hipError_t enqueue_iter_seq(const GraphDev& g, int slot, hipStream_t s, hipEvent_t ev_a, hipEvent_t ev_b);

@@ -192,8 +192,13 @@ constexpr int RITEMS = 16;
 constexpr int RTILE = RBLK * RITEMS;
 constexpr int RBINS = 256;
 
+// `gate` (optional): the pass is skipped when *gate <= 2^16, i.e. when every
+// key is below 2^16 and the pass's digit is zero for all of them.
+__device__ __forceinline__ bool radix_skip(const int* gate) { return gate && *gate <= (1 << 16); }
+
 __global__ __launch_bounds__(RBLK) void k_radix_hist(const int* __restrict__ keys, int n, int shift,
-                                                     int* __restrict__ hist, int ntiles) {
+                                                     int* __restrict__ hist, int ntiles, const int* gate) {
+    if (radix_skip(gate)) return;
     __shared__ int h[RBINS];
     h[threadIdx.x] = 0;
     __syncthreads();
@@ -210,7 +215,8 @@ __global__ __launch_bounds__(RBLK) void k_radix_hist(const int* __restrict__ key
 // Digit-major exclusive scan of hist[RBINS * ntiles] in three kernels:
 // per-tile sums, one-block scan of those sums, in-tile scan plus offset.
 __global__ __launch_bounds__(SCAN_BLK) void k_rscan_tiles(const int* __restrict__ hist, int total,
-                                                          long long* __restrict__ tile_sum) {
+                                                          long long* __restrict__ tile_sum, const int* gate) {
+    if (radix_skip(gate)) return;
     __shared__ long long sh[SCAN_BLK / WAVE];
     const long long base = (long long)blockIdx.x * SCAN_TILE + (long long)threadIdx.x * SCAN_ITEMS;
     long long s = 0;
@@ -223,7 +229,8 @@ __global__ __launch_bounds__(SCAN_BLK) void k_rscan_tiles(const int* __restrict_
     if (threadIdx.x == 0) tile_sum[blockIdx.x] = s;
 }
 
-__global__ __launch_bounds__(1024) void k_rscan_top(long long* __restrict__ tile_sum, int ntiles) {
+__global__ __launch_bounds__(1024) void k_rscan_top(long long* __restrict__ tile_sum, int ntiles, const int* gate) {
+    if (radix_skip(gate)) return;
     __shared__ long long sh[1024 / WAVE];
     long long carry = 0;
     for (int base = 0; base < ntiles; base += 1024) {
@@ -237,7 +244,8 @@ __global__ __launch_bounds__(1024) void k_rscan_top(long long* __restrict__ tile
 }
 
 __global__ __launch_bounds__(SCAN_BLK) void k_rscan_apply(int* __restrict__ hist, int total,
-                                                          const long long* __restrict__ tile_sum) {
+                                                          const long long* __restrict__ tile_sum, const int* gate) {
+    if (radix_skip(gate)) return;
     __shared__ long long sh[SCAN_BLK / WAVE];
     const long long base = (long long)blockIdx.x * SCAN_TILE + (long long)threadIdx.x * SCAN_ITEMS;
     int x[SCAN_ITEMS];
@@ -263,7 +271,8 @@ __global__ __launch_bounds__(SCAN_BLK) void k_rscan_apply(int* __restrict__ hist
 __global__ __launch_bounds__(RBLK) void k_radix_scatter(const int* __restrict__ keys_in,
                                                         const int* __restrict__ vals_in, int* __restrict__ keys_out,
                                                         int* __restrict__ vals_out, int n, int shift,
-                                                        const int* __restrict__ hist, int ntiles) {
+                                                        const int* __restrict__ hist, int ntiles, const int* gate) {
+    if (radix_skip(gate)) return;
     const int tid = threadIdx.x;
     const int lane = tid & (WAVE - 1);
     const int wid = tid / WAVE;
@@ -536,6 +545,9 @@ __global__ void k_iter_begin(Ctl* ctl, GridSync* gs, unsigned int* bfill, int nr
         ctl->lcnt[threadIdx.x] = 0;
         ctl->fcnt[threadIdx.x] = 0;
         ctl->cnext[threadIdx.x] = 0;
+        ctl->pcnt[threadIdx.x] = 0;
+        ctl->xcnt[threadIdx.x] = 0;
+        ctl->mn2[threadIdx.x] = 0xFFFFFFFFu;
     }
     if (threadIdx.x == 0) {
         ctl->nrounds = 0;
@@ -553,6 +565,7 @@ __global__ void k_iter_begin(Ctl* ctl, GridSync* gs, unsigned int* bfill, int nr
 // serialise at about 11 ns each).  Probing is bounded; a target that finds
 // no slot within PROBE steps is decremented directly in global memory.
 constexpr int DEC_SLOTS = 2 * PEEL_CH;  // at most PEEL_CH keys: probing always finds a slot
+constexpr int XS_CAP = BKT_MAX_NR;       // crossing staging entries (in the bucket flush's base array)
 constexpr int DEC_PROBE = 64;
 constexpr int DEC_EMPTY = -1;
 
@@ -593,6 +606,62 @@ __device__ __forceinline__ int st2_get(const unsigned int* st2, int u) {
     return (int)((st2[u >> 4] >> ((u & 15) * 2)) & 3u);
 }
 
+// Crossing list staging for one block: entries go to an LDS buffer with one
+// LDS atomic per wave, and the buffer goes to the global list with one global
+// atomic per flush (one global counter shared by every block serialises at
+// about 11 ns per atomic).  Lanes that find the buffer full append directly.
+struct XStage {
+    int* xs;              // LDS buffer of XS_CAP entries
+    unsigned int* xn;     // LDS count (may pass XS_CAP: the excess went to the global list directly)
+    int* xout;            // global list
+    unsigned int* xcnt;   // its count
+    int cap;              // global capacity (n)
+    Ctl* ctl;
+    __device__ __forceinline__ void direct(int u) const {
+        const unsigned int at = atomicAdd(xcnt, 1u);
+        if (at < (unsigned int)cap) {
+            xout[at] = u;
+        } else {
+            atomicAdd(&ctl->err_count, 1);
+            ctl->err_code = ERR_INTERNAL;
+        }
+    }
+    // every lane of the wave calls it
+    __device__ __forceinline__ void stage_wave(bool x, int u) const {
+        const unsigned long long m = __ballot(x);
+        if (m == 0ull) return;
+        const int lane = (int)(threadIdx.x & (WAVE - 1));
+        const int leader = __ffsll((long long)m) - 1;
+        unsigned int base = 0;
+        if (lane == leader) base = atomicAdd(xn, (unsigned int)__popcll(m));
+        base = (unsigned int)__shfl((int)base, leader, WAVE);
+        if (x) {
+            const unsigned int at = base + (unsigned int)__popcll(m & ((1ull << lane) - 1ull));
+            if (at < (unsigned int)XS_CAP) xs[at] = u; else direct(u);
+        }
+    }
+    // Block-uniform call point; `sbase` is an LDS word.  Leaves the buffer empty.
+    __device__ __forceinline__ void flush(unsigned int* sbase) const {
+        __syncthreads();
+        const unsigned int k = min(*xn, (unsigned int)XS_CAP);
+        if (k == 0u) return;  // uniform: every thread read the same count after the barrier
+        if (threadIdx.x == 0) *sbase = atomicAdd(xcnt, k);
+        __syncthreads();
+        const unsigned int b = *sbase;
+        for (unsigned int i = threadIdx.x; i < k; i += blockDim.x) {
+            if (b + i < (unsigned int)cap) {
+                xout[b + i] = xs[i];
+            } else if (i == threadIdx.x) {
+                atomicAdd(&ctl->err_count, 1);
+                ctl->err_code = ERR_INTERNAL;
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) *xn = 0u;
+        __syncthreads();
+    }
+};
+
 struct PeelEdgeOp {
     const unsigned int* st2;
     int* prio;
@@ -611,6 +680,10 @@ struct PeelEdgeOp {
     unsigned int* bfill;
     int* bcnt;
     int* bbase;
+    // near-list rounds: a decrement that takes a priority from above nearB to
+    // at or below it appends the vertex to the next round's crossing list
+    int nearB = -1;  // -1: off
+    XStage xst{};
     __device__ void flag_error() {
         atomicAdd(&ctl->err_count, 1);
         ctl->err_code = ERR_INTERNAL;
@@ -633,6 +706,9 @@ struct PeelEdgeOp {
             }
             const int old = atomicSub(&prio[u], 1);
             lmin = min(lmin, (unsigned int)(old - 1));
+            // (directly to the global list: in bucketed rounds the staging
+            // buffer is the bucket flush's scratch)
+            if (nearB >= 0 && old > nearB && old - 1 <= nearB) xst.direct(u);
             return true;
         }
         return su == 3 && u > v;
@@ -663,6 +739,11 @@ struct PeelEdgeOp {
                 dec->key[slot] = DEC_EMPTY;
                 dec->cnt[slot] = 0;
             }
+        }
+        if (nearB >= 0) {
+#pragma unroll
+            for (int k = 0; k < PER; k++)
+                xst.stage_wave(key[k] != DEC_EMPTY && old[k] > nearB && old[k] - c[k] <= nearB, key[k]);
         }
     }
     // Ranks each aggregated target within its owner range (LDS counters),
@@ -1003,32 +1084,41 @@ __global__ __launch_bounds__(PEEL_BLK, PEEL_BLOCKS_PER_CU) void k_peel_rounds(Pe
         unsigned int rmin = op.lmin;
         if (bucket) {
             grid_sync(bar);
-            // apply: block b owns ranges b, b + grid, ...  It sums its
-            // ranges' bucket entries in a dense LDS histogram and lowers the
-            // priorities with plain read-modify-writes (no other block
-            // touches them until the next grid sync).
+            // apply: block b owns ranges b, b + grid, ...  It sums each
+            // range's bucket entries in a dense LDS histogram, then walks the
+            // entries again: the first entry of each vertex takes (and
+            // clears) its slot and lowers the priority with a plain
+            // read-modify-write (no other block touches it until the next
+            // grid sync).  Work follows the entries, not the range size, and
+            // every range leaves the histogram clear for the next one.
             const int R = 1 << a.rshift;
+            if ((int)blockIdx.x < a.nr) {
+                for (int i = threadIdx.x; i < R; i += PEEL_BLK) lds.dense[i] = 0;  // it aliases the sweep's LDS
+                lds_barrier();
+            }
             for (int j = blockIdx.x; j < a.nr; j += nblocks) {
-                for (int i = threadIdx.x; i < R; i += PEEL_BLK) lds.dense[i] = 0;
                 const int v0 = j << a.rshift;
                 const int v1 = min(a.n, v0 + R);
                 const int lo = a.off[v0];
                 // a reservation past the range's capacity was refused (and
                 // flagged) but still counted: never read past the range
                 const int cnt = min((int)ld_agent(&a.bfill[j]), a.off[v1] - lo);
-                lds_barrier();
                 for (int i = threadIdx.x; i < cnt; i += PEEL_BLK) {
                     const unsigned int e = (unsigned int)a.bkt[lo + i];
                     const unsigned int li = e >> BKT_CNT_BITS;
-                    if (li < (unsigned int)R) atomicAdd(&lds.dense[li], (int)(e & ((1u << BKT_CNT_BITS) - 1)) + 1);
+                    if (li < (unsigned int)(v1 - v0)) atomicAdd(&lds.dense[li], (int)(e & ((1u << BKT_CNT_BITS) - 1)) + 1);
                 }
                 lds_barrier();
-                for (int u = v0 + (int)threadIdx.x; u < v1; u += PEEL_BLK) {
-                    const int c = lds.dense[u - v0];
-                    if (c) {
-                        const int pu = a.prio[u] - c;
-                        a.prio[u] = pu;
-                        rmin = min(rmin, (unsigned int)pu);
+                for (int i = threadIdx.x; i < cnt; i += PEEL_BLK) {
+                    const unsigned int li = (unsigned int)a.bkt[lo + i] >> BKT_CNT_BITS;
+                    if (li < (unsigned int)(v1 - v0)) {
+                        const int c = atomicExch(&lds.dense[li], 0);
+                        if (c) {
+                            const int u = v0 + (int)li;
+                            const int pu = a.prio[u] - c;
+                            a.prio[u] = pu;
+                            rmin = min(rmin, (unsigned int)pu);
+                        }
                     }
                 }
                 if (threadIdx.x == 0) a.bfill[j] = 0;  // empty for the next bucketed round
@@ -1080,6 +1170,449 @@ __global__ __launch_bounds__(PEEL_BLK, PEEL_BLOCKS_PER_CU) void k_peel_rounds(Pe
                     ctl->err_code = ERR_INTERNAL;
                 }
             }
+            grid_wait(bar);
+        }
+    }
+}
+
+// ============================================================ near-list PEEL
+// The same round loop with a select that does not rescan every alive vertex in
+// every round.  Large sparse graphs have hundreds of rounds per iteration in
+// which millions of vertices are alive and a few hundred are peeled; the
+// full-list select reads every alive vertex in each of them.  Here:
+//   * the near bound B splits the alive vertices.  The near list N holds
+//     exactly the alive vertices whose priority is at most B.  Priorities
+//     only fall within an iteration, so a vertex joins N at most once: when a
+//     decrement first takes its priority from above B to B or below, the
+//     decrement appends it to the crossing list X, which the next round reads
+//     after N's own entries;
+//   * a round whose threshold is at most B has its whole frontier in N and
+//     scans only N.  Every other round (round 0, a threshold above B, or an
+//     empty N) scans the full list F: it drops the vertices peeled since F was
+//     last written, sets B = thr * near_num / near_den + 1 and rebuilds N;
+//   * the next round's minimum is exact whenever N is not empty: every near
+//     vertex bids its priority, and every other alive vertex is above B.  When
+//     N runs empty, the next round first rescans F for the exact minimum (one
+//     more pass over F and one more grid sync), then classifies F;
+//   * peeled vertices get priority -1, which marks them dead in F;
+//   * a round's frontier comes out of N in list order, not id order, so the
+//     positions (by round, ascending id inside a round) are sorted after the
+//     loop instead of written by it.
+// Rounds, frontiers, charges and decrements are those of k_peel_rounds.
+// Lists are virtual as there: each block writes its outputs to its own
+// segment (at its slice's start), and per-block tables of segment starts and
+// lengths map virtual positions.
+
+// LDS map of a segment table tab[start | len][PEEL_BLK] with nseg segments;
+// returns the total length.  Reads of `tab` must follow the grid barrier
+// that published it.  Contains block barriers.
+__device__ __forceinline__ long long build_map(const int* __restrict__ tab, int nseg, int* spref, int* sstart,
+                                               unsigned long long* shs) {
+    const int j = (int)threadIdx.x;
+    const int len = j < nseg ? tab[PEEL_BLK + j] : 0;
+    const int st = j < nseg ? tab[j] : 0;
+    unsigned long long tot;
+    const unsigned long long ex = block_excl_scan<PEEL_BLK>((unsigned long long)(unsigned int)len, &tot, shs);
+    if (j < nseg) {
+        spref[j] = (int)ex;
+        sstart[j] = st;
+    }
+    __syncthreads();
+    return (long long)tot;
+}
+
+// Per-block result of one classification pass over a list slice.
+struct NearPass {
+    int n_run;   // near survivors written to the near segment
+    int s_run;   // survivors written to the full-list segment
+    int f_run;   // frontier vertices (written to the tail of the near slice)
+    int i_run;   // frontier vertices with edges
+    unsigned long long edges;  // frontier edges (this thread's share)
+    unsigned int lmin;         // smallest survivor priority (this thread's share)
+    bool one_tile;
+};
+
+// Classifies the slice [beg, end) of a virtual list.  kind 0: entry i is
+// vertex i; 1: Lin[map(i)]; 2: Lin[map(i)] for i < mtot, then Xin[i - mtot].
+// Each alive entry (priority >= 0) goes to exactly one class:
+//   frontier (priority <= thr): round r, priority -1, state bit, Nout tail;
+//   survivor: bids its priority; to Fout[beg + ...] when Fout is given, and
+//   to Nout[beg + ...] when its priority is at most B.
+// For slices of one tile the frontier stays in registers (u, fr, o0, o1).
+template <bool WRITE_F>
+__device__ __forceinline__ NearPass near_classify(const PeelArgs& a, int r, int kind, const int* __restrict__ Lin,
+                                                  const int* __restrict__ Xin, long long mtot, int beg, int end,
+                                                  long long thr, long long B, int* __restrict__ Fout,
+                                                  int* __restrict__ Nout, const int* spref, const int* sstart,
+                                                  unsigned long long* shs, int (&u)[SEL_U], bool (&fr)[SEL_U],
+                                                  int (&o0)[SEL_U], int (&o1)[SEL_U]) {
+    constexpr int TILE = PEEL_BLK * SEL_U;
+    const int nseg = (int)gridDim.x;
+    NearPass P{0, 0, 0, 0, 0ull, 0xFFFFFFFFu, end - beg <= TILE};
+    int sj = 0;
+    if (kind != 0 && end > beg) {
+        const int first = beg + (int)threadIdx.x * SEL_U;
+        int lo = 0, hi = nseg - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (spref[mid] <= first) lo = mid; else hi = mid - 1;
+        }
+        sj = lo;
+    }
+    auto entry = [&](int idx) -> int {
+        if (idx >= end) return -1;
+        if (kind == 0) return idx;
+        if (kind == 2 && idx >= mtot) return Xin[idx - mtot];
+        while (sj + 1 < nseg && spref[sj + 1] <= idx) sj++;
+        return Lin[sstart[sj] + (idx - spref[sj])];
+    };
+    int un[SEL_U];
+#pragma unroll
+    for (int k = 0; k < SEL_U; k++) {
+        u[k] = -1;
+        fr[k] = false;
+        un[k] = entry(beg + (int)threadIdx.x * SEL_U + k);
+    }
+    for (int base = beg; base < end; base += TILE) {
+        int pu[SEL_U];
+#pragma unroll
+        for (int k = 0; k < SEL_U; k++) {
+            u[k] = un[k];
+            un[k] = entry(base + TILE + (int)threadIdx.x * SEL_U + k);
+        }
+#pragma unroll
+        for (int k = 0; k < SEL_U; k++) pu[k] = u[k] >= 0 ? a.prio[u[k]] : -1;
+#pragma unroll
+        for (int k = 0; k < SEL_U; k++) {
+            fr[k] = pu[k] >= 0 && (long long)pu[k] <= thr;
+            o0[k] = fr[k] ? a.off[u[k]] : 0;
+            o1[k] = fr[k] ? a.off[u[k] + 1] : 0;
+        }
+        // packed per-thread counts: [near: 0-15][full-list survivors: 16-31][frontier: 32-47][items: 48-63]
+        unsigned long long val = 0;
+#pragma unroll
+        for (int k = 0; k < SEL_U; k++) {
+            if (pu[k] < 0) continue;  // no entry, or peeled in an earlier round
+            if (fr[k]) {
+                a.rnd[u[k]] = r;
+                a.prio[u[k]] = -1;
+                val += 1ull << 32;
+                const int d = o1[k] - o0[k];
+                if (d > 0) {
+                    val += 1ull << 48;
+                    P.edges += (unsigned long long)d;
+                    atomicOr(&a.st2[u[k] >> 4], 2u << ((u[k] & 15) * 2));
+                }
+            } else {
+                P.lmin = min(P.lmin, (unsigned int)pu[k]);
+                if (WRITE_F) val += 1ull << 16;
+                if ((long long)pu[k] <= B) val += 1ull;
+            }
+        }
+        unsigned long long tot;
+        const unsigned long long ex = block_excl_scan<PEEL_BLK>(val, &tot, shs);
+        int nr_ = beg + P.n_run + (int)(ex & 0xFFFFull);
+        int sr_ = beg + P.s_run + (int)((ex >> 16) & 0xFFFFull);
+        int fr_ = end - 1 - (P.f_run + (int)((ex >> 32) & 0xFFFFull));
+#pragma unroll
+        for (int k = 0; k < SEL_U; k++) {
+            if (pu[k] < 0) continue;
+            if (fr[k]) {
+                Nout[fr_--] = u[k];
+            } else {
+                if (WRITE_F) Fout[sr_++] = u[k];
+                if ((long long)pu[k] <= B) Nout[nr_++] = u[k];
+            }
+        }
+        P.n_run += (int)(tot & 0xFFFFull);
+        P.s_run += (int)((tot >> 16) & 0xFFFFull);
+        P.f_run += (int)((tot >> 32) & 0xFFFFull);
+        P.i_run += (int)(tot >> 48);
+    }
+    return P;
+}
+
+template <bool MONO>
+__global__ __launch_bounds__(PEEL_BLK, PEEL_BLOCKS_PER_CU) void k_peel_rounds_near(PeelArgs a) {
+    __shared__ PeelLds lds;
+    __shared__ unsigned long long shs[PEEL_BLK / WAVE];
+    __shared__ unsigned int shm[PEEL_BLK / WAVE];
+    __shared__ unsigned long long s_fbase;
+    __shared__ int s_chunk;
+    __shared__ long long s_ntot;  // entries in the near list's segments (map built at the previous round's end)
+    __shared__ unsigned int s_xn;     // staged crossings
+    __shared__ unsigned int s_xbase;  // their reserved start in the global list
+    Ctl* ctl = a.ctl;
+    GridSync* gs = a.gs;
+    const unsigned int nblocks = gridDim.x;
+    const long long q = a.eps_den, p = a.eps_num;
+    for (int slot = threadIdx.x; slot < DEC_SLOTS; slot += PEEL_BLK) {
+        lds.m.dec.key[slot] = DEC_EMPTY;
+        lds.m.dec.cnt[slot] = 0;
+    }
+    for (int j = threadIdx.x; j < BKT_MAX_NR; j += PEEL_BLK) lds.bcnt[j] = 0;
+    if (threadIdx.x == 0) {
+        s_ntot = 0;
+        s_xn = 0;
+    }
+    GridBarrier bar = grid_sync_init(gs, nblocks, xcd_id());
+    long long alive = a.n;
+    long long B = -1;        // near bound (-1 until the first full-list round)
+    long long thr_prev = 0;  // MONO: largest threshold so far
+    int fpar = 0;            // the full list F is segF[fpar] over L0 (fpar 0) or L1 (fpar 1)
+    bool f_all = true;       // F is still every vertex (before the first full-list round writes it)
+    for (int r = 0;; r++) {
+        const int slot = r & 3, nslot = (r + 1) & 3;
+        if (r > 0) {
+            const unsigned int pc = ld_agent(&ctl->pcnt[(r - 1) & 3]);
+            if (pc == 0u || (long long)pc > alive) {
+                // every round peels the minimum vertex; all blocks see the same
+                // counts and leave together
+                if (blockIdx.x == 0 && threadIdx.x == 0) {
+                    ctl->nrounds = r;
+                    atomicAdd(&ctl->err_count, 1);
+                    ctl->err_code = ERR_INTERNAL;
+                }
+                break;
+            }
+            alive -= pc;
+        }
+        if (alive == 0) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) ctl->nrounds = r;
+            break;
+        }
+        unsigned int mn = ld_agent(&ctl->mn[slot]);
+        const long long xin = r > 0 ? (long long)ld_agent(&ctl->xcnt[slot]) : 0;
+        const long long nin = r > 0 ? s_ntot + xin : 0;
+        long long thr = ((q + p) * (long long)mn) / q;
+        if (MONO && r > 0) thr = max(thr, thr_prev);
+        const bool full = r == 0 || nin == 0 || thr > B;
+        const bool exact = r == 0 || nin > 0;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            const int zs = (r + 2) & 3;
+            ctl->mn[zs] = 0xFFFFFFFFu;
+            ctl->fcnt[zs] = 0;
+            ctl->cnext[zs] = 0;
+            ctl->pcnt[zs] = 0;
+            ctl->xcnt[zs] = 0;
+            ctl->mn2[zs] = 0xFFFFFFFFu;
+        }
+        int* __restrict__ ivr = (r & 1) ? a.iv1 : a.iv0;
+        const int* __restrict__ Nin = (r & 1) ? a.N1 : a.N0;
+        int* __restrict__ Nout = (r & 1) ? a.N0 : a.N1;
+        const int* __restrict__ Xin = (r & 1) ? a.X1 : a.X0;
+        int* __restrict__ Xout = (r & 1) ? a.X0 : a.X1;
+        int* __restrict__ segNout = a.segN + (r & 1) * 2 * PEEL_BLK;
+        if (r > 0) {
+            // the previous round's frontier is peeled now: clear its state bits
+            const int* __restrict__ ivp = (r & 1) ? a.iv0 : a.iv1;
+            const int Kp = (int)(ld_agent_u64(&ctl->fcnt[(r - 1) & 3]) >> FCNT_SHIFT);
+            for (int k = blockIdx.x * PEEL_BLK + threadIdx.x; k < Kp; k += nblocks * PEEL_BLK) {
+                const int w = ivp[k];
+                atomicAnd(&a.st2[w >> 4], ~(3u << ((w & 15) * 2)));
+            }
+        }
+        int u[SEL_U], o0[SEL_U], o1[SEL_U];
+        bool fr[SEL_U];
+        NearPass P;
+        int beg, end;
+        if (full) {
+            long long ftot = a.n;
+            if (!f_all) ftot = build_map(a.segF + fpar * 2 * PEEL_BLK, (int)nblocks, lds.spref, lds.sstart, shs);
+            if (!exact) {
+                // N ran empty: compact F into the other buffer and find the exact minimum first
+                const long long per = (ftot + nblocks - 1) / nblocks;
+                beg = (int)min(ftot, (long long)blockIdx.x * per);
+                end = (int)min(ftot, (long long)beg + per);
+                const int* Fin = fpar ? a.L1 : a.L0;
+                int* Fout = fpar ? a.L0 : a.L1;
+                P = near_classify<true>(a, r, f_all ? 0 : 1, Fin, nullptr, ftot, beg, end, -2, -1, Fout, Nout,
+                                        lds.spref, lds.sstart, shs, u, fr, o0, o1);
+                int* segFout = a.segF + (fpar ^ 1) * 2 * PEEL_BLK;
+                if (threadIdx.x == 0) {
+                    segFout[blockIdx.x] = beg;
+                    segFout[PEEL_BLK + blockIdx.x] = P.s_run;
+                }
+                const unsigned int bmin = block_min<PEEL_BLK>(P.lmin, shm);
+                if (threadIdx.x == 0 && bmin != 0xFFFFFFFFu) atomicMin(&ctl->mn2[slot], bmin);
+                grid_sync(bar);
+                fpar ^= 1;
+                f_all = false;
+                ftot = build_map(a.segF + fpar * 2 * PEEL_BLK, (int)nblocks, lds.spref, lds.sstart, shs);
+                mn = ld_agent(&ctl->mn2[slot]);
+                thr = ((q + p) * (long long)mn) / q;
+                if (MONO && r > 0) thr = max(thr, thr_prev);
+            }
+            B = min(thr * a.near_num / a.near_den + 1, (long long)0x7FFFFFFE);
+            const long long per = (ftot + nblocks - 1) / nblocks;
+            beg = (int)min(ftot, (long long)blockIdx.x * per);
+            end = (int)min(ftot, (long long)beg + per);
+            const int* Fin = fpar ? a.L1 : a.L0;
+            if (exact) {
+                // one pass: survivors to the other F buffer, near survivors to N
+                int* Fout = fpar ? a.L0 : a.L1;
+                P = near_classify<true>(a, r, f_all ? 0 : 1, Fin, nullptr, ftot, beg, end, thr, B, Fout, Nout,
+                                        lds.spref, lds.sstart, shs, u, fr, o0, o1);
+                int* segFout = a.segF + (fpar ^ 1) * 2 * PEEL_BLK;
+                if (threadIdx.x == 0) {
+                    segFout[blockIdx.x] = beg;
+                    segFout[PEEL_BLK + blockIdx.x] = P.s_run;
+                }
+                fpar ^= 1;
+                f_all = false;
+            } else {
+                P = near_classify<false>(a, r, 1, Fin, nullptr, ftot, beg, end, thr, B, nullptr, Nout, lds.spref,
+                                         lds.sstart, shs, u, fr, o0, o1);
+            }
+        } else {
+            const long long per = (nin + nblocks - 1) / nblocks;
+            beg = (int)min(nin, (long long)blockIdx.x * per);
+            end = (int)min(nin, (long long)beg + per);
+            P = near_classify<false>(a, r, 2, Nin, Xin, s_ntot, beg, end, thr, B, nullptr, Nout, lds.spref,
+                                     lds.sstart, shs, u, fr, o0, o1);
+        }
+        thr_prev = thr;
+        if (a.rmin && blockIdx.x == 0 && threadIdx.x == 0) a.rmin[r] = (int)min(thr, 0x7FFFFFFFLL);
+        {
+            const unsigned long long eb = block_sum<PEEL_BLK>(P.edges, shs);
+            const unsigned long long packed = ((unsigned long long)P.i_run << FCNT_SHIFT) | eb;
+            if (threadIdx.x == 0) {
+                s_fbase = packed ? atomicAdd(&ctl->fcnt[slot], packed) : 0ull;
+                if (P.f_run) atomicAdd(&ctl->pcnt[slot], (unsigned int)P.f_run);
+                segNout[blockIdx.x] = beg;
+                segNout[PEEL_BLK + blockIdx.x] = P.n_run;
+            }
+            __syncthreads();  // also orders the tail writes before the reads below
+        }
+        unsigned long long fb = s_fbase;
+        // item pass: the frontier vertices with edges, from registers (one
+        // tile) or from the tail of the block's near slice
+        constexpr int TILE = PEEL_BLK * SEL_U;
+        const int item_end = P.one_tile ? (end > beg ? 1 : 0) : P.f_run;
+        for (int base = 0; base < item_end; base += TILE) {
+            if (!P.one_tile) {
+#pragma unroll
+                for (int k = 0; k < SEL_U; k++) {
+                    const int j = base + (int)threadIdx.x * SEL_U + k;
+                    u[k] = j < P.f_run ? Nout[end - 1 - j] : -1;
+                    fr[k] = u[k] >= 0;
+                    o0[k] = fr[k] ? a.off[u[k]] : 0;
+                    o1[k] = fr[k] ? a.off[u[k] + 1] : 0;
+                }
+            }
+            unsigned long long val = 0;
+#pragma unroll
+            for (int k = 0; k < SEL_U; k++) {
+                const int d = o1[k] - o0[k];
+                if (fr[k] && d > 0) val += (1ull << TITEM_SHIFT) + (unsigned long long)d;
+            }
+            unsigned long long tot;
+            const unsigned long long ex = block_excl_scan<PEEL_BLK>(val, &tot, shs);
+            unsigned long long it = (fb >> FCNT_SHIFT) + (ex >> TITEM_SHIFT);
+            unsigned long long ed = (fb & FCNT_MASK) + (ex & 0xFFFFFFFFull);
+#pragma unroll
+            for (int k = 0; k < SEL_U; k++) {
+                const int d = o1[k] - o0[k];
+                if (fr[k] && d > 0) {
+                    ivr[it] = u[k];
+                    a.ie[it] = (int)ed;
+                    a.ir[it] = o0[k] - (int)ed;
+                    mark_chunks<PEEL_MARK>((long long)ed, (long long)ed + d, (int)it, a.cfirst, a.clast);
+                    it++;
+                    ed += d;
+                }
+            }
+            fb += ((tot >> TITEM_SHIFT) << FCNT_SHIFT) + (tot & 0xFFFFFFFFull);
+        }
+        grid_sync(bar);
+        // ---------------- sweep
+        const unsigned long long f = ld_agent_u64(&ctl->fcnt[slot]);
+        const int K = (int)(f >> FCNT_SHIFT);
+        const long long E = (long long)(f & FCNT_MASK);
+        const bool bucket = a.nr > 0 && E >= a.bkt_min_e;
+        PeelEdgeOp op{a.st2, a.prio, r, P.lmin, ctl, &lds.m.dec, bucket, a.rshift, a.nr, a.n, a.off, a.bkt, a.bfill,
+                      lds.bcnt, lds.bbase};
+        // crossings are staged in lds.bbase, which only the bucket flush uses (as scratch)
+        const XStage xst{lds.bbase, &s_xn, Xout, &ctl->xcnt[nslot], a.n, ctl};
+        op.nearB = (int)B;
+        op.xst = xst;
+        if (E >= a.coarse_min_e)
+            sweep_chunks<PEEL_BLK, PEEL_CH, PEEL_CH / PEEL_MARK>(K, E, ivr, a.ie, a.ir, a.cfirst, a.clast, a.adj,
+                                                                 a.inc, op, lds.m.sw, blockIdx.x, nblocks,
+                                                                 &ctl->cnext[slot], &s_chunk);
+        else
+            sweep_chunks<PEEL_BLK, PEEL_MARK, 1>(K, E, ivr, a.ie, a.ir, a.cfirst, a.clast, a.adj, a.inc, op,
+                                                 lds.m.sw, blockIdx.x, nblocks, &ctl->cnext[slot], &s_chunk);
+        unsigned int rmin = op.lmin;
+        if (bucket) {
+            grid_sync(bar);
+            // apply the owner buckets as k_peel_rounds does; a decrement that
+            // crosses B appends its vertex to the crossing list
+            const int R = 1 << a.rshift;
+            if ((int)blockIdx.x < a.nr) {
+                for (int i = threadIdx.x; i < R; i += PEEL_BLK) lds.dense[i] = 0;
+                lds_barrier();
+            }
+            for (int j = blockIdx.x; j < a.nr; j += nblocks) {
+                const int v0 = j << a.rshift;
+                const int v1 = min(a.n, v0 + R);
+                const int lo = a.off[v0];
+                const int cnt = min((int)ld_agent(&a.bfill[j]), a.off[v1] - lo);
+                for (int i = threadIdx.x; i < cnt; i += PEEL_BLK) {
+                    const unsigned int e = (unsigned int)a.bkt[lo + i];
+                    const unsigned int li = e >> BKT_CNT_BITS;
+                    if (li < (unsigned int)(v1 - v0)) atomicAdd(&lds.dense[li], (int)(e & ((1u << BKT_CNT_BITS) - 1)) + 1);
+                }
+                lds_barrier();
+                for (int base = 0; base < cnt; base += PEEL_BLK) {
+                    const int i = base + (int)threadIdx.x;
+                    bool x = false;
+                    int w = 0;
+                    if (i < cnt) {
+                        const unsigned int li = (unsigned int)a.bkt[lo + i] >> BKT_CNT_BITS;
+                        if (li < (unsigned int)(v1 - v0)) {
+                            const int c = atomicExch(&lds.dense[li], 0);
+                            if (c) {
+                                w = v0 + (int)li;
+                                const int old = a.prio[w];
+                                const int pw = old - c;
+                                a.prio[w] = pw;
+                                rmin = min(rmin, (unsigned int)pw);
+                                x = (long long)old > B && (long long)pw <= B;
+                            }
+                        }
+                    }
+                    xst.stage_wave(x, w);
+                }
+                if (threadIdx.x == 0) a.bfill[j] = 0;
+                lds_barrier();
+            }
+            if ((int)blockIdx.x < a.nr) {
+                for (int t = threadIdx.x; t < DEC_SLOTS; t += PEEL_BLK) {
+                    lds.m.dec.key[t] = DEC_EMPTY;
+                    lds.m.dec.cnt[t] = 0;
+                }
+            }
+        }
+        xst.flush(&s_xbase);
+        const unsigned int bmin = block_min<PEEL_BLK>(rmin, shm);
+        if (threadIdx.x == 0 && bmin != 0xFFFFFFFFu) atomicMin(&ctl->mn[nslot], bmin);
+        {
+            // the near list's segment table was published by the grid sync
+            // after the select: map it between the halves of the round-end
+            // barrier (the crossings' count is read after it)
+            const int j = (int)threadIdx.x;
+            const int len = j < (int)nblocks ? segNout[PEEL_BLK + j] : 0;
+            const int st = j < (int)nblocks ? segNout[j] : 0;
+            grid_arrive(bar);
+            unsigned long long tot;
+            const unsigned long long ex =
+                block_excl_scan<PEEL_BLK>((unsigned long long)(unsigned int)len, &tot, shs);
+            if (j < (int)nblocks) {
+                lds.spref[j] = (int)ex;
+                lds.sstart[j] = st;
+            }
+            if (j == 0) s_ntot = (long long)tot;
             grid_wait(bar);
         }
     }
@@ -1909,21 +2442,49 @@ hipError_t launch_reset_state(const GraphDev& g, hipStream_t s) {
 
 // Stable LSD radix sort of the n vertex ids by key_src[v] over `passes`
 // 8-bit digits; the sorted ids land in g.order.
-static hipError_t enqueue_radix(const GraphDev& g, const int* key_src, int passes, hipStream_t s) {
+// One stable LSD pass: keys kin (values vin, or the index when null) by the
+// 8-bit digit at `shift` into kout (may be null) / vout.
+static void enqueue_radix_pass(const GraphDev& g, const int* kin, const int* vin, int* kout, int* vout, int shift,
+                               const int* gate, hipStream_t s) {
     const int rt = ceil_div(g.n, RTILE);
+    const int total = RBINS * rt;
+    const int st = ceil_div(total, SCAN_TILE);
+    k_radix_hist<<<rt, RBLK, 0, s>>>(kin, g.n, shift, g.rhist, rt, gate);
+    k_rscan_tiles<<<st, SCAN_BLK, 0, s>>>(g.rhist, total, g.tile_off, gate);
+    k_rscan_top<<<1, 1024, 0, s>>>(g.tile_off, st, gate);
+    k_rscan_apply<<<st, SCAN_BLK, 0, s>>>(g.rhist, total, g.tile_off, gate);
+    k_radix_scatter<<<rt, RBLK, 0, s>>>(kin, vin, kout, vout, g.n, shift, g.rhist, rt, gate);
+}
+
+static hipError_t enqueue_radix(const GraphDev& g, const int* key_src, int passes, hipStream_t s) {
     for (int p = 0; p < passes; p++) {
-        const int shift = 8 * p;
         const int* kin = p == 0 ? key_src : ((p - 1) & 1 ? g.kB : g.kA);
         const int* vin = p == 0 ? nullptr : ((p - 1) & 1 ? g.vB : g.vA);
         int* kout = p == passes - 1 ? nullptr : (p & 1 ? g.kB : g.kA);
         int* vout = p == passes - 1 ? g.order : (p & 1 ? g.vB : g.vA);
-        const int total = RBINS * rt;
-        const int st = ceil_div(total, SCAN_TILE);
-        k_radix_hist<<<rt, RBLK, 0, s>>>(kin, g.n, shift, g.rhist, rt);
-        k_rscan_tiles<<<st, SCAN_BLK, 0, s>>>(g.rhist, total, g.tile_off);
-        k_rscan_top<<<1, 1024, 0, s>>>(g.tile_off, st);
-        k_rscan_apply<<<st, SCAN_BLK, 0, s>>>(g.rhist, total, g.tile_off);
-        k_radix_scatter<<<rt, RBLK, 0, s>>>(kin, vin, kout, vout, g.n, shift, g.rhist, rt);
+        enqueue_radix_pass(g, kin, vin, kout, vout, 8 * p, nullptr, s);
+    }
+    return hipGetLastError();
+}
+
+// The order by (round, id) after a near-list round loop: a stable sort of the
+// vertices by round.  Rounds number at most n.  Up to 2^16 vertices two passes
+// suffice; above, the first two passes already leave their result in the
+// order array, and the two upper passes (order -> vA -> order) skip
+// themselves when the iteration had at most 2^16 rounds, as it nearly always
+// has.
+static hipError_t enqueue_sort_by_round(const GraphDev& g, hipStream_t s) {
+    if (g.n <= 256) {
+        enqueue_radix_pass(g, g.rnd, nullptr, nullptr, g.order, 0, nullptr, s);
+    } else if (g.n <= (1 << 16)) {
+        enqueue_radix_pass(g, g.rnd, nullptr, g.kA, g.vA, 0, nullptr, s);
+        enqueue_radix_pass(g, g.kA, g.vA, nullptr, g.order, 8, nullptr, s);
+    } else {
+        const int* gate = &g.ctl->nrounds;
+        enqueue_radix_pass(g, g.rnd, nullptr, g.kA, g.vA, 0, nullptr, s);
+        enqueue_radix_pass(g, g.kA, g.vA, g.kB, g.order, 8, nullptr, s);
+        enqueue_radix_pass(g, g.kB, g.order, g.kA, g.vA, 16, gate, s);
+        enqueue_radix_pass(g, g.kA, g.vA, nullptr, g.order, 24, gate, s);
     }
     return hipGetLastError();
 }
@@ -1943,8 +2504,8 @@ static hipError_t enqueue_alg3(const GraphDev& g, int slot, int nrounds_static, 
 }
 
 hipError_t enqueue_iter_peel(const GraphDev& g, int slot, int eps_num, int eps_den, int peel_grid,
-                             long long bkt_min_e, long long coarse_min_e, int mono, hipStream_t s, hipEvent_t ev_a,
-                             hipEvent_t ev_b) {
+                             long long bkt_min_e, long long coarse_min_e, int mono, int near, hipStream_t s,
+                             hipEvent_t ev_a, hipEvent_t ev_b) {
     k_iter_begin<<<1, 256, 0, s>>>(g.ctl, g.gsync, g.bfill, g.nr);
     k_peel_init<<<grid_for(g.n, 256, 2048), 256, 0, s>>>(g.n, g.off, g.load, g.prio, g.rnd, g.inc, g.st2, g.ctl);
     hipError_t e = hipGetLastError();
@@ -1978,15 +2539,30 @@ hipError_t enqueue_iter_peel(const GraphDev& g, int slot, int eps_num, int eps_d
     a.seg = g.seg;
     a.order = g.order;
     a.rmin = g.rmin;
+    a.N0 = g.N0;
+    a.N1 = g.N1;
+    a.X0 = g.X0;
+    a.X1 = g.X1;
+    a.segF = g.segF;
+    a.segN = g.segN;
+    a.near_num = NEAR_B_NUM;
+    a.near_den = NEAR_B_DEN;
     if (peel_grid > PEEL_BLK) return hipErrorInvalidValue;  // one segment per thread of a block
     void* args[] = {&a};
     if (ev_a && (e = hipEventRecord(ev_a, s)) != hipSuccess) return e;
-    e = hipLaunchCooperativeKernel(mono ? reinterpret_cast<const void*>(k_peel_rounds<true>)
-                                        : reinterpret_cast<const void*>(k_peel_rounds<false>),
-                                   dim3(peel_grid), dim3(PEEL_BLK), args, 0, s);
+    const void* kern = near ? (mono ? reinterpret_cast<const void*>(k_peel_rounds_near<true>)
+                                    : reinterpret_cast<const void*>(k_peel_rounds_near<false>))
+                            : (mono ? reinterpret_cast<const void*>(k_peel_rounds<true>)
+                                    : reinterpret_cast<const void*>(k_peel_rounds<false>));
+    e = hipLaunchCooperativeKernel(kern, dim3(peel_grid), dim3(PEEL_BLK), args, 0, s);
     if (e != hipSuccess) return e;
     if (ev_b && (e = hipEventRecord(ev_b, s)) != hipSuccess) return e;
-    // the round loop wrote the order (by round, ascending id inside a round)
+    if (near) {
+        e = enqueue_sort_by_round(g, s);
+        if (e != hipSuccess) return e;
+    }
+    // the order is by round, ascending id inside a round (written by the
+    // full-list round loop itself)
     return enqueue_alg3(g, slot, 0, s);
 }
 

@@ -57,12 +57,11 @@ def test_workspace_bytes_host_logic(lib):
     big = dsg.workspace_bytes(4194304, 128312518, 64)
     assert 0 < small < big
     assert big % 256 == 0
-    # state grows linearly in n and nnz: about 18 int32 arrays of n, chunk maps, and the PEEL owner buckets
-    # (one int32 per adjacency entry while n <= 1024 * 16384)
-    assert 4194304 * 4 * 16 + 4 * 128312518 < big < 4194304 * 4 * 24 + 5 * 128312518
-    # beyond 1024 ranges of 16384 ids the bucketed path is off and takes no space
-    huge_n = 1024 * 16384 + 1
-    assert dsg.workspace_bytes(huge_n, 1000, 4) < huge_n * 4 * 24
+    # state grows linearly in n and nnz: about 22 int32 arrays of n (the near-list select's four included),
+    # chunk maps, and the PEEL owner buckets (one int32 per adjacency entry; every n below 2^26 has them)
+    assert 4194304 * 4 * 20 + 4 * 128312518 < big < 4194304 * 4 * 28 + 5 * 128312518
+    huge_n = (1 << 26) - 1
+    assert huge_n * 4 * 20 + 4 * 1000 < dsg.workspace_bytes(huge_n, 1000, 4) < huge_n * 4 * 28 + 5 * 1000
     with pytest.raises(dsg.DsgError):
         dsg.workspace_bytes(0, 0, 1)
     with pytest.raises(dsg.DsgError):

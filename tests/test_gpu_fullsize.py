@@ -6,13 +6,15 @@
   the oracle alone).  The comparison covers per-iteration densities and
   indices, order digests, round counts, best pair, and SHA-256 of the loads,
   of the best-set mask, and of the last iteration's rounds and positions.
-* Chung-Lu n = 40M, gamma 2.1 (the 5 GB configuration), SORT and PEEL
-  eps = 1/20.  Here the oracle is too slow for the whole run, so it checks
-  properties that hold at any size: sum of loads = T*m, the best mask
-  recounted from the CSR on the host equals (edges, vertices), per-iteration
-  width <= Delta, positions form a permutation, and the ordering property
-  of the last iteration holds.  The first iteration of SORT is compared
-  with the oracle outright.
+* Chung-Lu n = 40M, gamma 2.1 (the 5 GB configuration), SORT T = 50 and PEEL
+  eps = 1/20 T = 50, bit for bit against stored oracle results
+  (tests/golden/config3_{sort,peel}.json, the same fields as above).  This is
+  the only configuration whose edge positions pass 2^30, whose owner ranges
+  exceed the bucketed path's limit and whose SORT class table lives outside
+  L2.  Beside it, properties that hold at any size: sum of loads = T*m, the
+  best mask recounted from the CSR on the host equals (edges, vertices),
+  per-iteration width <= Delta, positions form a permutation, and the
+  ordering property of the last iteration holds.
 """
 import hashlib
 import json
@@ -88,6 +90,39 @@ def _recount(o, a, mask):
 def config3():
     log("generating Chung-Lu n=40M")
     return graphgen.config3(1)
+
+
+def _compare_golden(g, gd, what):
+    dens = g.iter_densities()
+    assert [[e, v] for e, v, _ in dens] == gd["hist"], what
+    assert [i for _, _, i in dens] == gd["hist_idx"], what
+    digests, rounds = g.digests()
+    assert rounds == gd["rounds"], what
+    assert [str(d) for d in digests] == gd["digests"], what
+    assert list(g.best()) == gd["best"], what
+    loads = g.loads()
+    assert int(loads.sum()) == gd["loads_sum"], what
+    assert sha(loads.astype(np.int64)) == gd["loads_sha256"], what
+    assert sha(g.best_mask().astype(np.uint8)) == gd["best_mask_sha256"], what
+    rnd, pos, _ = g.order()
+    assert sha(rnd.astype(np.int32)) == gd["last_round_sha256"], what
+    assert sha(pos.astype(np.int32)) == gd["last_pos_sha256"], what
+
+
+@pytest.mark.parametrize("golden_name", ["config3_sort", "config3_peel"])
+def test_config3_against_golden(dsg, config3, golden_name):
+    with open(os.path.join(HERE, "golden", golden_name + ".json")) as f:
+        gd = json.load(f)
+    o, a = config3
+    assert sha(o) + sha(a) == gd["csr_sha256"], "generator output changed"
+    ctx = dsg.Context(0)
+    g = dsg.Graph(ctx, o, a, t_cap=gd["T"], validate=False)
+    log(f"{golden_name}: running {gd['variant']} eps={gd['eps']} T={gd['T']}")
+    g.run(gd["T"], tuple(gd["eps"]), gd["variant"])
+    g.sync()
+    _compare_golden(g, gd, golden_name)
+    g.close()
+    ctx.close()
 
 
 @pytest.mark.parametrize("variant,eps,T", [("sort", (0, 1), 50), ("peel", (1, 20), 10)])

@@ -294,15 +294,15 @@ def test_peel_bucket_paths(dsg, ctx, name):
 
 
 def test_peel_bucket_more_ranges_than_blocks(dsg, ctx):
-    """n = 5M vertices: 16384-id ranges number 306, more than the round loop's blocks, so blocks apply several
-    ranges per bucketed round."""
-    o, a = graphgen.er_planted(14, 5_000_000, 6_000_000, 60, 1, 2)
+    """n = 12M vertices: 32768-id ranges number 367, more than the round loop's blocks, so blocks apply several
+    ranges per bucketed round (and the last range is partial)."""
+    o, a = graphgen.er_planted(14, 12_000_000, 14_000_000, 60, 1, 2)
     ref = oracle.run(o, a, 2, "peel", (1, 10))
     for thr in [0, 1 << 62]:
-        log(f"bucket n=5M threshold={thr}")
+        log(f"bucket n=12M threshold={thr}")
         g = dsg.Graph(ctx, o, a, t_cap=4).set_peel_tuning(thr, thr)
         g.run(2, (1, 10), "peel")
-        assert_same(g, ref, f"bucket5M/{thr}")
+        assert_same(g, ref, f"bucket12M/{thr}")
         g.close()
 
 
@@ -336,4 +336,73 @@ def test_width_and_load_bounds(dsg, ctx, name):
             st = oracle.run(o, a, 1, variant, eps, state=st)
             ref.append((st.width[-1], int(st.loads.max()) if n > 0 else 0))
         assert g.iter_bounds() == ref, f"{name}/{variant}: {g.iter_bounds()} vs {ref}"
+        g.close()
+
+
+def _near_cases():
+    ec = edge_cases()
+    cases = {k: ec[k] for k in ["single_vertex", "no_edges_n7", "one_edge", "triangle", "K40", "star_3000",
+                                "path_50", "isolated_mix", "two_cliques", "gnp_0", "gnp_5"]}
+    cases["config1"] = graphgen.config1(4)
+    cases["ragged_12289"] = graphgen.er_planted(17, 12289, 70000, 60, 1, 2)
+    cases["rmat16"] = graphgen.rmat(21, 16, 16 << 16)
+    cases["chunglu_300k"] = graphgen.chunglu(23, 300_000, 2.1, 30.0, 15_000.0)
+    return cases
+
+
+@pytest.mark.parametrize("name", list(_near_cases().keys()))
+def test_peel_near_select(dsg, ctx, name):
+    """The near-list select against the oracle: PEEL and PEEL_MONO at several eps (eps = 0 gives many rounds with
+    tiny frontiers, where the near list runs empty and rounds rescan the full list for the exact minimum), with
+    owner buckets in every round or in none, over 5 iterations (loads make later priorities tie densely)."""
+    o, a = _near_cases()[name]
+    for variant, eps in [("peel", (1, 10)), ("peel", (0, 1)), ("peel", (1, 20)), ("peel_mono", (0, 1)),
+                         ("peel_mono", (1, 10))]:
+        ref = oracle.run(o, a, 5, variant, eps)
+        for bkt in (0, 1 << 62):
+            log(f"near case={name} variant={variant} eps={eps} bucket_min={bkt}")
+            g = dsg.Graph(ctx, o, a, t_cap=8).set_peel_select(1).set_peel_tuning(bkt, -1)
+            g.run(5, eps, variant)
+            assert_same(g, ref, f"near/{name}/{variant}/{eps}/{bkt}")
+            g.close()
+
+
+def test_peel_select_modes_agree_large(dsg, ctx):
+    """A 2M-vertex Chung-Lu graph (thousands of owner-range entries per block, a near list of millions): both
+    selects give the same results, and those of the oracle."""
+    o, a = graphgen.chunglu(29, 2_000_000, 2.1, 20.0, 100_000.0)
+    ref = oracle.run(o, a, 3, "peel", (1, 20))
+    for mode in (0, 1):
+        log(f"select mode={mode} on Chung-Lu 2M")
+        g = dsg.Graph(ctx, o, a, t_cap=4).set_peel_select(mode)
+        g.run(3, (1, 20), "peel")
+        assert_same(g, ref, f"chunglu2M/select{mode}")
+        g.close()
+
+
+@pytest.mark.parametrize("variant,eps", [("peel", (1, 10)), ("sort", (0, 1)), ("seq", (0, 1)), ("peel_mono", (1, 20))])
+def test_run_until_certificate(dsg, ctx, variant, eps):
+    """dsg_run_until stops at the first iteration whose load certificate L_t * v * den <= t * e * (den + num) holds,
+    computed here from the oracle's own loads and best pair one iteration at a time, and leaves exactly the
+    oracle's state after that many iterations (or after T_max when the certificate never holds)."""
+    cases = [("config1", graphgen.config1(2), (1, 50), 40), ("K40", graphgen.complete(40), (0, 1), 5),
+             ("rmat12", graphgen.rmat(8, 12, 16 << 12), (1, 20), 30), ("rmat12_tight", graphgen.rmat(8, 12, 16 << 12),
+                                                                        (0, 1), 6)]
+    for name, (o, a), (tn, td), tmax in cases:
+        if variant == "seq" and len(o) - 1 > 16000:
+            continue
+        st, stop = None, None
+        for t in range(1, tmax + 1):
+            st = oracle.run(o, a, 1, variant, eps, state=st)
+            lmax = int(st.loads.max())
+            e, v = int(st.best[0]), int(st.best[1])
+            if lmax * v * td <= t * e * (td + tn):
+                stop = t
+                break
+        log(f"run_until case={name} variant={variant} tol={tn}/{td}: oracle stops at {stop}")
+        g = dsg.Graph(ctx, o, a, t_cap=tmax)
+        it, ok = g.run_until(tmax, eps, variant, (tn, td))
+        assert ok == (stop is not None), name
+        assert it == (stop if stop is not None else tmax), (name, it, stop)
+        assert_same(g, st, f"run_until/{name}/{variant}")
         g.close()

@@ -52,3 +52,24 @@ def test_exact_planted_set_is_found():
     r, mask = densest_exact(o, a)
     assert int(mask.sum()) == 50 and _density(o, a, mask) == r
     assert r > Fraction(20000, 2000)
+
+
+@pytest.mark.parametrize("variant,eps", [("seq", (0, 1)), ("peel", (1, 10)), ("peel", (0, 1)), ("sort", (0, 1)),
+                                         ("peel_mono", (1, 20))])
+def test_load_certificate_is_sound(variant, eps):
+    """The stopping certificate's bound rho* <= L_t / t (L_t = largest load after t iterations): every iteration of
+    every ordering charges each edge to one of its endpoints, so the loads inside a densest set S* grow by at least
+    |E(S*)| per iteration.  Checked against the exact rho* after each of 12 iterations on the pin family, config 1
+    and a small R-MAT graph; the best density found never exceeds rho* either."""
+    import oracle
+
+    graphs = list(_small_graphs()) + [graphgen.config1(2), graphgen.rmat(6, 9, 16 << 9)]
+    for o, a in graphs:
+        r, _ = densest_exact(o, a)
+        st = None
+        for t in range(1, 13):
+            st = oracle.run(o, a, 1, variant, eps, state=st)
+            lmax = int(st.loads.max()) if len(st.loads) else 0
+            assert r * t <= lmax, (variant, t)
+            e, v = int(st.best[0]), int(st.best[1])
+            assert Fraction(e, v) <= r
