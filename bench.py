@@ -27,10 +27,13 @@ Also printed, on the same JSON line:
                 per launch from committed rocprofv3 FETCH_SIZE / WRITE_SIZE
                 summaries, while they match the kernel sources.
   cpu_baseline  the CPU oracle (single thread) timed on a bounded sample of
-                the same workload (see --cpu-*).
-  legs          (default workload) the sort-based ordering on the same graph
-                and both orderings with exact k-core pruning, one timed run
-                each, with the best density each reaches.
+                the same workload (see --cpu-*), and beside it (all_cores)
+                the oracle's multi-threaded timing build on every usable
+                host core, with the host's core count, CPU model and memory.
+  legs          (default workload) the sort-based ordering on the same graph,
+                both orderings with exact k-core pruning, and both with
+                approximate k-core pruning (c = 3/2), one timed run each,
+                with the best density each reaches.
   check         sum of loads = T*m, the best set's size, and, at the stored
                 sizes, equality with the oracle's stored results.
 
@@ -145,10 +148,11 @@ def main():
                          "request stream through the continuous-batching server; par: Pruning-and-Refining (exact "
                          "k-core pruning) on the R-MAT scale-22 graph")
     ap.add_argument("--rates", default="100,300,1000,3000,5000", help="serve: offered request rates (req/s)")
-    ap.add_argument("--window", type=float, default=3.0, help="serve: seconds of Poisson arrivals per rate")
+    ap.add_argument("--requests", type=int, default=2000, help="serve: measured requests per rate (after warm-up)")
+    ap.add_argument("--serve-warmup", type=int, default=200, help="serve: warm-up requests per rate (not measured)")
     ap.add_argument("--variant", default="peel", choices=["peel", "sort"])
     ap.add_argument("--select", type=int, default=-1, choices=[-1, 0, 1],
-                    help="PEEL select: -1 = the library's default (full list), 0 = full list, 1 = near list")
+                    help="PEEL select: -1 = by size (near list from 2^23 vertices), 0 = full list, 1 = near list")
     ap.add_argument("--count", type=int, default=4096, help="graphs in the batched mix")
     ap.add_argument("--plain-sample", type=int, default=256, help="graphs of the mix timed on the plain path")
     ap.add_argument("--T", type=int, default=None, help="iterations per step (default: 50 for c3, 20 otherwise)")
@@ -221,7 +225,7 @@ def bench_graph(args):
     g = dsg.Graph(ctx, o_dev, a_dev, t_cap=T, validate=False)
     g.set_kernel_timing(True)
     g.set_peel_select(args.select)
-    near = args.select == 1
+    near = args.select == 1 or (args.select < 0 and n >= (1 << 23))
     torch.cuda.synchronize()
 
     for w in range(args.warmup):
@@ -298,6 +302,8 @@ def bench_graph(args):
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kernel,
                      "avg_launch_ms": kern_ms / max(launches, 1), "launches": launches,
                      "alg_bytes_per_launch": alg_bytes, "alg_bytes_model": alg_model,
+                     "alg_bytes_split": "the dominant kernel's share of the per-iteration bytes; the rest of the "
+                                        "iteration's model is in the init and Algorithm 3 kernels (see iteration)",
                      "iteration": {"alg_bytes": it_bytes, "alg_bytes_model": it_model, "ms": iter_s * 1e3,
                                    "achieved": it_bytes / iter_s / 1e9,
                                    "frac": it_bytes / iter_s / 1e9 / HBM_PEAK_GBS}},
@@ -310,8 +316,9 @@ def bench_graph(args):
 
 
 def c3_legs(args, dsg, ctx, o_dev, a_dev, n, m, T):
-    """The sort-based ordering on the same graph, and both orderings with exact k-core pruning (Algorithm 1): one
-    run each after one warm-up iteration, with the best density each reaches."""
+    """The sort-based ordering on the same graph, both orderings with exact k-core pruning (Algorithm 1), and the
+    approximate-pruning frameworks (PaRApxSorting++, PaRApxGreedy++): one run each after one warm-up run of one
+    iteration, with the best density each reaches."""
     import torch
 
     out = {}
@@ -332,17 +339,22 @@ def c3_legs(args, dsg, ctx, o_dev, a_dev, n, m, T):
     out["sort"] = rec
     log(f"sort leg: {sec:.2f} s for T={T} ({2.0 * m * T / sec / 1e9:.1f} G edge-visits/s), best {e}/{v}")
     ws = torch.empty(dsg.par_workspace_bytes(n, int(a_dev.numel()), T) + 256, dtype=torch.uint8, device="cuda")
-    for variant, eps in (("sort", (0, 1)), ("peel", (1, 20))):
-        dsg.par_run(ctx, o_dev, a_dev, 1, eps, variant, validate=False, workspace=ws)
+    # PaRSorting++ / PaRGreedy++ (exact k-core pruning), then PaRApxSorting++ (approximate pruning only) and
+    # PaRApxGreedy++ (approximate, then exact pruning), with the ratio c = 3/2 of the paper's experiments
+    for name, variant, eps, prune in (("par_sort", "sort", (0, 1), "exact"), ("par_peel", "peel", (1, 20), "exact"),
+                                      ("par_apx_sort", "sort", (0, 1), "apx"),
+                                      ("par_apx_peel", "peel", (1, 20), "apx_exact")):
+        dsg.par_run(ctx, o_dev, a_dev, 1, eps, variant, validate=False, workspace=ws, prune=prune)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        r = dsg.par_run(ctx, o_dev, a_dev, T, eps, variant, validate=False, workspace=ws)
+        r = dsg.par_run(ctx, o_dev, a_dev, T, eps, variant, validate=False, workspace=ws, prune=prune)
         torch.cuda.synchronize()
         sec = time.perf_counter() - t1
-        out["par_" + variant] = {"seconds": sec, "best": list(r.best[:2]), "density": r.best[0] / r.best[1],
-                                 "k_max": r.kmax, "first_cut": r.sizes[0] if r.sizes else None,
-                                 "last_cut": r.final_size}
-        log(f"par {variant} leg: {sec:.2f} s for T={T}, best {r.best[0]}/{r.best[1]}, k_max {r.kmax}, "
+        out[name] = {"seconds": sec, "best": list(r.best[:2]), "density": r.best[0] / r.best[1],
+                     "k_max": r.kmax, "first_cut": r.sizes[0] if r.sizes else None, "last_cut": r.final_size}
+        if prune != "exact":
+            out[name]["apx"] = {"khat_max": r.apx_kmax, "level": r.apx_level, "cut": r.apx_size}
+        log(f"{name} leg: {sec:.2f} s for T={T}, best {r.best[0]}/{r.best[1]}, k_max {r.kmax}, "
             f"cuts {r.sizes[0] if r.sizes else None} -> {r.final_size}")
     del ws
     return out
@@ -534,9 +546,9 @@ def bench_serve(args):
     served_sample = {}
     try:
         for rate in [float(r) for r in args.rates.split(",")]:
-            W = args.window
-            N = max(1, int(round(rate * W)))
+            N = args.serve_warmup + args.requests
             arrivals = np.cumsum(rng.exponential(1.0 / rate, N))
+            W = float(arrivals[-1])
             plan = [((gids_big[rng.integers(4)] if rng.random() < 0.02 else gids_mix[rng.integers(256)]),
                      int(rng.integers(5, 51)), (1, 20) if rng.random() < 0.5 else (1, 10)) for _ in range(N)]
             lat = np.zeros(N)
@@ -564,12 +576,17 @@ def bench_serve(args):
                         served_sample[plan[j]] = res
                 if time.perf_counter() - start > 240:
                     raise RuntimeError(f"rate {rate}: stream did not drain in 240 s ({done_cnt}/{N} done)")
-            w0, w1 = 0.25 * W, W
-            thr = float(np.count_nonzero((tdone > w0) & (tdone <= w1))) / (w1 - w0)
-            rec = {"rate": rate, "requests": N, "window_s": W, "graphs_per_s": thr, "drained_s": last_done,
-                   "p50_ms": float(np.percentile(lat, 50) * 1e3),
-                   "p99_ms": float(np.percentile(lat, 99) * 1e3),
-                   "p99_small_ms": float(np.percentile(lat[[p[0] not in gids_big for p in plan]], 99) * 1e3)}
+            # measured: the requests after the warm-up ones; throughput over the span of their arrivals
+            meas = np.arange(args.serve_warmup, N)
+            w0, w1 = float(arrivals[args.serve_warmup]), W
+            thr = float(np.count_nonzero((tdone > w0) & (tdone <= w1))) / max(w1 - w0, 1e-9)
+            small = np.array([plan[j][0] not in gids_big for j in meas])
+            lm = lat[meas]
+            rec = {"rate": rate, "requests": int(len(meas)), "warmup_requests": args.serve_warmup,
+                   "arrival_span_s": W, "graphs_per_s": thr, "drained_s": last_done,
+                   "p50_ms": float(np.percentile(lm, 50) * 1e3),
+                   "p99_ms": float(np.percentile(lm, 99) * 1e3),
+                   "p99_small_ms": float(np.percentile(lm[small], 99) * 1e3) if small.any() else None}
             results.append(rec)
             log(f"rate {rate:6.0f}/s ({N} requests): {thr:8.1f} graphs/s served, p50 {rec['p50_ms']:.1f} ms, "
                 f"p99 {rec['p99_ms']:.1f} ms (p99 without the R-MAT-20 requests {rec['p99_small_ms']:.1f} ms), "
@@ -607,8 +624,9 @@ def bench_serve(args):
         "dtype": "int32",
         "data": "synthetic",
         "config": {"workload": f"Poisson stream: 98% batched-mix graphs, 2% R-MAT scale 20; T~U{{5..50}}, "
-                               f"eps in {{1/20, 1/10}}; HBM budget {budget / 1e9:.0f} GB; {args.window:.0f} s of "
-                               f"arrivals per rate; schedule cfg={cfg} blocks/CU={bpc}"},
+                               f"eps in {{1/20, 1/10}}; HBM budget {budget / 1e9:.0f} GB; {args.requests} measured "
+                               f"requests per rate after {args.serve_warmup} warm-up ones; schedule cfg={cfg} "
+                               f"blocks/CU={bpc}"},
         "rates": results,
         "plain": {"graphs_per_s": plain_gps, "requests": len(plan)},
         "served_over_plain": best["graphs_per_s"] / plain_gps,

@@ -222,7 +222,7 @@ dsg_status dsg_set_sort_tuning(dsg_graph* g, int32_t coarse_ranks);
  *       decrement takes them to B or below.  The positions are sorted by round
  *       after the loop.  Pays off where many rounds peel few vertices out of
  *       many alive ones (large sparse graphs).
- *  -1 = the default, which is the full list.
+ *  -1 = near list from n >= 2^23 vertices, full list below (the default).
  * Kept across dsg_reset.  DSG_EINVAL for other values or a NULL graph. */
 dsg_status dsg_set_peel_select(dsg_graph* g, int32_t mode);
 

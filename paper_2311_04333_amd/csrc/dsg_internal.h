@@ -40,13 +40,13 @@ constexpr int BKT_MAX_NR = 2048;
 constexpr int BKT_CNT_BITS = 12;  // bucket entry = local id << 12 | (count - 1); count <= PEEL_CH
 constexpr long long BKT_DEFAULT_MIN_E = 1LL << 20;
 // Near-list select (k_peel_rounds_near): the near bound is B = thr * 5/4 + 1
-// at each full-list round.  Off by default (NEAR_DEFAULT_MIN_N = 0): measured
-// on the 40M-vertex Chung-Lu graph it scans far fewer entries but runs the
-// round loop no faster (53.1 against 52.5 ms per iteration), and on R-MAT
-// scale 22 it is slower (6.0 against 4.6 ms).
+// at each full-list round.  The default from 2^23 vertices: on the 40M-vertex
+// Chung-Lu graph its round loop takes 48.9 ms per iteration against 53.2 ms for
+// the full-list select; on R-MAT scale 22 (2^22 vertices) it is slower (5.1
+// against 4.6 ms).
 constexpr int NEAR_B_NUM = 5;
 constexpr int NEAR_B_DEN = 4;
-constexpr int NEAR_DEFAULT_MIN_N = 0;
+constexpr int NEAR_DEFAULT_MIN_N = 1 << 23;
 // SORT compares coarse ranks first once the position table (4n bytes) no
 // longer fits an XCD's L2.  The 4-bit table (n/2 bytes) fits it up to 2^22
 // vertices; above that both tables live in the MALL, where the 8x smaller

@@ -662,6 +662,7 @@ struct XStage {
     }
 };
 
+template <int BLK>
 struct PeelEdgeOp {
     const unsigned int* st2;
     int* prio;
@@ -718,13 +719,13 @@ struct PeelEdgeOp {
             flush_to_buckets();
             return;
         }
-        constexpr int PER = DEC_SLOTS / PEEL_BLK;
-        static_assert(PER * PEEL_BLK == DEC_SLOTS, "slots must be a multiple of the block");
+        constexpr int PER = DEC_SLOTS / BLK;
+        static_assert(PER * BLK == DEC_SLOTS, "slots must be a multiple of the block");
         lds_barrier();
         int key[PER], c[PER], old[PER];
 #pragma unroll
         for (int k = 0; k < PER; k++) {
-            const int slot = threadIdx.x + k * PEEL_BLK;
+            const int slot = threadIdx.x + k * BLK;
             key[k] = dec->key[slot];
             c[k] = dec->cnt[slot];
         }
@@ -735,7 +736,7 @@ struct PeelEdgeOp {
         for (int k = 0; k < PER; k++) {
             if (key[k] != DEC_EMPTY) {
                 lmin = min(lmin, (unsigned int)(old[k] - c[k]));
-                const int slot = threadIdx.x + k * PEEL_BLK;
+                const int slot = threadIdx.x + k * BLK;
                 dec->key[slot] = DEC_EMPTY;
                 dec->cnt[slot] = 0;
             }
@@ -752,18 +753,18 @@ struct PeelEdgeOp {
     // holds at most one entry per decrement of its vertices in a round, so
     // its capacity is the range's degree sum: it starts at off[j << rshift].
     __device__ __forceinline__ void flush_to_buckets() {
-        constexpr int PER = DEC_SLOTS / PEEL_BLK;
+        constexpr int PER = DEC_SLOTS / BLK;
         lds_barrier();
         int key[PER], c[PER], rk[PER];
 #pragma unroll
         for (int k = 0; k < PER; k++) {
-            const int slot = threadIdx.x + k * PEEL_BLK;
+            const int slot = threadIdx.x + k * BLK;
             key[k] = dec->key[slot];
             c[k] = dec->cnt[slot];
             rk[k] = key[k] != DEC_EMPTY ? atomicAdd(&bcnt[key[k] >> rshift], 1) : 0;
         }
         lds_barrier();
-        for (int j = threadIdx.x; j < nr; j += PEEL_BLK) {
+        for (int j = threadIdx.x; j < nr; j += BLK) {
             const int cj = bcnt[j];
             if (cj) {
                 const int lo = off[j << rshift];
@@ -785,7 +786,7 @@ struct PeelEdgeOp {
                 const int j = key[k] >> rshift;
                 const int b = bbase[j];
                 if (b >= 0) bkt[b + rk[k]] = ((key[k] - (j << rshift)) << BKT_CNT_BITS) | (c[k] - 1);
-                const int slot = threadIdx.x + k * PEEL_BLK;
+                const int slot = threadIdx.x + k * BLK;
                 dec->key[slot] = DEC_EMPTY;
                 dec->cnt[slot] = 0;
             }
@@ -1072,8 +1073,8 @@ __global__ __launch_bounds__(PEEL_BLK, PEEL_BLOCKS_PER_CU) void k_peel_rounds(Pe
         const int K = (int)(f >> FCNT_SHIFT);
         const long long E = (long long)(f & FCNT_MASK);
         const bool bucket = a.nr > 0 && E >= a.bkt_min_e;
-        PeelEdgeOp op{a.st2, a.prio, r, lmin, ctl, &lds.m.dec, bucket, a.rshift, a.nr, a.n, a.off, a.bkt, a.bfill,
-                      lds.bcnt, lds.bbase};
+        PeelEdgeOp<PEEL_BLK> op{a.st2, a.prio, r, lmin, ctl, &lds.m.dec, bucket, a.rshift, a.nr, a.n, a.off, a.bkt,
+                                a.bfill, lds.bcnt, lds.bbase};
         if (E >= a.coarse_min_e)
             sweep_chunks<PEEL_BLK, PEEL_CH, PEEL_CH / PEEL_MARK>(K, E, ivr, a.ie, a.ir, a.cfirst, a.clast, a.adj,
                                                                  a.inc, op, lds.m.sw, blockIdx.x, nblocks,
@@ -1203,16 +1204,25 @@ __global__ __launch_bounds__(PEEL_BLK, PEEL_BLOCKS_PER_CU) void k_peel_rounds(Pe
 // segment (at its slice's start), and per-block tables of segment starts and
 // lengths map virtual positions.
 
-// LDS map of a segment table tab[start | len][PEEL_BLK] with nseg segments;
+// 512 threads per block: at 1024 the kernel spilled about 45 VGPRs and its
+// sweep paid for it (53.1 ms per iteration on the 40M-vertex Chung-Lu graph);
+// at 512 it spills none (48.9 ms).  Four list entries per thread per tile.
+constexpr int NEAR_BLK = 512;
+constexpr int NEAR_SEL_U = 4;
+constexpr int SEG_STRIDE = PEEL_BLK;  // segment tables hold PEEL_BLK entries per field
+static_assert(NEAR_BLK * NEAR_SEL_U < (1 << 16), "tile counts must fit their packed fields");
+static_assert(DEC_SLOTS % NEAR_BLK == 0, "slots must be a multiple of the block");
+
+// LDS map of a segment table tab[start | len][SEG_STRIDE] with nseg segments;
 // returns the total length.  Reads of `tab` must follow the grid barrier
 // that published it.  Contains block barriers.
 __device__ __forceinline__ long long build_map(const int* __restrict__ tab, int nseg, int* spref, int* sstart,
                                                unsigned long long* shs) {
     const int j = (int)threadIdx.x;
-    const int len = j < nseg ? tab[PEEL_BLK + j] : 0;
+    const int len = j < nseg ? tab[SEG_STRIDE + j] : 0;
     const int st = j < nseg ? tab[j] : 0;
     unsigned long long tot;
-    const unsigned long long ex = block_excl_scan<PEEL_BLK>((unsigned long long)(unsigned int)len, &tot, shs);
+    const unsigned long long ex = block_excl_scan<NEAR_BLK>((unsigned long long)(unsigned int)len, &tot, shs);
     if (j < nseg) {
         spref[j] = (int)ex;
         sstart[j] = st;
@@ -1244,14 +1254,14 @@ __device__ __forceinline__ NearPass near_classify(const PeelArgs& a, int r, int 
                                                   const int* __restrict__ Xin, long long mtot, int beg, int end,
                                                   long long thr, long long B, int* __restrict__ Fout,
                                                   int* __restrict__ Nout, const int* spref, const int* sstart,
-                                                  unsigned long long* shs, int (&u)[SEL_U], bool (&fr)[SEL_U],
-                                                  int (&o0)[SEL_U], int (&o1)[SEL_U]) {
-    constexpr int TILE = PEEL_BLK * SEL_U;
+                                                  unsigned long long* shs, int (&u)[NEAR_SEL_U], bool (&fr)[NEAR_SEL_U],
+                                                  int (&o0)[NEAR_SEL_U], int (&o1)[NEAR_SEL_U]) {
+    constexpr int TILE = NEAR_BLK * NEAR_SEL_U;
     const int nseg = (int)gridDim.x;
     NearPass P{0, 0, 0, 0, 0ull, 0xFFFFFFFFu, end - beg <= TILE};
     int sj = 0;
     if (kind != 0 && end > beg) {
-        const int first = beg + (int)threadIdx.x * SEL_U;
+        const int first = beg + (int)threadIdx.x * NEAR_SEL_U;
         int lo = 0, hi = nseg - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
@@ -1266,24 +1276,24 @@ __device__ __forceinline__ NearPass near_classify(const PeelArgs& a, int r, int 
         while (sj + 1 < nseg && spref[sj + 1] <= idx) sj++;
         return Lin[sstart[sj] + (idx - spref[sj])];
     };
-    int un[SEL_U];
+    int un[NEAR_SEL_U];
 #pragma unroll
-    for (int k = 0; k < SEL_U; k++) {
+    for (int k = 0; k < NEAR_SEL_U; k++) {
         u[k] = -1;
         fr[k] = false;
-        un[k] = entry(beg + (int)threadIdx.x * SEL_U + k);
+        un[k] = entry(beg + (int)threadIdx.x * NEAR_SEL_U + k);
     }
     for (int base = beg; base < end; base += TILE) {
-        int pu[SEL_U];
+        int pu[NEAR_SEL_U];
 #pragma unroll
-        for (int k = 0; k < SEL_U; k++) {
+        for (int k = 0; k < NEAR_SEL_U; k++) {
             u[k] = un[k];
-            un[k] = entry(base + TILE + (int)threadIdx.x * SEL_U + k);
+            un[k] = entry(base + TILE + (int)threadIdx.x * NEAR_SEL_U + k);
         }
 #pragma unroll
-        for (int k = 0; k < SEL_U; k++) pu[k] = u[k] >= 0 ? a.prio[u[k]] : -1;
+        for (int k = 0; k < NEAR_SEL_U; k++) pu[k] = u[k] >= 0 ? a.prio[u[k]] : -1;
 #pragma unroll
-        for (int k = 0; k < SEL_U; k++) {
+        for (int k = 0; k < NEAR_SEL_U; k++) {
             fr[k] = pu[k] >= 0 && (long long)pu[k] <= thr;
             o0[k] = fr[k] ? a.off[u[k]] : 0;
             o1[k] = fr[k] ? a.off[u[k] + 1] : 0;
@@ -1291,7 +1301,7 @@ __device__ __forceinline__ NearPass near_classify(const PeelArgs& a, int r, int 
         // packed per-thread counts: [near: 0-15][full-list survivors: 16-31][frontier: 32-47][items: 48-63]
         unsigned long long val = 0;
 #pragma unroll
-        for (int k = 0; k < SEL_U; k++) {
+        for (int k = 0; k < NEAR_SEL_U; k++) {
             if (pu[k] < 0) continue;  // no entry, or peeled in an earlier round
             if (fr[k]) {
                 a.rnd[u[k]] = r;
@@ -1310,12 +1320,12 @@ __device__ __forceinline__ NearPass near_classify(const PeelArgs& a, int r, int 
             }
         }
         unsigned long long tot;
-        const unsigned long long ex = block_excl_scan<PEEL_BLK>(val, &tot, shs);
+        const unsigned long long ex = block_excl_scan<NEAR_BLK>(val, &tot, shs);
         int nr_ = beg + P.n_run + (int)(ex & 0xFFFFull);
         int sr_ = beg + P.s_run + (int)((ex >> 16) & 0xFFFFull);
         int fr_ = end - 1 - (P.f_run + (int)((ex >> 32) & 0xFFFFull));
 #pragma unroll
-        for (int k = 0; k < SEL_U; k++) {
+        for (int k = 0; k < NEAR_SEL_U; k++) {
             if (pu[k] < 0) continue;
             if (fr[k]) {
                 Nout[fr_--] = u[k];
@@ -1333,10 +1343,10 @@ __device__ __forceinline__ NearPass near_classify(const PeelArgs& a, int r, int 
 }
 
 template <bool MONO>
-__global__ __launch_bounds__(PEEL_BLK, PEEL_BLOCKS_PER_CU) void k_peel_rounds_near(PeelArgs a) {
+__global__ __launch_bounds__(NEAR_BLK, 1) void k_peel_rounds_near(PeelArgs a) {
     __shared__ PeelLds lds;
-    __shared__ unsigned long long shs[PEEL_BLK / WAVE];
-    __shared__ unsigned int shm[PEEL_BLK / WAVE];
+    __shared__ unsigned long long shs[NEAR_BLK / WAVE];
+    __shared__ unsigned int shm[NEAR_BLK / WAVE];
     __shared__ unsigned long long s_fbase;
     __shared__ int s_chunk;
     __shared__ long long s_ntot;  // entries in the near list's segments (map built at the previous round's end)
@@ -1346,11 +1356,11 @@ __global__ __launch_bounds__(PEEL_BLK, PEEL_BLOCKS_PER_CU) void k_peel_rounds_ne
     GridSync* gs = a.gs;
     const unsigned int nblocks = gridDim.x;
     const long long q = a.eps_den, p = a.eps_num;
-    for (int slot = threadIdx.x; slot < DEC_SLOTS; slot += PEEL_BLK) {
+    for (int slot = threadIdx.x; slot < DEC_SLOTS; slot += NEAR_BLK) {
         lds.m.dec.key[slot] = DEC_EMPTY;
         lds.m.dec.cnt[slot] = 0;
     }
-    for (int j = threadIdx.x; j < BKT_MAX_NR; j += PEEL_BLK) lds.bcnt[j] = 0;
+    for (int j = threadIdx.x; j < BKT_MAX_NR; j += NEAR_BLK) lds.bcnt[j] = 0;
     if (threadIdx.x == 0) {
         s_ntot = 0;
         s_xn = 0;
@@ -1402,23 +1412,23 @@ __global__ __launch_bounds__(PEEL_BLK, PEEL_BLOCKS_PER_CU) void k_peel_rounds_ne
         int* __restrict__ Nout = (r & 1) ? a.N0 : a.N1;
         const int* __restrict__ Xin = (r & 1) ? a.X1 : a.X0;
         int* __restrict__ Xout = (r & 1) ? a.X0 : a.X1;
-        int* __restrict__ segNout = a.segN + (r & 1) * 2 * PEEL_BLK;
+        int* __restrict__ segNout = a.segN + (r & 1) * 2 * SEG_STRIDE;
         if (r > 0) {
             // the previous round's frontier is peeled now: clear its state bits
             const int* __restrict__ ivp = (r & 1) ? a.iv0 : a.iv1;
             const int Kp = (int)(ld_agent_u64(&ctl->fcnt[(r - 1) & 3]) >> FCNT_SHIFT);
-            for (int k = blockIdx.x * PEEL_BLK + threadIdx.x; k < Kp; k += nblocks * PEEL_BLK) {
+            for (int k = blockIdx.x * NEAR_BLK + threadIdx.x; k < Kp; k += nblocks * NEAR_BLK) {
                 const int w = ivp[k];
                 atomicAnd(&a.st2[w >> 4], ~(3u << ((w & 15) * 2)));
             }
         }
-        int u[SEL_U], o0[SEL_U], o1[SEL_U];
-        bool fr[SEL_U];
+        int u[NEAR_SEL_U], o0[NEAR_SEL_U], o1[NEAR_SEL_U];
+        bool fr[NEAR_SEL_U];
         NearPass P;
         int beg, end;
         if (full) {
             long long ftot = a.n;
-            if (!f_all) ftot = build_map(a.segF + fpar * 2 * PEEL_BLK, (int)nblocks, lds.spref, lds.sstart, shs);
+            if (!f_all) ftot = build_map(a.segF + fpar * 2 * SEG_STRIDE, (int)nblocks, lds.spref, lds.sstart, shs);
             if (!exact) {
                 // N ran empty: compact F into the other buffer and find the exact minimum first
                 const long long per = (ftot + nblocks - 1) / nblocks;
@@ -1428,17 +1438,17 @@ __global__ __launch_bounds__(PEEL_BLK, PEEL_BLOCKS_PER_CU) void k_peel_rounds_ne
                 int* Fout = fpar ? a.L0 : a.L1;
                 P = near_classify<true>(a, r, f_all ? 0 : 1, Fin, nullptr, ftot, beg, end, -2, -1, Fout, Nout,
                                         lds.spref, lds.sstart, shs, u, fr, o0, o1);
-                int* segFout = a.segF + (fpar ^ 1) * 2 * PEEL_BLK;
+                int* segFout = a.segF + (fpar ^ 1) * 2 * SEG_STRIDE;
                 if (threadIdx.x == 0) {
                     segFout[blockIdx.x] = beg;
-                    segFout[PEEL_BLK + blockIdx.x] = P.s_run;
+                    segFout[SEG_STRIDE + blockIdx.x] = P.s_run;
                 }
-                const unsigned int bmin = block_min<PEEL_BLK>(P.lmin, shm);
+                const unsigned int bmin = block_min<NEAR_BLK>(P.lmin, shm);
                 if (threadIdx.x == 0 && bmin != 0xFFFFFFFFu) atomicMin(&ctl->mn2[slot], bmin);
                 grid_sync(bar);
                 fpar ^= 1;
                 f_all = false;
-                ftot = build_map(a.segF + fpar * 2 * PEEL_BLK, (int)nblocks, lds.spref, lds.sstart, shs);
+                ftot = build_map(a.segF + fpar * 2 * SEG_STRIDE, (int)nblocks, lds.spref, lds.sstart, shs);
                 mn = ld_agent(&ctl->mn2[slot]);
                 thr = ((q + p) * (long long)mn) / q;
                 if (MONO && r > 0) thr = max(thr, thr_prev);
@@ -1453,10 +1463,10 @@ __global__ __launch_bounds__(PEEL_BLK, PEEL_BLOCKS_PER_CU) void k_peel_rounds_ne
                 int* Fout = fpar ? a.L0 : a.L1;
                 P = near_classify<true>(a, r, f_all ? 0 : 1, Fin, nullptr, ftot, beg, end, thr, B, Fout, Nout,
                                         lds.spref, lds.sstart, shs, u, fr, o0, o1);
-                int* segFout = a.segF + (fpar ^ 1) * 2 * PEEL_BLK;
+                int* segFout = a.segF + (fpar ^ 1) * 2 * SEG_STRIDE;
                 if (threadIdx.x == 0) {
                     segFout[blockIdx.x] = beg;
-                    segFout[PEEL_BLK + blockIdx.x] = P.s_run;
+                    segFout[SEG_STRIDE + blockIdx.x] = P.s_run;
                 }
                 fpar ^= 1;
                 f_all = false;
@@ -1474,26 +1484,26 @@ __global__ __launch_bounds__(PEEL_BLK, PEEL_BLOCKS_PER_CU) void k_peel_rounds_ne
         thr_prev = thr;
         if (a.rmin && blockIdx.x == 0 && threadIdx.x == 0) a.rmin[r] = (int)min(thr, 0x7FFFFFFFLL);
         {
-            const unsigned long long eb = block_sum<PEEL_BLK>(P.edges, shs);
+            const unsigned long long eb = block_sum<NEAR_BLK>(P.edges, shs);
             const unsigned long long packed = ((unsigned long long)P.i_run << FCNT_SHIFT) | eb;
             if (threadIdx.x == 0) {
                 s_fbase = packed ? atomicAdd(&ctl->fcnt[slot], packed) : 0ull;
                 if (P.f_run) atomicAdd(&ctl->pcnt[slot], (unsigned int)P.f_run);
                 segNout[blockIdx.x] = beg;
-                segNout[PEEL_BLK + blockIdx.x] = P.n_run;
+                segNout[SEG_STRIDE + blockIdx.x] = P.n_run;
             }
             __syncthreads();  // also orders the tail writes before the reads below
         }
         unsigned long long fb = s_fbase;
         // item pass: the frontier vertices with edges, from registers (one
         // tile) or from the tail of the block's near slice
-        constexpr int TILE = PEEL_BLK * SEL_U;
+        constexpr int TILE = NEAR_BLK * NEAR_SEL_U;
         const int item_end = P.one_tile ? (end > beg ? 1 : 0) : P.f_run;
         for (int base = 0; base < item_end; base += TILE) {
             if (!P.one_tile) {
 #pragma unroll
-                for (int k = 0; k < SEL_U; k++) {
-                    const int j = base + (int)threadIdx.x * SEL_U + k;
+                for (int k = 0; k < NEAR_SEL_U; k++) {
+                    const int j = base + (int)threadIdx.x * NEAR_SEL_U + k;
                     u[k] = j < P.f_run ? Nout[end - 1 - j] : -1;
                     fr[k] = u[k] >= 0;
                     o0[k] = fr[k] ? a.off[u[k]] : 0;
@@ -1502,16 +1512,16 @@ __global__ __launch_bounds__(PEEL_BLK, PEEL_BLOCKS_PER_CU) void k_peel_rounds_ne
             }
             unsigned long long val = 0;
 #pragma unroll
-            for (int k = 0; k < SEL_U; k++) {
+            for (int k = 0; k < NEAR_SEL_U; k++) {
                 const int d = o1[k] - o0[k];
                 if (fr[k] && d > 0) val += (1ull << TITEM_SHIFT) + (unsigned long long)d;
             }
             unsigned long long tot;
-            const unsigned long long ex = block_excl_scan<PEEL_BLK>(val, &tot, shs);
+            const unsigned long long ex = block_excl_scan<NEAR_BLK>(val, &tot, shs);
             unsigned long long it = (fb >> FCNT_SHIFT) + (ex >> TITEM_SHIFT);
             unsigned long long ed = (fb & FCNT_MASK) + (ex & 0xFFFFFFFFull);
 #pragma unroll
-            for (int k = 0; k < SEL_U; k++) {
+            for (int k = 0; k < NEAR_SEL_U; k++) {
                 const int d = o1[k] - o0[k];
                 if (fr[k] && d > 0) {
                     ivr[it] = u[k];
@@ -1530,18 +1540,18 @@ __global__ __launch_bounds__(PEEL_BLK, PEEL_BLOCKS_PER_CU) void k_peel_rounds_ne
         const int K = (int)(f >> FCNT_SHIFT);
         const long long E = (long long)(f & FCNT_MASK);
         const bool bucket = a.nr > 0 && E >= a.bkt_min_e;
-        PeelEdgeOp op{a.st2, a.prio, r, P.lmin, ctl, &lds.m.dec, bucket, a.rshift, a.nr, a.n, a.off, a.bkt, a.bfill,
+        PeelEdgeOp<NEAR_BLK> op{a.st2, a.prio, r, P.lmin, ctl, &lds.m.dec, bucket, a.rshift, a.nr, a.n, a.off, a.bkt, a.bfill,
                       lds.bcnt, lds.bbase};
         // crossings are staged in lds.bbase, which only the bucket flush uses (as scratch)
         const XStage xst{lds.bbase, &s_xn, Xout, &ctl->xcnt[nslot], a.n, ctl};
         op.nearB = (int)B;
         op.xst = xst;
         if (E >= a.coarse_min_e)
-            sweep_chunks<PEEL_BLK, PEEL_CH, PEEL_CH / PEEL_MARK>(K, E, ivr, a.ie, a.ir, a.cfirst, a.clast, a.adj,
+            sweep_chunks<NEAR_BLK, PEEL_CH, PEEL_CH / PEEL_MARK>(K, E, ivr, a.ie, a.ir, a.cfirst, a.clast, a.adj,
                                                                  a.inc, op, lds.m.sw, blockIdx.x, nblocks,
                                                                  &ctl->cnext[slot], &s_chunk);
         else
-            sweep_chunks<PEEL_BLK, PEEL_MARK, 1>(K, E, ivr, a.ie, a.ir, a.cfirst, a.clast, a.adj, a.inc, op,
+            sweep_chunks<NEAR_BLK, PEEL_MARK, 1>(K, E, ivr, a.ie, a.ir, a.cfirst, a.clast, a.adj, a.inc, op,
                                                  lds.m.sw, blockIdx.x, nblocks, &ctl->cnext[slot], &s_chunk);
         unsigned int rmin = op.lmin;
         if (bucket) {
@@ -1550,7 +1560,7 @@ __global__ __launch_bounds__(PEEL_BLK, PEEL_BLOCKS_PER_CU) void k_peel_rounds_ne
             // crosses B appends its vertex to the crossing list
             const int R = 1 << a.rshift;
             if ((int)blockIdx.x < a.nr) {
-                for (int i = threadIdx.x; i < R; i += PEEL_BLK) lds.dense[i] = 0;
+                for (int i = threadIdx.x; i < R; i += NEAR_BLK) lds.dense[i] = 0;
                 lds_barrier();
             }
             for (int j = blockIdx.x; j < a.nr; j += nblocks) {
@@ -1558,13 +1568,13 @@ __global__ __launch_bounds__(PEEL_BLK, PEEL_BLOCKS_PER_CU) void k_peel_rounds_ne
                 const int v1 = min(a.n, v0 + R);
                 const int lo = a.off[v0];
                 const int cnt = min((int)ld_agent(&a.bfill[j]), a.off[v1] - lo);
-                for (int i = threadIdx.x; i < cnt; i += PEEL_BLK) {
+                for (int i = threadIdx.x; i < cnt; i += NEAR_BLK) {
                     const unsigned int e = (unsigned int)a.bkt[lo + i];
                     const unsigned int li = e >> BKT_CNT_BITS;
                     if (li < (unsigned int)(v1 - v0)) atomicAdd(&lds.dense[li], (int)(e & ((1u << BKT_CNT_BITS) - 1)) + 1);
                 }
                 lds_barrier();
-                for (int base = 0; base < cnt; base += PEEL_BLK) {
+                for (int base = 0; base < cnt; base += NEAR_BLK) {
                     const int i = base + (int)threadIdx.x;
                     bool x = false;
                     int w = 0;
@@ -1588,26 +1598,26 @@ __global__ __launch_bounds__(PEEL_BLK, PEEL_BLOCKS_PER_CU) void k_peel_rounds_ne
                 lds_barrier();
             }
             if ((int)blockIdx.x < a.nr) {
-                for (int t = threadIdx.x; t < DEC_SLOTS; t += PEEL_BLK) {
+                for (int t = threadIdx.x; t < DEC_SLOTS; t += NEAR_BLK) {
                     lds.m.dec.key[t] = DEC_EMPTY;
                     lds.m.dec.cnt[t] = 0;
                 }
             }
         }
         xst.flush(&s_xbase);
-        const unsigned int bmin = block_min<PEEL_BLK>(rmin, shm);
+        const unsigned int bmin = block_min<NEAR_BLK>(rmin, shm);
         if (threadIdx.x == 0 && bmin != 0xFFFFFFFFu) atomicMin(&ctl->mn[nslot], bmin);
         {
             // the near list's segment table was published by the grid sync
             // after the select: map it between the halves of the round-end
             // barrier (the crossings' count is read after it)
             const int j = (int)threadIdx.x;
-            const int len = j < (int)nblocks ? segNout[PEEL_BLK + j] : 0;
+            const int len = j < (int)nblocks ? segNout[SEG_STRIDE + j] : 0;
             const int st = j < (int)nblocks ? segNout[j] : 0;
             grid_arrive(bar);
             unsigned long long tot;
             const unsigned long long ex =
-                block_excl_scan<PEEL_BLK>((unsigned long long)(unsigned int)len, &tot, shs);
+                block_excl_scan<NEAR_BLK>((unsigned long long)(unsigned int)len, &tot, shs);
             if (j < (int)nblocks) {
                 lds.spref[j] = (int)ex;
                 lds.sstart[j] = st;
@@ -2547,14 +2557,15 @@ hipError_t enqueue_iter_peel(const GraphDev& g, int slot, int eps_num, int eps_d
     a.segN = g.segN;
     a.near_num = NEAR_B_NUM;
     a.near_den = NEAR_B_DEN;
-    if (peel_grid > PEEL_BLK) return hipErrorInvalidValue;  // one segment per thread of a block
+    // one segment per thread of a block (segment tables hold PEEL_BLK entries)
+    if (peel_grid > (near ? NEAR_BLK : PEEL_BLK)) return hipErrorInvalidValue;
     void* args[] = {&a};
     if (ev_a && (e = hipEventRecord(ev_a, s)) != hipSuccess) return e;
     const void* kern = near ? (mono ? reinterpret_cast<const void*>(k_peel_rounds_near<true>)
                                     : reinterpret_cast<const void*>(k_peel_rounds_near<false>))
                             : (mono ? reinterpret_cast<const void*>(k_peel_rounds<true>)
                                     : reinterpret_cast<const void*>(k_peel_rounds<false>));
-    e = hipLaunchCooperativeKernel(kern, dim3(peel_grid), dim3(PEEL_BLK), args, 0, s);
+    e = hipLaunchCooperativeKernel(kern, dim3(peel_grid), dim3(near ? NEAR_BLK : PEEL_BLK), args, 0, s);
     if (e != hipSuccess) return e;
     if (ev_b && (e = hipEventRecord(ev_b, s)) != hipSuccess) return e;
     if (near) {
