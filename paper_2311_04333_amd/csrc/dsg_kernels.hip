@@ -406,7 +406,11 @@ struct SweepLds {
 // (charges, aggregated decrements) overlap the next chunk's loads.  The
 // markers may be finer than the chunk: MS markers per chunk, so chunk c
 // starts at item cfirst[c * MS] and ends at item clast[c * MS + MS - 1].
-template <int BLK, int CH, int MS, class Op, class Lds>
+// With PF > 0 (dynamic chunks only), the first PF * BLK items of the block's
+// next chunk, and its item range, are loaded into registers while the current
+// chunk is processed, which takes two dependent memory round trips (markers,
+// then items) off the start of every chunk.
+template <int BLK, int CH, int MS, class Op, class Lds, int PF = 0>
 __device__ __forceinline__ void sweep_chunks(int K, long long E, const int* __restrict__ iv, const int* __restrict__ ie,
                                              const int* __restrict__ ir, const int* __restrict__ cfirst,
                                              const int* __restrict__ clast, const int* __restrict__ adj,
@@ -423,11 +427,24 @@ __device__ __forceinline__ void sweep_chunks(int K, long long E, const int* __re
         c = *s_chunk;
         lds_barrier();
     }
+    // item range of chunk cc: [k0, k1]
+    auto range = [&](long long cc, int& k0, int& k1) {
+        k0 = cfirst[cc * MS];
+        k1 = (cc + 1 < nchunks) ? clast[cc * MS + MS - 1] : K - 1;
+    };
+    int pk0 = 0, pk1 = -1;       // prefetched chunk's item range (valid when pf_ok)
+    bool pf_ok = false;
+    int pv[PF > 0 ? PF : 1], pe[PF > 0 ? PF : 1], pr[PF > 0 ? PF : 1];
     for (; c < nchunks;) {
         const long long x0 = c * CH;
         const long long x1 = min(E, x0 + CH);
-        const int k0 = cfirst[c * MS];
-        const int k1 = (c + 1 < nchunks) ? clast[c * MS + MS - 1] : K - 1;
+        int k0, k1;
+        if (PF > 0 && pf_ok) {
+            k0 = pk0;
+            k1 = pk1;
+        } else {
+            range(c, k0, k1);
+        }
         const int nitems = k1 - k0 + 1;
         if (nitems < 1 || nitems > CH) {
             // impossible when every item has an edge in the chunk; refuse to
@@ -437,7 +454,22 @@ __device__ __forceinline__ void sweep_chunks(int K, long long E, const int* __re
         }
         // grab the next chunk while this one is processed
         if (cnext && threadIdx.x == 0) *s_chunk = (int)atomicAdd(cnext, 1u);
-        for (int j = threadIdx.x; j < nitems; j += BLK) {
+        int jstart = 0;
+        if (PF > 0 && pf_ok) {
+#pragma unroll
+            for (int q = 0; q < (PF > 0 ? PF : 1); q++) {
+                const int j = (int)threadIdx.x + q * BLK;
+                if (j < nitems) {
+                    s.fe[j] = pe[q];
+                    s.rb[j] = pr[q];
+                    s.v[j] = pv[q];
+                    s.cnt[j] = 0;
+                    op.stage_item(j, pv[q]);
+                }
+            }
+            jstart = (PF > 0 ? PF : 1) * BLK;
+        }
+        for (int j = jstart + (int)threadIdx.x; j < nitems; j += BLK) {
             const int v = iv[k0 + j];
             s.fe[j] = ie[k0 + j];
             s.rb[j] = ir[k0 + j];
@@ -446,6 +478,14 @@ __device__ __forceinline__ void sweep_chunks(int K, long long E, const int* __re
             op.stage_item(j, v);
         }
         lds_barrier();
+        // the next chunk's id is in LDS since the barrier: start loading its
+        // item range now (the items themselves follow the adjacency loads)
+        long long cn = nchunks;
+        if (PF > 0 && cnext) {
+            cn = *s_chunk;
+            pf_ok = cn < nchunks;
+            if (pf_ok) range(cn, pk0, pk1);
+        }
         // thread t owns the EPT consecutive edges from x0 + t*EPT: one binary
         // search for the first, then a linear advance over item boundaries
         const int xs = (int)x0 + (int)threadIdx.x * EPT;
@@ -472,6 +512,18 @@ __device__ __forceinline__ void sweep_chunks(int K, long long E, const int* __re
                 }
             }
         }
+        if (PF > 0 && pf_ok) {
+            const int nn = pk1 - pk0 + 1;
+#pragma unroll
+            for (int q = 0; q < (PF > 0 ? PF : 1); q++) {
+                const int j = (int)threadIdx.x + q * BLK;
+                const bool in = j < nn && nn <= CH;
+                pv[q] = in ? iv[pk0 + j] : 0;
+                pe[q] = in ? ie[pk0 + j] : 0;
+                pr[q] = in ? ir[pk0 + j] : 0;
+            }
+        }
+        (void)cn;
 #pragma unroll
         for (int e = 0; e < EPT; e++) st[e] = jj[e] >= 0 ? op.gather(uu[e]) : 0;
         op.template resolve<EPT>(jj, uu, st);
@@ -1210,6 +1262,10 @@ __global__ __launch_bounds__(PEEL_BLK, PEEL_BLOCKS_PER_CU) void k_peel_rounds(Pe
 constexpr int NEAR_BLK = 512;
 constexpr int NEAR_SEL_U = 4;
 constexpr int SEG_STRIDE = PEEL_BLK;  // segment tables hold PEEL_BLK entries per field
+constexpr int APPLY_META = 64;        // ranges per block whose bounds are read up front (2048 ranges / 32 blocks)
+constexpr int APPLY_REG = 8;          // bucket entries per thread kept in registers between the apply's passes
+constexpr int NEAR_PF = 2;            // items per thread of the next sweep chunk loaded ahead
+using PeelSweepLdsT = SweepLds<PEEL_CH>;
 static_assert(NEAR_BLK * NEAR_SEL_U < (1 << 16), "tile counts must fit their packed fields");
 static_assert(DEC_SLOTS % NEAR_BLK == 0, "slots must be a multiple of the block");
 
@@ -1351,6 +1407,7 @@ __global__ __launch_bounds__(NEAR_BLK, 1) void k_peel_rounds_near(PeelArgs a) {
     __shared__ int s_chunk;
     __shared__ long long s_ntot;  // entries in the near list's segments (map built at the previous round's end)
     __shared__ unsigned int s_xn;     // staged crossings
+    __shared__ int s_meta[2 * APPLY_META];  // bucket apply: start and entry count of each of the block's ranges
     __shared__ unsigned int s_xbase;  // their reserved start in the global list
     Ctl* ctl = a.ctl;
     GridSync* gs = a.gs;
@@ -1547,56 +1604,95 @@ __global__ __launch_bounds__(NEAR_BLK, 1) void k_peel_rounds_near(PeelArgs a) {
         op.nearB = (int)B;
         op.xst = xst;
         if (E >= a.coarse_min_e)
-            sweep_chunks<NEAR_BLK, PEEL_CH, PEEL_CH / PEEL_MARK>(K, E, ivr, a.ie, a.ir, a.cfirst, a.clast, a.adj,
+            sweep_chunks<NEAR_BLK, PEEL_CH, PEEL_CH / PEEL_MARK, PeelEdgeOp<NEAR_BLK>, PeelSweepLdsT, NEAR_PF>(
+                K, E, ivr, a.ie, a.ir, a.cfirst, a.clast, a.adj,
                                                                  a.inc, op, lds.m.sw, blockIdx.x, nblocks,
                                                                  &ctl->cnext[slot], &s_chunk);
         else
-            sweep_chunks<NEAR_BLK, PEEL_MARK, 1>(K, E, ivr, a.ie, a.ir, a.cfirst, a.clast, a.adj, a.inc, op,
+            sweep_chunks<NEAR_BLK, PEEL_MARK, 1, PeelEdgeOp<NEAR_BLK>, PeelSweepLdsT, NEAR_PF>(
+                K, E, ivr, a.ie, a.ir, a.cfirst, a.clast, a.adj, a.inc, op,
                                                  lds.m.sw, blockIdx.x, nblocks, &ctl->cnext[slot], &s_chunk);
         unsigned int rmin = op.lmin;
         if (bucket) {
             grid_sync(bar);
-            // apply the owner buckets as k_peel_rounds does; a decrement that
-            // crosses B appends its vertex to the crossing list
+            // apply the owner buckets as k_peel_rounds does, with two memory
+            // round trips fewer per range: the block reads the bounds and fill
+            // counts of all its ranges at once, and keeps up to
+            // APPLY_REG * NEAR_BLK entries of a range in registers between the
+            // two passes.  A decrement that crosses B appends its vertex to the
+            // crossing list.
             const int R = 1 << a.rshift;
-            if ((int)blockIdx.x < a.nr) {
-                for (int i = threadIdx.x; i < R; i += NEAR_BLK) lds.dense[i] = 0;
+            const int my_nr = (int)blockIdx.x < a.nr ? (a.nr - (int)blockIdx.x + (int)nblocks - 1) / (int)nblocks : 0;
+            if (my_nr > 0) {
+                for (int t = threadIdx.x; t < min(my_nr, APPLY_META); t += NEAR_BLK) {
+                    const int j = (int)blockIdx.x + t * (int)nblocks;
+                    const int v0 = j << a.rshift;
+                    const int lo = a.off[v0];
+                    s_meta[2 * t] = lo;
+                    // a reservation past the range's capacity was refused (and
+                    // flagged) but still counted: never read past the range
+                    s_meta[2 * t + 1] = min((int)ld_agent(&a.bfill[j]), a.off[min(a.n, v0 + R)] - lo);
+                }
+                for (int i = threadIdx.x; i < R; i += NEAR_BLK) lds.dense[i] = 0;  // it aliases the sweep's LDS
                 lds_barrier();
             }
-            for (int j = blockIdx.x; j < a.nr; j += nblocks) {
+            for (int k = 0; k < my_nr; k++) {
+                const int j = (int)blockIdx.x + k * (int)nblocks;
                 const int v0 = j << a.rshift;
-                const int v1 = min(a.n, v0 + R);
-                const int lo = a.off[v0];
-                const int cnt = min((int)ld_agent(&a.bfill[j]), a.off[v1] - lo);
-                for (int i = threadIdx.x; i < cnt; i += NEAR_BLK) {
+                const unsigned int span = (unsigned int)(min(a.n, v0 + R) - v0);
+                int lo, cnt;
+                if (k < APPLY_META) {
+                    lo = s_meta[2 * k];
+                    cnt = s_meta[2 * k + 1];
+                } else {
+                    lo = a.off[v0];
+                    cnt = min((int)ld_agent(&a.bfill[j]), a.off[v0 + (int)span] - lo);
+                }
+                constexpr unsigned int CMASK = (1u << BKT_CNT_BITS) - 1;
+                unsigned int ent[APPLY_REG];
+#pragma unroll
+                for (int q = 0; q < APPLY_REG; q++) {
+                    const int i = (int)threadIdx.x + q * NEAR_BLK;
+                    ent[q] = i < cnt ? (unsigned int)a.bkt[lo + i] : 0xFFFFFFFFu;  // local id 2^20 - 1: no slot
+                }
+#pragma unroll
+                for (int q = 0; q < APPLY_REG; q++) {
+                    const unsigned int li = ent[q] >> BKT_CNT_BITS;
+                    if (li < span) atomicAdd(&lds.dense[li], (int)(ent[q] & CMASK) + 1);
+                }
+                for (int i = (int)threadIdx.x + APPLY_REG * NEAR_BLK; i < cnt; i += NEAR_BLK) {
                     const unsigned int e = (unsigned int)a.bkt[lo + i];
                     const unsigned int li = e >> BKT_CNT_BITS;
-                    if (li < (unsigned int)(v1 - v0)) atomicAdd(&lds.dense[li], (int)(e & ((1u << BKT_CNT_BITS) - 1)) + 1);
+                    if (li < span) atomicAdd(&lds.dense[li], (int)(e & CMASK) + 1);
                 }
                 lds_barrier();
-                for (int base = 0; base < cnt; base += NEAR_BLK) {
-                    const int i = base + (int)threadIdx.x;
+                // the first entry of each vertex takes (and clears) its slot
+                auto take = [&](unsigned int e) {
                     bool x = false;
                     int w = 0;
-                    if (i < cnt) {
-                        const unsigned int li = (unsigned int)a.bkt[lo + i] >> BKT_CNT_BITS;
-                        if (li < (unsigned int)(v1 - v0)) {
-                            const int c = atomicExch(&lds.dense[li], 0);
-                            if (c) {
-                                w = v0 + (int)li;
-                                const int old = a.prio[w];
-                                const int pw = old - c;
-                                a.prio[w] = pw;
-                                rmin = min(rmin, (unsigned int)pw);
-                                x = (long long)old > B && (long long)pw <= B;
-                            }
+                    const unsigned int li = e >> BKT_CNT_BITS;
+                    if (li < span) {
+                        const int c = atomicExch(&lds.dense[li], 0);
+                        if (c) {
+                            w = v0 + (int)li;
+                            const int old = a.prio[w];
+                            const int pw = old - c;
+                            a.prio[w] = pw;
+                            rmin = min(rmin, (unsigned int)pw);
+                            x = (long long)old > B && (long long)pw <= B;
                         }
                     }
                     xst.stage_wave(x, w);
+                };
+#pragma unroll
+                for (int q = 0; q < APPLY_REG; q++) take(ent[q]);
+                for (int base = APPLY_REG * NEAR_BLK; base < cnt; base += NEAR_BLK) {
+                    const int i = base + (int)threadIdx.x;
+                    take(i < cnt ? (unsigned int)a.bkt[lo + i] : 0xFFFFFFFFu);
                 }
-                if (threadIdx.x == 0) a.bfill[j] = 0;
                 lds_barrier();
             }
+            for (int t = threadIdx.x; t < my_nr; t += NEAR_BLK) a.bfill[(int)blockIdx.x + t * (int)nblocks] = 0;
             if ((int)blockIdx.x < a.nr) {
                 for (int t = threadIdx.x; t < DEC_SLOTS; t += NEAR_BLK) {
                     lds.m.dec.key[t] = DEC_EMPTY;
