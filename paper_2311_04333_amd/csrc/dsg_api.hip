@@ -155,8 +155,10 @@ long long carve(int n, long long nnz, int t_cap, char* base, GraphDev* g) {
     long long o_rh = L.add(4 * 256 * rtiles);
     long long o_he = L.add(8LL * t_cap), o_hv = L.add(8LL * t_cap), o_hi = L.add(4LL * t_cap);
     long long o_rd = L.add(4LL * t_cap), o_dg = L.add(8LL * t_cap), o_hw = L.add(4LL * t_cap), o_hl = L.add(4LL * t_cap);
-    const int rshift = dsg::bucket_shift(N);
-    long long o_bkt = L.add(rshift >= 0 ? 4 * nnz : 0), o_bf = L.add(4 * dsg::BKT_MAX_NR);
+    int lbits = 0, sbits = 0;
+    const bool bucketed = dsg::bucket_params(N, &lbits, &sbits);
+    long long o_bkt = L.add(bucketed ? 4 * nnz : 0), o_bf = L.add(4 * dsg::BKT_MAX_NR);
+    long long o_rb = L.add(4 * (dsg::BKT_MAX_NR + 1));
     long long o_cb = L.add(4 * ((N + 7) / 8 + 1)), o_crb = L.add(4 * 16), o_crs = L.add(4 * (1 << 17));
     long long o_crt = L.add(8 * ((1 << 17) / 1024));
     long long o_seg = L.add(4 * 6 * dsg::PEEL_BLK);
@@ -174,8 +176,10 @@ long long carve(int n, long long nnz, int t_cap, char* base, GraphDev* g) {
         g->seg = reinterpret_cast<int*>(base + o_seg);
         g->cb = reinterpret_cast<unsigned int*>(base + o_cb);
         g->cr_bounds = reinterpret_cast<int*>(base + o_crb);
-        g->rshift = rshift >= 0 ? rshift : 0;
-        g->nr = rshift >= 0 ? (int)((N + (1LL << rshift) - 1) >> rshift) : 0;
+        g->rshift = bucketed ? lbits : 0;
+        g->rsbits = bucketed ? sbits : 0;
+        g->nr = bucketed ? 1 << sbits : 0;
+        g->rbase = reinterpret_cast<int*>(base + o_rb);
         g->bkt = reinterpret_cast<int*>(base + o_bkt);
         g->bfill = reinterpret_cast<unsigned int*>(base + o_bf);
         g->ctl = reinterpret_cast<dsg::Ctl*>(base + o_ctl);
@@ -346,6 +350,7 @@ dsg_status graph_init(dsg_graph* g, dsg_ctx* ctx, int32_t n, int64_t nnz, const 
     // offsets and entries are in range now, so the static item list (which
     // the row check walks) can be built
     if ((e = dsg::launch_build_static_items(g->d, s)) != hipSuccess) return hip_fail(e, "static items");
+    if ((e = dsg::launch_bucket_bases(g->d, s)) != hipSuccess) return hip_fail(e, "bucket bases");
     dsg::Ctl c;
     st = read_ctl(g, &c);
     if (st != DSG_OK) return st;

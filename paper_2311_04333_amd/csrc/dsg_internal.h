@@ -30,13 +30,22 @@ constexpr int PEEL_MAX_N = 1 << 26;  // frontier item counter has 26 bits
 // Adjacency entries are indexed with int32, and a sweep chunk's edge
 // positions (start + up to 4096) must stay below 2^31 as well.
 constexpr long long MAX_NNZ = (1LL << 31) - (1LL << 16);
-// Owner-bucketed decrements of the PEEL round loop: vertex ids are split into
-// ranges of 2^shift ids (shift <= BKT_MAX_SHIFT, so a range's counters fit a
-// dense LDS histogram), at most BKT_MAX_NR ranges, which covers every graph
-// the PEEL path accepts (n < 2^26).  Rounds whose frontier has at least the
-// threshold's edges take the bucketed path.
+// Owner-bucketed decrements of the PEEL round loop.  Vertex ids are split
+// into 2^sbits ranges: the first BKT_HUB_IDS ids one by one, the others by
+// 32-id lines, dealt out round robin.  A range's vertices are then spread
+// over the whole id space, so the ranges stay balanced when ids are ordered
+// by degree (the hubs come first), and above the hub ids a 128-byte line of
+// priorities has one owner.  Inside its range a vertex has a local id below
+// 2^lbits (lbits <= BKT_MAX_SHIFT, so a range's counters fit a dense LDS
+// histogram).
+// At most BKT_MAX_NR ranges, which covers every graph the PEEL path accepts
+// (n < 2^26).  Rounds whose frontier has at least the threshold's edges take
+// the bucketed path.
 constexpr int BKT_MAX_SHIFT = 15;
 constexpr int BKT_MAX_NR = 2048;
+constexpr int BKT_LINE = 5;  // 32 ids per line
+constexpr int BKT_HUB_IDS = 1 << 16;  // dealt singly; a multiple of 32 * BKT_MAX_NR
+static_assert(BKT_HUB_IDS % ((1 << BKT_LINE) * BKT_MAX_NR) == 0, "hub ids fill whole lines of every range");
 constexpr int BKT_CNT_BITS = 12;  // bucket entry = local id << 12 | (count - 1); count <= PEEL_CH
 constexpr long long BKT_DEFAULT_MIN_E = 1LL << 20;
 // Near-list select (k_peel_rounds_near): the near bound is B = thr * 5/4 + 1
@@ -56,16 +65,23 @@ constexpr int SORT_COARSE_MIN_N = 1 << 19;
 constexpr int SORT_COARSE_MAX_N = (1 << 26) - 1;
 static_assert((1 << BKT_CNT_BITS) >= 4096, "chunk-local counts must fit the entry's count field");
 static_assert(BKT_MAX_SHIFT + BKT_CNT_BITS <= 32, "a bucket entry holds a local id and a count");
-static_assert(((PEEL_MAX_N + (1 << BKT_MAX_SHIFT) - 1) >> BKT_MAX_SHIFT) <= BKT_MAX_NR,
-              "every graph the PEEL path accepts fits the bucketed path");
-// Range shift for n vertices, or -1 when the graph is too large for the
-// bucketed path: the smallest shift >= 8 giving at most 256 ranges (one per
-// block of the round loop), capped at BKT_MAX_SHIFT.
-inline int bucket_shift(long long n) {
-    int s = 8;
-    while (s < BKT_MAX_SHIFT && ((n + (1LL << s) - 1) >> s) > 256) s++;
-    return ((n + (1LL << s) - 1) >> s) <= BKT_MAX_NR ? s : -1;
+// Range layout for n vertices: about 256 ranges (one per block of the round
+// loop) while a range's local ids fit 2^BKT_MAX_SHIFT, more above.  Returns
+// false when the graph needs more than BKT_MAX_NR ranges (the bucketed path is
+// then off).
+inline bool bucket_params(long long n, int* lbits, int* sbits) {
+    int cl = 0;
+    while ((1LL << cl) < n) cl++;
+    int l = cl - 8;
+    if (l < BKT_LINE) l = BKT_LINE;
+    if (l > BKT_MAX_SHIFT) l = BKT_MAX_SHIFT;
+    const int sb = cl > l ? cl - l : 0;
+    *lbits = l;
+    *sbits = sb;
+    return (1 << sb) <= BKT_MAX_NR;
 }
+static_assert(PEEL_MAX_N <= (1LL << (BKT_MAX_SHIFT + 11)) && (1 << 11) <= BKT_MAX_NR,
+              "every graph the PEEL path accepts fits the bucketed path");
 
 struct PeelArgs {
     int n;
@@ -88,10 +104,12 @@ struct PeelArgs {
     int* clast;
     Ctl* ctl;
     GridSync* gs;
-    int* bkt;              // owner buckets (nnz entries; range j starts at off[j << rshift])
+    int* bkt;              // owner buckets (nnz entries; range j's starts at rbase[j])
     unsigned int* bfill;   // per-range fill counters, zero between bucketed rounds
-    int rshift;
-    int nr;                // ranges; 0 = bucketed path off
+    const int* rbase;      // nr + 1 bucket starts: range j holds rbase[j + 1] - rbase[j] entries (its degree sum)
+    int rshift;            // local id bits of a range
+    int rsbits;            // log2 of the range count
+    int nr;                // ranges (2^rsbits); 0 = bucketed path off
     long long bkt_min_e;   // frontier edges from which a round is bucketed
     long long coarse_min_e;  // frontier edges from which a round sweeps coarse chunks
     int* seg;              // per block, by round parity: [2][alive start | alive len | frontier len][PEEL_BLK]
@@ -171,7 +189,9 @@ struct GraphDev {
     int* hist_lmax;  // per iteration: largest load after it
     int* bkt;
     unsigned int* bfill;
-    int rshift;
+    int* rbase;   // bucket starts per range (nr + 1), from the degree sums
+    int rshift;   // local id bits of a range
+    int rsbits;   // log2 of the range count
     int nr;
     unsigned int* cb;  // SORT coarse ranks
     int* cr_bounds;    // first position of each coarse class
@@ -194,6 +214,7 @@ hipError_t launch_check_offsets(const GraphDev& g, hipStream_t s);
 hipError_t launch_check_range(const GraphDev& g, hipStream_t s);
 hipError_t launch_check_rows(const GraphDev& g, hipStream_t s);
 hipError_t launch_build_static_items(const GraphDev& g, hipStream_t s);
+hipError_t launch_bucket_bases(const GraphDev& g, hipStream_t s);
 hipError_t launch_reset_state(const GraphDev& g, hipStream_t s);
 hipError_t launch_zero_ctl(const GraphDev& g, hipStream_t s);
 

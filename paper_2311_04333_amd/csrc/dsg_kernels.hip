@@ -714,6 +714,28 @@ struct XStage {
     }
 };
 
+// Owner ranges of the bucketed decrements (2^sb ranges).  The first
+// BKT_HUB_IDS ids are dealt one by one (u mod 2^sb), the rest by 32-id lines
+// (line mod 2^sb).  With ids ordered by degree the first ids are the hubs,
+// whose decrements come from nearly every chunk: dealt singly they spread
+// evenly over the ranges, where a whole line of them would overload one.
+// Local ids: the hub ids take the first BKT_HUB_IDS >> sb slots of a range.
+__device__ __forceinline__ int bkt_owner(int u, int sb) {
+    const int m = (1 << sb) - 1;
+    return u < BKT_HUB_IDS ? (u & m) : (((u - BKT_HUB_IDS) >> BKT_LINE) & m);
+}
+__device__ __forceinline__ int bkt_local(int u, int sb) {
+    if (u < BKT_HUB_IDS) return u >> sb;
+    const int w = u - BKT_HUB_IDS;
+    return (BKT_HUB_IDS >> sb) + (((w >> (BKT_LINE + sb)) << BKT_LINE) | (w & ((1 << BKT_LINE) - 1)));
+}
+__device__ __forceinline__ int bkt_global(int j, int li, int sb) {
+    const int h = BKT_HUB_IDS >> sb;
+    if (li < h) return (li << sb) | j;
+    const int w = li - h;
+    return BKT_HUB_IDS + (((w >> BKT_LINE) << (BKT_LINE + sb)) | (j << BKT_LINE) | (w & ((1 << BKT_LINE) - 1)));
+}
+
 template <int BLK>
 struct PeelEdgeOp {
     const unsigned int* st2;
@@ -725,10 +747,10 @@ struct PeelEdgeOp {
     // bucketed rounds: the chunk's aggregated (target, count) pairs go to
     // the owner range's bucket instead of one atomicSub per target
     bool bucket;
-    int rshift;
+    int rsb;  // log2 of the range count
     int nr;
     int n;
-    const int* off;
+    const int* rbase;
     int* bkt;
     unsigned int* bfill;
     int* bcnt;
@@ -803,7 +825,7 @@ struct PeelEdgeOp {
     // reserves the chunk's share of every touched range's bucket with one
     // global atomic per range, then writes the entries.  A range's bucket
     // holds at most one entry per decrement of its vertices in a round, so
-    // its capacity is the range's degree sum: it starts at off[j << rshift].
+    // its capacity is the range's degree sum: rbase[j + 1] - rbase[j].
     __device__ __forceinline__ void flush_to_buckets() {
         constexpr int PER = DEC_SLOTS / BLK;
         lds_barrier();
@@ -813,14 +835,14 @@ struct PeelEdgeOp {
             const int slot = threadIdx.x + k * BLK;
             key[k] = dec->key[slot];
             c[k] = dec->cnt[slot];
-            rk[k] = key[k] != DEC_EMPTY ? atomicAdd(&bcnt[key[k] >> rshift], 1) : 0;
+            rk[k] = key[k] != DEC_EMPTY ? atomicAdd(&bcnt[bkt_owner(key[k], rsb)], 1) : 0;
         }
         lds_barrier();
         for (int j = threadIdx.x; j < nr; j += BLK) {
             const int cj = bcnt[j];
             if (cj) {
-                const int lo = off[j << rshift];
-                const int hi = off[min(n, (j + 1) << rshift)];
+                const int lo = rbase[j];
+                const int hi = rbase[j + 1];
                 const int b = lo + (int)atomicAdd(&bfill[j], (unsigned int)cj);
                 if (b + cj > hi) {  // impossible by the capacity argument; never write past the range
                     flag_error();
@@ -835,9 +857,9 @@ struct PeelEdgeOp {
 #pragma unroll
         for (int k = 0; k < PER; k++) {
             if (key[k] != DEC_EMPTY) {
-                const int j = key[k] >> rshift;
+                const int j = bkt_owner(key[k], rsb);
                 const int b = bbase[j];
-                if (b >= 0) bkt[b + rk[k]] = ((key[k] - (j << rshift)) << BKT_CNT_BITS) | (c[k] - 1);
+                if (b >= 0) bkt[b + rk[k]] = (bkt_local(key[k], rsb) << BKT_CNT_BITS) | (c[k] - 1);
                 const int slot = threadIdx.x + k * BLK;
                 dec->key[slot] = DEC_EMPTY;
                 dec->cnt[slot] = 0;
@@ -1125,7 +1147,7 @@ __global__ __launch_bounds__(PEEL_BLK, PEEL_BLOCKS_PER_CU) void k_peel_rounds(Pe
         const int K = (int)(f >> FCNT_SHIFT);
         const long long E = (long long)(f & FCNT_MASK);
         const bool bucket = a.nr > 0 && E >= a.bkt_min_e;
-        PeelEdgeOp<PEEL_BLK> op{a.st2, a.prio, r, lmin, ctl, &lds.m.dec, bucket, a.rshift, a.nr, a.n, a.off, a.bkt,
+        PeelEdgeOp<PEEL_BLK> op{a.st2, a.prio, r, lmin, ctl, &lds.m.dec, bucket, a.rsbits, a.nr, a.n, a.rbase, a.bkt,
                                 a.bfill, lds.bcnt, lds.bbase};
         if (E >= a.coarse_min_e)
             sweep_chunks<PEEL_BLK, PEEL_CH, PEEL_CH / PEEL_MARK>(K, E, ivr, a.ie, a.ir, a.cfirst, a.clast, a.adj,
@@ -1150,24 +1172,22 @@ __global__ __launch_bounds__(PEEL_BLK, PEEL_BLOCKS_PER_CU) void k_peel_rounds(Pe
                 lds_barrier();
             }
             for (int j = blockIdx.x; j < a.nr; j += nblocks) {
-                const int v0 = j << a.rshift;
-                const int v1 = min(a.n, v0 + R);
-                const int lo = a.off[v0];
+                const int lo = a.rbase[j];
                 // a reservation past the range's capacity was refused (and
                 // flagged) but still counted: never read past the range
-                const int cnt = min((int)ld_agent(&a.bfill[j]), a.off[v1] - lo);
+                const int cnt = min((int)ld_agent(&a.bfill[j]), a.rbase[j + 1] - lo);
                 for (int i = threadIdx.x; i < cnt; i += PEEL_BLK) {
                     const unsigned int e = (unsigned int)a.bkt[lo + i];
                     const unsigned int li = e >> BKT_CNT_BITS;
-                    if (li < (unsigned int)(v1 - v0)) atomicAdd(&lds.dense[li], (int)(e & ((1u << BKT_CNT_BITS) - 1)) + 1);
+                    if (li < (unsigned int)R) atomicAdd(&lds.dense[li], (int)(e & ((1u << BKT_CNT_BITS) - 1)) + 1);
                 }
                 lds_barrier();
                 for (int i = threadIdx.x; i < cnt; i += PEEL_BLK) {
                     const unsigned int li = (unsigned int)a.bkt[lo + i] >> BKT_CNT_BITS;
-                    if (li < (unsigned int)(v1 - v0)) {
+                    if (li < (unsigned int)R) {
                         const int c = atomicExch(&lds.dense[li], 0);
-                        if (c) {
-                            const int u = v0 + (int)li;
+                        const int u = bkt_global(j, (int)li, a.rsbits);
+                        if (c && u < a.n) {
                             const int pu = a.prio[u] - c;
                             a.prio[u] = pu;
                             rmin = min(rmin, (unsigned int)pu);
@@ -1287,6 +1307,31 @@ __device__ __forceinline__ long long build_map(const int* __restrict__ tab, int 
     return (long long)tot;
 }
 
+// The order in which the first full-list pass of an iteration visits the
+// vertices (and so the order of the full list after it): 32-id lines read
+// column by column from a 256-column row-major layout of the lines.  Every
+// block's slice then samples the whole id space, so the blocks share the
+// frontier evenly also when the ids are ordered by degree.  A bijection of
+// [0, n); the partial last line stays in place.
+__device__ __forceinline__ int spread_id(int idx, int n) {
+    constexpr int S = 256;
+    const int nl = n >> 5;
+    const int line = idx >> 5;
+    if (line >= nl) return idx;
+    const int rows = (nl + S - 1) / S;
+    const int cfull = nl - (rows - 1) * S;  // columns with `rows` lines
+    int col, row;
+    if (line < cfull * rows) {
+        col = line / rows;
+        row = line - col * rows;
+    } else {
+        const int p = line - cfull * rows;
+        col = cfull + p / (rows - 1);
+        row = p - (col - cfull) * (rows - 1);
+    }
+    return ((row * S + col) << 5) | (idx & 31);
+}
+
 // Per-block result of one classification pass over a list slice.
 struct NearPass {
     int n_run;   // near survivors written to the near segment
@@ -1299,7 +1344,8 @@ struct NearPass {
 };
 
 // Classifies the slice [beg, end) of a virtual list.  kind 0: entry i is
-// vertex i; 1: Lin[map(i)]; 2: Lin[map(i)] for i < mtot, then Xin[i - mtot].
+// vertex spread_id(i); 1: Lin[map(i)]; 2: Lin[map(i)] for i < mtot, then
+// Xin[i - mtot].
 // Each alive entry (priority >= 0) goes to exactly one class:
 //   frontier (priority <= thr): round r, priority -1, state bit, Nout tail;
 //   survivor: bids its priority; to Fout[beg + ...] when Fout is given, and
@@ -1327,7 +1373,7 @@ __device__ __forceinline__ NearPass near_classify(const PeelArgs& a, int r, int 
     }
     auto entry = [&](int idx) -> int {
         if (idx >= end) return -1;
-        if (kind == 0) return idx;
+        if (kind == 0) return spread_id(idx, a.n);
         if (kind == 2 && idx >= mtot) return Xin[idx - mtot];
         while (sj + 1 < nseg && spref[sj + 1] <= idx) sj++;
         return Lin[sstart[sj] + (idx - spref[sj])];
@@ -1356,6 +1402,9 @@ __device__ __forceinline__ NearPass near_classify(const PeelArgs& a, int r, int 
         }
         // packed per-thread counts: [near: 0-15][full-list survivors: 16-31][frontier: 32-47][items: 48-63]
         unsigned long long val = 0;
+        // frontier marks of this thread's entries, one atomic per state word
+        int mword = -1;
+        unsigned int mbits = 0;
 #pragma unroll
         for (int k = 0; k < NEAR_SEL_U; k++) {
             if (pu[k] < 0) continue;  // no entry, or peeled in an earlier round
@@ -1367,7 +1416,12 @@ __device__ __forceinline__ NearPass near_classify(const PeelArgs& a, int r, int 
                 if (d > 0) {
                     val += 1ull << 48;
                     P.edges += (unsigned long long)d;
-                    atomicOr(&a.st2[u[k] >> 4], 2u << ((u[k] & 15) * 2));
+                    if ((u[k] >> 4) != mword) {
+                        if (mbits) atomicOr(&a.st2[mword], mbits);
+                        mword = u[k] >> 4;
+                        mbits = 0;
+                    }
+                    mbits |= 2u << ((u[k] & 15) * 2);
                 }
             } else {
                 P.lmin = min(P.lmin, (unsigned int)pu[k]);
@@ -1375,6 +1429,7 @@ __device__ __forceinline__ NearPass near_classify(const PeelArgs& a, int r, int 
                 if ((long long)pu[k] <= B) val += 1ull;
             }
         }
+        if (mbits) atomicOr(&a.st2[mword], mbits);
         unsigned long long tot;
         const unsigned long long ex = block_excl_scan<NEAR_BLK>(val, &tot, shs);
         int nr_ = beg + P.n_run + (int)(ex & 0xFFFFull);
@@ -1597,7 +1652,7 @@ __global__ __launch_bounds__(NEAR_BLK, 1) void k_peel_rounds_near(PeelArgs a) {
         const int K = (int)(f >> FCNT_SHIFT);
         const long long E = (long long)(f & FCNT_MASK);
         const bool bucket = a.nr > 0 && E >= a.bkt_min_e;
-        PeelEdgeOp<NEAR_BLK> op{a.st2, a.prio, r, P.lmin, ctl, &lds.m.dec, bucket, a.rshift, a.nr, a.n, a.off, a.bkt, a.bfill,
+        PeelEdgeOp<NEAR_BLK> op{a.st2, a.prio, r, P.lmin, ctl, &lds.m.dec, bucket, a.rsbits, a.nr, a.n, a.rbase, a.bkt, a.bfill,
                       lds.bcnt, lds.bbase};
         // crossings are staged in lds.bbase, which only the bucket flush uses (as scratch)
         const XStage xst{lds.bbase, &s_xn, Xout, &ctl->xcnt[nslot], a.n, ctl};
@@ -1626,27 +1681,25 @@ __global__ __launch_bounds__(NEAR_BLK, 1) void k_peel_rounds_near(PeelArgs a) {
             if (my_nr > 0) {
                 for (int t = threadIdx.x; t < min(my_nr, APPLY_META); t += NEAR_BLK) {
                     const int j = (int)blockIdx.x + t * (int)nblocks;
-                    const int v0 = j << a.rshift;
-                    const int lo = a.off[v0];
+                    const int lo = a.rbase[j];
                     s_meta[2 * t] = lo;
                     // a reservation past the range's capacity was refused (and
                     // flagged) but still counted: never read past the range
-                    s_meta[2 * t + 1] = min((int)ld_agent(&a.bfill[j]), a.off[min(a.n, v0 + R)] - lo);
+                    s_meta[2 * t + 1] = min((int)ld_agent(&a.bfill[j]), a.rbase[j + 1] - lo);
                 }
                 for (int i = threadIdx.x; i < R; i += NEAR_BLK) lds.dense[i] = 0;  // it aliases the sweep's LDS
                 lds_barrier();
             }
             for (int k = 0; k < my_nr; k++) {
                 const int j = (int)blockIdx.x + k * (int)nblocks;
-                const int v0 = j << a.rshift;
-                const unsigned int span = (unsigned int)(min(a.n, v0 + R) - v0);
+                const unsigned int span = (unsigned int)R;
                 int lo, cnt;
                 if (k < APPLY_META) {
                     lo = s_meta[2 * k];
                     cnt = s_meta[2 * k + 1];
                 } else {
-                    lo = a.off[v0];
-                    cnt = min((int)ld_agent(&a.bfill[j]), a.off[v0 + (int)span] - lo);
+                    lo = a.rbase[j];
+                    cnt = min((int)ld_agent(&a.bfill[j]), a.rbase[j + 1] - lo);
                 }
                 constexpr unsigned int CMASK = (1u << BKT_CNT_BITS) - 1;
                 unsigned int ent[APPLY_REG];
@@ -1673,8 +1726,9 @@ __global__ __launch_bounds__(NEAR_BLK, 1) void k_peel_rounds_near(PeelArgs a) {
                     const unsigned int li = e >> BKT_CNT_BITS;
                     if (li < span) {
                         const int c = atomicExch(&lds.dense[li], 0);
-                        if (c) {
-                            w = v0 + (int)li;
+                        const int u = bkt_global(j, (int)li, a.rsbits);
+                        if (c && u < a.n) {
+                            w = u;
                             const int old = a.prio[w];
                             const int pw = old - c;
                             a.prio[w] = pw;
@@ -2540,6 +2594,48 @@ hipError_t launch_build_static_items(const GraphDev& g, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Degree sum of each owner range, written to rbase[j + 1]: block j sums its
+// single hub ids (j, j + nr, ... below BKT_HUB_IDS) and its lines above (line
+// l covers ids BKT_HUB_IDS + [32 l, 32 l + 32) and belongs to range l mod nr).
+__global__ __launch_bounds__(256) void k_bucket_cap(int n, const int* __restrict__ off, int sb,
+                                                    int* __restrict__ rbase) {
+    __shared__ long long sh[256 / WAVE];
+    const int j = blockIdx.x;
+    long long sum = 0;
+    const int nh = min(n, BKT_HUB_IDS);
+    for (int u = j + ((int)threadIdx.x << sb); u < nh; u += 256 << sb) sum += off[u + 1] - off[u];
+    const long long rest = (long long)n - nh;
+    const long long nlines = (rest + (1 << BKT_LINE) - 1) >> BKT_LINE;
+    for (long long l = j + ((long long)threadIdx.x << sb); l < nlines; l += 256LL << sb) {
+        const long long v0 = nh + (l << BKT_LINE);
+        const long long v1 = min((long long)n, v0 + (1 << BKT_LINE));
+        sum += off[v1] - off[v0];
+    }
+    sum = block_sum<256>(sum, sh);
+    if (threadIdx.x == 0) rbase[j + 1] = (int)sum;
+}
+
+// Exclusive scan of the nr range sums into bucket starts (one block; nr <=
+// BKT_MAX_NR = 2 * 1024).
+__global__ __launch_bounds__(1024) void k_bucket_scan(int nr, int* __restrict__ rbase) {
+    __shared__ int sh[1024 / WAVE];
+    const int i0 = 2 * (int)threadIdx.x;
+    const int a0 = i0 < nr ? rbase[i0 + 1] : 0;
+    const int a1 = i0 + 1 < nr ? rbase[i0 + 2] : 0;
+    int total;
+    const int base = block_excl_scan<1024>(a0 + a1, &total, sh);
+    if (i0 < nr) rbase[i0 + 1] = base + a0;
+    if (i0 + 1 < nr) rbase[i0 + 2] = base + a0 + a1;
+    if (threadIdx.x == 0) rbase[0] = 0;
+}
+
+hipError_t launch_bucket_bases(const GraphDev& g, hipStream_t s) {
+    if (g.nr <= 0) return hipSuccess;
+    k_bucket_cap<<<g.nr, 256, 0, s>>>(g.n, g.off, g.rsbits, g.rbase);
+    k_bucket_scan<<<1, 1024, 0, s>>>(g.nr, g.rbase);
+    return hipGetLastError();
+}
+
 hipError_t launch_reset_state(const GraphDev& g, hipStream_t s) {
     k_fill_i32<<<grid_for(g.n, 256), 256, 0, s>>>(g.load, 0, g.n);
     k_ctl_reset<<<1, 64, 0, s>>>(g.ctl, g.nnz / 2, g.n);
@@ -2639,6 +2735,8 @@ hipError_t enqueue_iter_peel(const GraphDev& g, int slot, int eps_num, int eps_d
     a.bkt = g.bkt;
     a.bfill = g.bfill;
     a.rshift = g.rshift;
+    a.rsbits = g.rsbits;
+    a.rbase = g.rbase;
     a.nr = g.nr;
     a.bkt_min_e = bkt_min_e;
     a.coarse_min_e = coarse_min_e;

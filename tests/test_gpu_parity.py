@@ -294,8 +294,8 @@ def test_peel_bucket_paths(dsg, ctx, name):
 
 
 def test_peel_bucket_more_ranges_than_blocks(dsg, ctx):
-    """n = 12M vertices: 32768-id ranges number 367, more than the round loop's blocks, so blocks apply several
-    ranges per bucketed round (and the last range is partial)."""
+    """n = 12M vertices: 512 owner ranges, more than the round loop's blocks, so blocks apply several ranges per
+    bucketed round (and the last lines of the id space fill only part of the ranges)."""
     o, a = graphgen.er_planted(14, 12_000_000, 14_000_000, 60, 1, 2)
     ref = oracle.run(o, a, 2, "peel", (1, 10))
     for thr in [0, 1 << 62]:
