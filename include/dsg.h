@@ -78,6 +78,16 @@ typedef enum { DSG_SEQ = 0, DSG_PEEL = 1, DSG_SORT = 2, DSG_PEEL_MONO = 3 } dsg_
 
 /* flags for dsg_graph_create */
 #define DSG_VALIDATE 1 /* check every CSR property listed above on the device */
+/* Hub order: the graph renumbers its vertices internally by non-increasing
+ * degree (ties by id) and keeps a renumbered copy of the CSR in its
+ * workspace (dsg_workspace_bytes_ex).  In a skewed graph most adjacency
+ * entries point at a few high-degree vertices; numbered first, their
+ * per-vertex state shares a few cache lines, so the neighbour gathers of the
+ * PEEL and SORT sweeps mostly hit the L2.  Every result (loads, orders,
+ * digests, best set, densities) is reported in the caller's ids and is
+ * identical to the result without the flag: ties between vertices still go
+ * to the smaller caller id. */
+#define DSG_HUB_ORDER 2
 
 typedef struct dsg_ctx dsg_ctx;
 typedef struct dsg_graph dsg_graph;
@@ -93,11 +103,19 @@ dsg_status dsg_ctx_destroy(dsg_ctx* ctx);
  * n >= 1, 0 <= nnz <= 2^31 - 2^16 (int32 edge positions with a chunk of headroom), t_cap >= 1. */
 dsg_status dsg_workspace_bytes(int32_t n, int64_t nnz, int32_t t_cap, int64_t* bytes);
 
+/* The same for a graph created with `flags`: DSG_HUB_ORDER adds the
+ * renumbered CSR and the two permutations, 4 (n + 1) + 4 nnz + 8 n bytes
+ * (rounded up to 256-byte regions).  Other flags add nothing. */
+dsg_status dsg_workspace_bytes_ex(int32_t n, int64_t nnz, int32_t t_cap, int32_t flags, int64_t* bytes);
+
 /* Bind a CSR already resident on the device.  d_workspace must be 256-byte
- * aligned and hold at least dsg_workspace_bytes(n, nnz, t_cap) bytes.  The
- * state is reset: loads 0, best = the input graph (iteration 0).  With
- * DSG_VALIDATE the CSR is checked and an invalid one gives DSG_EINVAL.
- * This call synchronises the stream once (it reads the maximum degree). */
+ * aligned and hold at least dsg_workspace_bytes_ex(n, nnz, t_cap, flags)
+ * bytes.  The state is reset: loads 0, best = the input graph (iteration 0).
+ * With DSG_VALIDATE the CSR is checked and an invalid one gives DSG_EINVAL.
+ * With DSG_HUB_ORDER the caller's CSR is read only here (it is renumbered
+ * into the workspace); otherwise it must stay resident and unchanged while
+ * the graph exists.  This call synchronises the stream (it reads the
+ * maximum degree). */
 dsg_status dsg_graph_create(dsg_ctx* ctx, int32_t n, int64_t nnz, const int32_t* d_offsets, const int32_t* d_adj,
                             void* d_workspace, int64_t workspace_bytes, int32_t t_cap, int32_t flags,
                             dsg_graph** out);

@@ -29,6 +29,9 @@ VARIANTS = {"seq": 0, "peel": 1, "sort": 2, "peel_mono": 3}
 STATUS = {0: "DSG_OK", -1: "DSG_EINVAL", -2: "DSG_ENOMEM", -3: "DSG_EDEVICE", -4: "DSG_EOVERFLOW",
           -5: "DSG_ESTATE", -6: "DSG_EBUSY"}
 VALIDATE = 1
+HUB_ORDER = 2
+# Graph(hub_order="auto") renumbers by degree from this many vertices on
+HUB_AUTO_MIN_N = 1 << 23
 
 # every entry point declared in include/dsg.h: (name, restype, argtypes)
 _P = ctypes.c_void_p
@@ -38,6 +41,7 @@ SIGNATURES = [
     ("dsg_ctx_create", ctypes.c_int, [ctypes.c_int, _P, _P]),
     ("dsg_ctx_destroy", ctypes.c_int, [_P]),
     ("dsg_workspace_bytes", ctypes.c_int, [_I32, _I64, _I32, _P]),
+    ("dsg_workspace_bytes_ex", ctypes.c_int, [_I32, _I64, _I32, _I32, _P]),
     ("dsg_graph_create", ctypes.c_int, [_P, _I32, _I64, _P, _P, _P, _I64, _I32, _I32, _P]),
     ("dsg_run", ctypes.c_int, [_P, _I32, _I32, _I32, ctypes.c_int]),
     ("dsg_run_until", ctypes.c_int, [_P, _I32, _I32, _I32, ctypes.c_int, _I32, _I32, _P, _P]),
@@ -169,9 +173,9 @@ def parse_eps(eps) -> tuple[int, int]:
     return num, den
 
 
-def workspace_bytes(n: int, nnz: int, t_cap: int) -> int:
+def workspace_bytes(n: int, nnz: int, t_cap: int, flags: int = 0) -> int:
     out = ctypes.c_int64()
-    _check(library().dsg_workspace_bytes(n, nnz, t_cap, ctypes.addressof(out)))
+    _check(library().dsg_workspace_bytes_ex(n, nnz, t_cap, flags, ctypes.addressof(out)))
     return out.value
 
 
@@ -208,10 +212,12 @@ class Graph:
 
     ``offsets``/``adj`` may be numpy arrays (copied to the device) or int32
     device tensors (used in place).  The workspace is a torch uint8 tensor
-    owned by this object.
+    owned by this object.  ``hub_order``: renumber the vertices internally by
+    degree (DSG_HUB_ORDER; same results, in the caller's ids); "auto" does so
+    from HUB_AUTO_MIN_N vertices on.
     """
 
-    def __init__(self, ctx: Context, offsets, adj, t_cap: int = 64, validate: bool = True):
+    def __init__(self, ctx: Context, offsets, adj, t_cap: int = 64, validate: bool = True, hub_order="auto"):
         import torch
 
         self.ctx = ctx
@@ -222,7 +228,11 @@ class Graph:
         self.nnz = int(self.adj.numel())
         self.m = self.nnz // 2
         self.t_cap = t_cap
-        nbytes = workspace_bytes(self.n, self.nnz, t_cap)
+        if hub_order == "auto":
+            hub_order = self.n >= HUB_AUTO_MIN_N
+        self.hub_order = bool(hub_order)
+        flags = (VALIDATE if validate else 0) | (HUB_ORDER if self.hub_order else 0)
+        nbytes = workspace_bytes(self.n, self.nnz, t_cap, flags)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
         base = self.workspace.data_ptr()
         aligned = (base + 255) // 256 * 256
@@ -230,7 +240,7 @@ class Graph:
         adj_ptr = self.adj.data_ptr() if self.nnz > 0 else 0
         _check(library().dsg_graph_create(ctx.handle, self.n, self.nnz, ctypes.c_void_p(self.offsets.data_ptr()),
                                           ctypes.c_void_p(adj_ptr), ctypes.c_void_p(aligned), nbytes, t_cap,
-                                          VALIDATE if validate else 0, ctypes.addressof(handle)))
+                                          flags, ctypes.addressof(handle)))
         self._h = handle
 
     @staticmethod

@@ -124,7 +124,7 @@ dsg_status hip_fail(hipError_t e, const char* where) {
     } while (0)
 
 struct Layout {
-    long long off[64];
+    long long off[80];
     int count = 0;
     long long total = 0;
     long long add(long long bytes) {
@@ -136,7 +136,7 @@ struct Layout {
 };
 
 // Sizes of every workspace region; the same function both sizes and carves.
-long long carve(int n, long long nnz, int t_cap, char* base, GraphDev* g) {
+long long carve(int n, long long nnz, int t_cap, char* base, GraphDev* g, int flags = 0) {
     Layout L;
     const long long N = n;
     const long long nch = nnz / dsg::MIN_CH + 2;
@@ -177,8 +177,14 @@ long long carve(int n, long long nnz, int t_cap, char* base, GraphDev* g) {
         g->cb = reinterpret_cast<unsigned int*>(base + o_cb);
         g->cr_bounds = reinterpret_cast<int*>(base + o_crb);
         g->rshift = bucketed ? lbits : 0;
-        g->rsbits = bucketed ? sbits : 0;
-        g->nr = bucketed ? 1 << sbits : 0;
+        if (flags & DSG_HUB_ORDER) {
+            g->bm = dsg::BktMap{sbits, dsg::BKT_LINE, dsg::BKT_HUB_IDS};
+            g->nr = bucketed ? 1 << sbits : 0;
+        } else {
+            // contiguous ranges of 2^lbits ids; only the first ceil(n / 2^lbits) hold vertices
+            g->bm = dsg::BktMap{sbits, lbits, 0};
+            g->nr = bucketed ? (int)((N + (1LL << lbits) - 1) >> lbits) : 0;
+        }
         g->rbase = reinterpret_cast<int*>(base + o_rb);
         g->bkt = reinterpret_cast<int*>(base + o_bkt);
         g->bfill = reinterpret_cast<unsigned int*>(base + o_bf);
@@ -220,6 +226,18 @@ long long carve(int n, long long nnz, int t_cap, char* base, GraphDev* g) {
         g->digest = reinterpret_cast<unsigned long long*>(base + o_dg);
         g->hist_w = reinterpret_cast<int*>(base + o_hw);
         g->hist_lmax = reinterpret_cast<int*>(base + o_hl);
+    }
+    if (flags & DSG_HUB_ORDER) {
+        // the renumbered CSR and the two permutations; graph_init fills them
+        // and points off / adj / perm / iperm there
+        const long long o_hoff = L.add(4 * (N + 1)), o_hadj = L.add(4 * nnz);
+        const long long o_perm = L.add(4 * N), o_iperm = L.add(4 * N);
+        if (base && g) {
+            g->hub_off = reinterpret_cast<int*>(base + o_hoff);
+            g->hub_adj = reinterpret_cast<int*>(base + o_hadj);
+            g->hub_perm = reinterpret_cast<int*>(base + o_perm);
+            g->hub_iperm = reinterpret_cast<int*>(base + o_iperm);
+        }
     }
     return L.total;
 }
@@ -303,6 +321,13 @@ dsg_status dsg_workspace_bytes(int32_t n, int64_t nnz, int32_t t_cap, int64_t* b
     return DSG_OK;
 }
 
+dsg_status dsg_workspace_bytes_ex(int32_t n, int64_t nnz, int32_t t_cap, int32_t flags, int64_t* bytes) {
+    const dsg_status st = dsg_workspace_bytes(n, nnz, t_cap, bytes);
+    if (st != DSG_OK) return st;
+    *bytes = carve(n, nnz, t_cap, nullptr, nullptr, flags);
+    return DSG_OK;
+}
+
 }  // extern "C"
 
 namespace {
@@ -321,8 +346,9 @@ dsg_status graph_init(dsg_graph* g, dsg_ctx* ctx, int32_t n, int64_t nnz, const 
     if (nnz > 0 && !d_adj) return fail(DSG_EINVAL, "adj is NULL");
     if (t_cap < 1) return fail(DSG_EINVAL, "t_cap must be >= 1");
     if (reinterpret_cast<uintptr_t>(d_workspace) % 256 != 0) return fail(DSG_EINVAL, "workspace not 256-byte aligned");
-    long long need = carve(n, nnz, t_cap, nullptr, nullptr);
-    if (workspace_bytes < need) return fail(DSG_ENOMEM, "workspace smaller than dsg_workspace_bytes()");
+    if (flags & ~(DSG_VALIDATE | DSG_HUB_ORDER)) return fail(DSG_EINVAL, "unknown flags");
+    long long need = carve(n, nnz, t_cap, nullptr, nullptr, flags);
+    if (workspace_bytes < need) return fail(DSG_ENOMEM, "workspace smaller than dsg_workspace_bytes_ex()");
     DSG_HIP(hipSetDevice(ctx->device), "hipSetDevice");
     g->ctx = ctx;
     g->ws = static_cast<char*>(d_workspace);
@@ -337,7 +363,7 @@ dsg_status graph_init(dsg_graph* g, dsg_ctx* ctx, int32_t n, int64_t nnz, const 
     g->d.nnz = nnz;
     g->d.off = d_offsets;
     g->d.adj = d_adj;
-    carve(n, nnz, t_cap, g->ws, &g->d);
+    carve(n, nnz, t_cap, g->ws, &g->d, flags);
     hipStream_t s = ctx->stream;
     hipError_t e;
     if ((e = dsg::launch_zero_ctl(g->d, s)) != hipSuccess) return hip_fail(e, "zero ctl");
@@ -350,20 +376,32 @@ dsg_status graph_init(dsg_graph* g, dsg_ctx* ctx, int32_t n, int64_t nnz, const 
     // offsets and entries are in range now, so the static item list (which
     // the row check walks) can be built
     if ((e = dsg::launch_build_static_items(g->d, s)) != hipSuccess) return hip_fail(e, "static items");
-    if ((e = dsg::launch_bucket_bases(g->d, s)) != hipSuccess) return hip_fail(e, "bucket bases");
     dsg::Ctl c;
     st = read_ctl(g, &c);
     if (st != DSG_OK) return st;
-    long long items = 0;
-    if ((e = hipMemcpy(&items, g->d.tile_off, sizeof(long long), hipMemcpyDeviceToHost)) != hipSuccess)
-        return hip_fail(e, "hipMemcpy(items)");
-    g->d.n_items = (int)items;
     g->d.max_deg = c.max_deg;
     if (flags & DSG_VALIDATE) {
         if ((e = dsg::launch_check_rows(g->d, s)) != hipSuccess) return hip_fail(e, "check rows");
         st = check_errors(g, "rows");
         if (st != DSG_OK) return st;
     }
+    if (flags & DSG_HUB_ORDER) {
+        // renumber into the workspace, then work on the renumbered CSR only
+        if ((e = dsg::launch_hub_order(g->d, c.max_deg, g->d.hub_off, g->d.hub_adj, g->d.hub_perm, g->d.hub_iperm,
+                                       s)) != hipSuccess)
+            return hip_fail(e, "hub order");
+        g->d.off = g->d.hub_off;
+        g->d.adj = g->d.hub_adj;
+        g->d.perm = g->d.hub_perm;
+        g->d.iperm = g->d.hub_iperm;
+        if ((e = dsg::launch_build_static_items(g->d, s)) != hipSuccess) return hip_fail(e, "static items");
+    }
+    long long items = 0;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    if ((e = hipMemcpy(&items, g->d.tile_off, sizeof(long long), hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_fail(e, "hipMemcpy(items)");
+    g->d.n_items = (int)items;
+    if ((e = dsg::launch_bucket_bases(g->d, s)) != hipSuccess) return hip_fail(e, "bucket bases");
     if ((e = dsg::launch_reset_state(g->d, s)) != hipSuccess) return hip_fail(e, "reset");
     if (events) {
         if ((e = hipEventCreate(&g->ev0)) != hipSuccess) {
@@ -648,6 +686,16 @@ dsg_status dsg_get_best(dsg_graph* g, int64_t* edges, int64_t* verts, int32_t* i
     return DSG_OK;
 }
 
+// Under hub order: the caller's id of every internal vertex (empty otherwise).
+static dsg_status read_perm(dsg_graph* g, std::vector<int32_t>* perm) {
+    perm->clear();
+    if (!g->d.perm) return DSG_OK;
+    perm->resize((size_t)g->d.n);
+    DSG_HIP(hipMemcpy(perm->data(), g->d.perm, sizeof(int32_t) * (size_t)g->d.n, hipMemcpyDeviceToHost),
+            "hipMemcpy(perm)");
+    return DSG_OK;
+}
+
 dsg_status dsg_get_best_mask(dsg_graph* g, uint8_t* h_mask) {
     if (!g || !h_mask) return fail(DSG_EINVAL, "NULL argument");
     dsg::Ctl c;
@@ -661,18 +709,25 @@ dsg_status dsg_get_best_mask(dsg_graph* g, uint8_t* h_mask) {
     std::vector<int32_t> ord((size_t)n);
     DSG_HIP(hipMemcpy(ord.data(), g->d.best_order, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost),
             "hipMemcpy(best order)");
+    std::vector<int32_t> perm;
+    if ((st = read_perm(g, &perm)) != DSG_OK) return st;
     memset(h_mask, 0, (size_t)n);
-    for (long long i = c.best_idx; i < n; i++) h_mask[ord[(size_t)i]] = 1;
+    for (long long i = c.best_idx; i < n; i++) {
+        const int v = ord[(size_t)i];
+        h_mask[perm.empty() ? v : perm[(size_t)v]] = 1;
+    }
     return DSG_OK;
 }
 
 dsg_status dsg_get_loads(dsg_graph* g, int64_t* h_loads) {
     if (!g || !h_loads) return fail(DSG_EINVAL, "NULL argument");
     DSG_HIP(hipStreamSynchronize(g->ctx->stream), "hipStreamSynchronize");
-    std::vector<int32_t> tmp((size_t)g->d.n);
+    std::vector<int32_t> tmp((size_t)g->d.n), perm;
     DSG_HIP(hipMemcpy(tmp.data(), g->d.load, sizeof(int32_t) * (size_t)g->d.n, hipMemcpyDeviceToHost),
             "hipMemcpy(loads)");
-    for (int v = 0; v < g->d.n; v++) h_loads[v] = tmp[(size_t)v];
+    const dsg_status st = read_perm(g, &perm);
+    if (st != DSG_OK) return st;
+    for (int v = 0; v < g->d.n; v++) h_loads[perm.empty() ? v : perm[(size_t)v]] = tmp[(size_t)v];
     return DSG_OK;
 }
 
@@ -698,13 +753,28 @@ dsg_status dsg_get_order(dsg_graph* g, int32_t* h_round, int32_t* h_pos, int32_t
     if (g->last_variant < 0) return fail(DSG_ESTATE, "no iteration has run");
     DSG_HIP(hipStreamSynchronize(g->ctx->stream), "hipStreamSynchronize");
     const int n = g->d.n;
-    if (h_round)
-        DSG_HIP(hipMemcpy(h_round, g->d.rnd, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost), "hipMemcpy(round)");
+    std::vector<int32_t> perm;
+    const dsg_status st = read_perm(g, &perm);
+    if (st != DSG_OK) return st;
+    if (h_round) {
+        if (perm.empty()) {
+            DSG_HIP(hipMemcpy(h_round, g->d.rnd, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost),
+                    "hipMemcpy(round)");
+        } else {
+            std::vector<int32_t> rnd((size_t)n);
+            DSG_HIP(hipMemcpy(rnd.data(), g->d.rnd, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost),
+                    "hipMemcpy(round)");
+            for (int v = 0; v < n; v++) h_round[perm[(size_t)v]] = rnd[(size_t)v];
+        }
+    }
     if (h_pos) {
         std::vector<int32_t> ord((size_t)n);
         DSG_HIP(hipMemcpy(ord.data(), g->d.order, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost),
                 "hipMemcpy(order)");
-        for (int i = 0; i < n; i++) h_pos[ord[(size_t)i]] = i;
+        for (int i = 0; i < n; i++) {
+            const int v = ord[(size_t)i];
+            h_pos[perm.empty() ? v : perm[(size_t)v]] = i;
+        }
     }
     if (n_rounds) {
         int r = 0;
@@ -844,7 +914,9 @@ dsg_status par_coreness(dsg_ctx* ctx, const ParWs& w, int n, long long nnz, cons
                         const int32_t* d_adj, int tcap, int flags, bool timed, int eps_num, int eps_den, int* core_out,
                         dsg_graph* gb, dsg_graph** gout, int* nrounds_out, int* kmax_out, float* ms_out) {
     *gb = dsg_graph();
-    dsg_status st = graph_init(gb, ctx, n, nnz, d_offsets, d_adj, w.gws, w.gws_bytes, tcap, flags, false);
+    // the framework's graphs keep the input ids (its workspace has no room for a renumbered copy)
+    dsg_status st = graph_init(gb, ctx, n, nnz, d_offsets, d_adj, w.gws, w.gws_bytes, tcap, flags & DSG_VALIDATE,
+                               false);
     if (st != DSG_OK) return st;
     dsg_graph* g = gb;
     hipStream_t s = ctx->stream;
@@ -948,7 +1020,7 @@ dsg_status par_run_impl(dsg_ctx* ctx, int32_t n, int64_t nnz, const int32_t* d_o
     ParWs w;
     carve_par(n, nnz, tcap, static_cast<char*>(d_workspace), &w);
     hipStream_t s = ctx->stream;
-    const int created_flags = flags & ~DSG_VALIDATE;  // a cut of a valid graph is valid
+    const int created_flags = 0;  // a cut of a valid graph is valid
     // one graph is bound at a time; it lives in this frame (no handle allocation)
     dsg_graph gb{};
     dsg_graph* g = nullptr;

@@ -31,13 +31,11 @@ constexpr int PEEL_MAX_N = 1 << 26;  // frontier item counter has 26 bits
 // positions (start + up to 4096) must stay below 2^31 as well.
 constexpr long long MAX_NNZ = (1LL << 31) - (1LL << 16);
 // Owner-bucketed decrements of the PEEL round loop.  Vertex ids are split
-// into 2^sbits ranges: the first BKT_HUB_IDS ids one by one, the others by
-// 32-id lines, dealt out round robin.  A range's vertices are then spread
-// over the whole id space, so the ranges stay balanced when ids are ordered
-// by degree (the hubs come first), and above the hub ids a 128-byte line of
-// priorities has one owner.  Inside its range a vertex has a local id below
-// 2^lbits (lbits <= BKT_MAX_SHIFT, so a range's counters fit a dense LDS
-// histogram).
+// into at most 2^sbits ranges (BktMap below: contiguous blocks of ids in the
+// caller's order; under hub order the first BKT_HUB_IDS ids one by one and
+// the others by 32-id lines, dealt round robin).  Inside its range a vertex
+// has a local id below 2^lbits (lbits <= BKT_MAX_SHIFT, so a range's
+// counters fit a dense LDS histogram).
 // At most BKT_MAX_NR ranges, which covers every graph the PEEL path accepts
 // (n < 2^26).  Rounds whose frontier has at least the threshold's edges take
 // the bucketed path.
@@ -83,6 +81,36 @@ inline bool bucket_params(long long n, int* lbits, int* sbits) {
 static_assert(PEEL_MAX_N <= (1LL << (BKT_MAX_SHIFT + 11)) && (1 << 11) <= BKT_MAX_NR,
               "every graph the PEEL path accepts fits the bucketed path");
 
+// Owner ranges of the bucketed decrements: 2^sb ranges.  The first `hub` ids
+// are dealt one by one (u mod 2^sb), the rest by lines of 2^ls ids (line mod
+// 2^sb).  In caller order a range is one contiguous block of ids (hub = 0,
+// ls = the local id bits), so its priorities share few lines.  Under hub
+// order the hubs come first and their decrements come from nearly every
+// chunk: dealt singly (hub = BKT_HUB_IDS), then by 32-id lines (ls =
+// BKT_LINE), they spread evenly over the ranges, where one block of them
+// would overload a single range.  Local ids: the hub ids take the first
+// hub >> sb slots of a range.
+struct BktMap {
+    int sb;   // log2 of the range count
+    int ls;   // log2 of the line size
+    int hub;  // ids dealt singly
+    __device__ __forceinline__ int owner(int u) const {
+        const int m = (1 << sb) - 1;
+        return u < hub ? (u & m) : (((u - hub) >> ls) & m);
+    }
+    __device__ __forceinline__ int local(int u) const {
+        if (u < hub) return u >> sb;
+        const int w = u - hub;
+        return (hub >> sb) + (((w >> (ls + sb)) << ls) | (w & ((1 << ls) - 1)));
+    }
+    __device__ __forceinline__ int global(int j, int li) const {
+        const int h = hub >> sb;
+        if (li < h) return (li << sb) | j;
+        const int w = li - h;
+        return hub + (((w >> ls) << (ls + sb)) | (j << ls) | (w & ((1 << ls) - 1)));
+    }
+};
+
 struct PeelArgs {
     int n;
     int eps_num;
@@ -108,8 +136,8 @@ struct PeelArgs {
     unsigned int* bfill;   // per-range fill counters, zero between bucketed rounds
     const int* rbase;      // nr + 1 bucket starts: range j holds rbase[j + 1] - rbase[j] entries (its degree sum)
     int rshift;            // local id bits of a range
-    int rsbits;            // log2 of the range count
-    int nr;                // ranges (2^rsbits); 0 = bucketed path off
+    BktMap bm;             // vertex -> (range, local id)
+    int nr;                // ranges holding vertices; 0 = bucketed path off
     long long bkt_min_e;   // frontier edges from which a round is bucketed
     long long coarse_min_e;  // frontier edges from which a round sweeps coarse chunks
     int* seg;              // per block, by round parity: [2][alive start | alive len | frontier len][PEEL_BLK]
@@ -124,6 +152,7 @@ struct PeelArgs {
     int* segN;             // near-list segments, by round parity: [2][start | len][PEEL_BLK]
     int near_num;          // near bound B = thr * near_num / near_den + 1
     int near_den;
+    int hub;               // hub order: bit 31 of an entry tells whether the neighbour comes later in a round
 };
 
 struct SweepArgs {
@@ -149,6 +178,14 @@ struct GraphDev {
     long long nnz;
     const int* off;
     const int* adj;
+    // hub order (null otherwise): internal vertex i is the caller's perm[i],
+    // the caller's v is internal iperm[v]; off/adj are then the renumbered CSR
+    const int* perm;
+    const int* iperm;
+    int* hub_off;    // hub order storage (carved when the flag is set)
+    int* hub_adj;
+    int* hub_perm;
+    int* hub_iperm;
     Ctl* ctl;
     GridSync* gsync;
     int* load;
@@ -191,7 +228,7 @@ struct GraphDev {
     unsigned int* bfill;
     int* rbase;   // bucket starts per range (nr + 1), from the degree sums
     int rshift;   // local id bits of a range
-    int rsbits;   // log2 of the range count
+    BktMap bm;
     int nr;
     unsigned int* cb;  // SORT coarse ranks
     int* cr_bounds;    // first position of each coarse class
@@ -208,6 +245,17 @@ struct GraphDev {
     int n_items;  // vertices with degree > 0
     int max_deg;
 };
+
+// Hub order (DSG_HUB_ORDER): internal ids by non-increasing degree, ties by
+// the caller's id.  Adjacency entries of the renumbered CSR carry the
+// neighbour's internal id in bits 0-30 and, in bit 31, whether the
+// neighbour's caller id is larger than the row vertex's.
+constexpr int ADJ_ID_MASK = 0x7FFFFFFF;
+// Builds perm, iperm and the renumbered CSR (off_h: n + 1, adj_h: nnz) from
+// the caller's CSR in g.off / g.adj; uses g's radix and scan scratch and
+// g.load as temporary keys.
+hipError_t launch_hub_order(const GraphDev& g, int max_deg, int* off_h, int* adj_h, int* perm, int* iperm,
+                            hipStream_t s);
 
 // launchers (enqueue on `s`; return the first HIP error)
 hipError_t launch_check_offsets(const GraphDev& g, hipStream_t s);

@@ -490,6 +490,7 @@ __device__ __forceinline__ void sweep_chunks(int K, long long E, const int* __re
         // search for the first, then a linear advance over item boundaries
         const int xs = (int)x0 + (int)threadIdx.x * EPT;
         int jj[EPT], uu[EPT], st[EPT];
+        unsigned int tl = 0;  // bit e: entry e's order flag (bit 31 of a renumbered CSR's entry)
         {
             int j = 0;
             if ((long long)xs < x1) {
@@ -505,7 +506,9 @@ __device__ __forceinline__ void sweep_chunks(int K, long long E, const int* __re
                 if ((long long)x < x1) {
                     while (j + 1 < nitems && s.fe[j + 1] <= x) j++;
                     jj[e] = j;
-                    uu[e] = adj[s.rb[j] + x];
+                    const int raw = adj[s.rb[j] + x];
+                    uu[e] = raw & ADJ_ID_MASK;
+                    tl |= (raw < 0 ? 1u : 0u) << e;
                 } else {
                     jj[e] = -1;
                     uu[e] = 0;
@@ -529,7 +532,7 @@ __device__ __forceinline__ void sweep_chunks(int K, long long E, const int* __re
         op.template resolve<EPT>(jj, uu, st);
         bool hit[EPT];
 #pragma unroll
-        for (int e = 0; e < EPT; e++) hit[e] = jj[e] >= 0 && op.edge(s.v[jj[e]], uu[e], st[e], jj[e]);
+        for (int e = 0; e < EPT; e++) hit[e] = jj[e] >= 0 && op.edge(s.v[jj[e]], uu[e], st[e], jj[e], (tl >> e) & 1u);
         // Per-item counts.  Same-address LDS atomics serialise, and in a hub
         // row every edge of the chunk has the same item, so the counts are
         // summed first: over runs of one item within the thread's consecutive
@@ -714,28 +717,6 @@ struct XStage {
     }
 };
 
-// Owner ranges of the bucketed decrements (2^sb ranges).  The first
-// BKT_HUB_IDS ids are dealt one by one (u mod 2^sb), the rest by 32-id lines
-// (line mod 2^sb).  With ids ordered by degree the first ids are the hubs,
-// whose decrements come from nearly every chunk: dealt singly they spread
-// evenly over the ranges, where a whole line of them would overload one.
-// Local ids: the hub ids take the first BKT_HUB_IDS >> sb slots of a range.
-__device__ __forceinline__ int bkt_owner(int u, int sb) {
-    const int m = (1 << sb) - 1;
-    return u < BKT_HUB_IDS ? (u & m) : (((u - BKT_HUB_IDS) >> BKT_LINE) & m);
-}
-__device__ __forceinline__ int bkt_local(int u, int sb) {
-    if (u < BKT_HUB_IDS) return u >> sb;
-    const int w = u - BKT_HUB_IDS;
-    return (BKT_HUB_IDS >> sb) + (((w >> (BKT_LINE + sb)) << BKT_LINE) | (w & ((1 << BKT_LINE) - 1)));
-}
-__device__ __forceinline__ int bkt_global(int j, int li, int sb) {
-    const int h = BKT_HUB_IDS >> sb;
-    if (li < h) return (li << sb) | j;
-    const int w = li - h;
-    return BKT_HUB_IDS + (((w >> BKT_LINE) << (BKT_LINE + sb)) | (j << BKT_LINE) | (w & ((1 << BKT_LINE) - 1)));
-}
-
 template <int BLK>
 struct PeelEdgeOp {
     const unsigned int* st2;
@@ -747,7 +728,7 @@ struct PeelEdgeOp {
     // bucketed rounds: the chunk's aggregated (target, count) pairs go to
     // the owner range's bucket instead of one atomicSub per target
     bool bucket;
-    int rsb;  // log2 of the range count
+    BktMap bm;
     int nr;
     int n;
     const int* rbase;
@@ -759,6 +740,9 @@ struct PeelEdgeOp {
     // at or below it appends the vertex to the next round's crossing list
     int nearB = -1;  // -1: off
     XStage xst{};
+    // hub order: the entry's flag, not the internal ids, says which of two
+    // vertices peeled in one round comes first (the smaller caller id)
+    bool hub = false;
     __device__ void flag_error() {
         atomicAdd(&ctl->err_count, 1);
         ctl->err_code = ERR_INTERNAL;
@@ -767,7 +751,7 @@ struct PeelEdgeOp {
     __device__ __forceinline__ int gather(int u) const { return st2_get(st2, u); }
     template <int EPT>
     __device__ __forceinline__ void resolve(const int (&)[EPT], const int (&)[EPT], int (&)[EPT]) const {}
-    __device__ __forceinline__ bool edge(int v, int u, int su, int) {
+    __device__ __forceinline__ bool edge(int v, int u, int su, int, unsigned int later_id) {
         if (su == 1) {
             unsigned int h = ((unsigned int)u * 0x9E3779B1u) >> (32 - __builtin_ctz(DEC_SLOTS));
 #pragma unroll 1
@@ -786,7 +770,7 @@ struct PeelEdgeOp {
             if (nearB >= 0 && old > nearB && old - 1 <= nearB) xst.direct(u);
             return true;
         }
-        return su == 3 && u > v;
+        return su == 3 && (hub ? later_id != 0u : u > v);
     }
     __device__ __forceinline__ void flush_chunk() {
         if (bucket) {
@@ -835,7 +819,7 @@ struct PeelEdgeOp {
             const int slot = threadIdx.x + k * BLK;
             key[k] = dec->key[slot];
             c[k] = dec->cnt[slot];
-            rk[k] = key[k] != DEC_EMPTY ? atomicAdd(&bcnt[bkt_owner(key[k], rsb)], 1) : 0;
+            rk[k] = key[k] != DEC_EMPTY ? atomicAdd(&bcnt[bm.owner(key[k])], 1) : 0;
         }
         lds_barrier();
         for (int j = threadIdx.x; j < nr; j += BLK) {
@@ -857,9 +841,9 @@ struct PeelEdgeOp {
 #pragma unroll
         for (int k = 0; k < PER; k++) {
             if (key[k] != DEC_EMPTY) {
-                const int j = bkt_owner(key[k], rsb);
+                const int j = bm.owner(key[k]);
                 const int b = bbase[j];
-                if (b >= 0) bkt[b + rk[k]] = (bkt_local(key[k], rsb) << BKT_CNT_BITS) | (c[k] - 1);
+                if (b >= 0) bkt[b + rk[k]] = (bm.local(key[k]) << BKT_CNT_BITS) | (c[k] - 1);
                 const int slot = threadIdx.x + k * BLK;
                 dec->key[slot] = DEC_EMPTY;
                 dec->cnt[slot] = 0;
@@ -1147,8 +1131,9 @@ __global__ __launch_bounds__(PEEL_BLK, PEEL_BLOCKS_PER_CU) void k_peel_rounds(Pe
         const int K = (int)(f >> FCNT_SHIFT);
         const long long E = (long long)(f & FCNT_MASK);
         const bool bucket = a.nr > 0 && E >= a.bkt_min_e;
-        PeelEdgeOp<PEEL_BLK> op{a.st2, a.prio, r, lmin, ctl, &lds.m.dec, bucket, a.rsbits, a.nr, a.n, a.rbase, a.bkt,
+        PeelEdgeOp<PEEL_BLK> op{a.st2, a.prio, r, lmin, ctl, &lds.m.dec, bucket, a.bm, a.nr, a.n, a.rbase, a.bkt,
                                 a.bfill, lds.bcnt, lds.bbase};
+        op.hub = a.hub != 0;
         if (E >= a.coarse_min_e)
             sweep_chunks<PEEL_BLK, PEEL_CH, PEEL_CH / PEEL_MARK>(K, E, ivr, a.ie, a.ir, a.cfirst, a.clast, a.adj,
                                                                  a.inc, op, lds.m.sw, blockIdx.x, nblocks,
@@ -1186,7 +1171,7 @@ __global__ __launch_bounds__(PEEL_BLK, PEEL_BLOCKS_PER_CU) void k_peel_rounds(Pe
                     const unsigned int li = (unsigned int)a.bkt[lo + i] >> BKT_CNT_BITS;
                     if (li < (unsigned int)R) {
                         const int c = atomicExch(&lds.dense[li], 0);
-                        const int u = bkt_global(j, (int)li, a.rsbits);
+                        const int u = a.bm.global(j, (int)li);
                         if (c && u < a.n) {
                             const int pu = a.prio[u] - c;
                             a.prio[u] = pu;
@@ -1307,12 +1292,13 @@ __device__ __forceinline__ long long build_map(const int* __restrict__ tab, int 
     return (long long)tot;
 }
 
-// The order in which the first full-list pass of an iteration visits the
-// vertices (and so the order of the full list after it): 32-id lines read
-// column by column from a 256-column row-major layout of the lines.  Every
-// block's slice then samples the whole id space, so the blocks share the
-// frontier evenly also when the ids are ordered by degree.  A bijection of
-// [0, n); the partial last line stays in place.
+// Under hub order, the order in which the first full-list pass of an
+// iteration visits the vertices (and so the order of the full list after it):
+// 32-id lines read column by column from a 256-column row-major layout of the
+// lines.  Every block's slice then samples the whole id space, so the blocks
+// share the frontier evenly although vertices of similar degree, which tend
+// to leave in the same rounds, have neighbouring ids.  A bijection of [0, n);
+// the partial last line stays in place.
 __device__ __forceinline__ int spread_id(int idx, int n) {
     constexpr int S = 256;
     const int nl = n >> 5;
@@ -1344,8 +1330,8 @@ struct NearPass {
 };
 
 // Classifies the slice [beg, end) of a virtual list.  kind 0: entry i is
-// vertex spread_id(i); 1: Lin[map(i)]; 2: Lin[map(i)] for i < mtot, then
-// Xin[i - mtot].
+// vertex i (spread_id(i) under hub order); 1: Lin[map(i)]; 2: Lin[map(i)] for
+// i < mtot, then Xin[i - mtot].
 // Each alive entry (priority >= 0) goes to exactly one class:
 //   frontier (priority <= thr): round r, priority -1, state bit, Nout tail;
 //   survivor: bids its priority; to Fout[beg + ...] when Fout is given, and
@@ -1373,7 +1359,7 @@ __device__ __forceinline__ NearPass near_classify(const PeelArgs& a, int r, int 
     }
     auto entry = [&](int idx) -> int {
         if (idx >= end) return -1;
-        if (kind == 0) return spread_id(idx, a.n);
+        if (kind == 0) return a.hub ? spread_id(idx, a.n) : idx;
         if (kind == 2 && idx >= mtot) return Xin[idx - mtot];
         while (sj + 1 < nseg && spref[sj + 1] <= idx) sj++;
         return Lin[sstart[sj] + (idx - spref[sj])];
@@ -1652,12 +1638,13 @@ __global__ __launch_bounds__(NEAR_BLK, 1) void k_peel_rounds_near(PeelArgs a) {
         const int K = (int)(f >> FCNT_SHIFT);
         const long long E = (long long)(f & FCNT_MASK);
         const bool bucket = a.nr > 0 && E >= a.bkt_min_e;
-        PeelEdgeOp<NEAR_BLK> op{a.st2, a.prio, r, P.lmin, ctl, &lds.m.dec, bucket, a.rsbits, a.nr, a.n, a.rbase, a.bkt, a.bfill,
+        PeelEdgeOp<NEAR_BLK> op{a.st2, a.prio, r, P.lmin, ctl, &lds.m.dec, bucket, a.bm, a.nr, a.n, a.rbase, a.bkt, a.bfill,
                       lds.bcnt, lds.bbase};
         // crossings are staged in lds.bbase, which only the bucket flush uses (as scratch)
         const XStage xst{lds.bbase, &s_xn, Xout, &ctl->xcnt[nslot], a.n, ctl};
         op.nearB = (int)B;
         op.xst = xst;
+        op.hub = a.hub != 0;
         if (E >= a.coarse_min_e)
             sweep_chunks<NEAR_BLK, PEEL_CH, PEEL_CH / PEEL_MARK, PeelEdgeOp<NEAR_BLK>, PeelSweepLdsT, NEAR_PF>(
                 K, E, ivr, a.ie, a.ir, a.cfirst, a.clast, a.adj,
@@ -1726,7 +1713,7 @@ __global__ __launch_bounds__(NEAR_BLK, 1) void k_peel_rounds_near(PeelArgs a) {
                     const unsigned int li = e >> BKT_CNT_BITS;
                     if (li < span) {
                         const int c = atomicExch(&lds.dense[li], 0);
-                        const int u = bkt_global(j, (int)li, a.rsbits);
+                        const int u = a.bm.global(j, (int)li);
                         if (c && u < a.n) {
                             w = u;
                             const int old = a.prio[w];
@@ -1943,7 +1930,7 @@ struct SortEdgeOp {
                 if (jj[e] >= 0) st[e] = st[e] > spos[jj[e]] ? 1 : 0;
         }
     }
-    __device__ __forceinline__ bool edge(int, int, int later, int) const { return later != 0; }
+    __device__ __forceinline__ bool edge(int, int, int later, int, unsigned int) const { return later != 0; }
     __device__ __forceinline__ void flush_chunk() {}
 };
 
@@ -1963,21 +1950,35 @@ __global__ __launch_bounds__(SORT_BLK) void k_sweep_sort(SweepArgs a) {
 __global__ __launch_bounds__(SEQ_BLK) void k_seq_order(int n, const int* __restrict__ off,
                                                        const int* __restrict__ adj, const int* __restrict__ load,
                                                        int* __restrict__ order, int* __restrict__ rnd,
-                                                       int* __restrict__ inc) {
+                                                       int* __restrict__ inc, const int* __restrict__ perm,
+                                                       const int* __restrict__ iperm) {
+    constexpr int PER = (SEQ_MAX_N + SEQ_BLK - 1) / SEQ_BLK;
     extern __shared__ unsigned int sprio[];
     __shared__ unsigned long long shk[SEQ_BLK / WAVE];
     __shared__ int s_win;
-    for (int v = threadIdx.x; v < n; v += SEQ_BLK) sprio[v] = (unsigned int)(load[v] + (off[v + 1] - off[v]));
+    // ties go to the smallest caller id (the internal id unless hub-ordered)
+    int cid[PER];
+#pragma unroll
+    for (int k = 0; k < PER; k++) {
+        const int v = (int)threadIdx.x + k * SEQ_BLK;
+        cid[k] = v < n ? (perm ? perm[v] : v) : 0;
+        if (v < n) sprio[v] = (unsigned int)(load[v] + (off[v + 1] - off[v]));
+    }
     __syncthreads();
     for (int j = 0; j < n; j++) {
         unsigned long long best = ~0ull;
-        for (int v = threadIdx.x; v < n; v += SEQ_BLK) {
-            unsigned long long k = ((unsigned long long)sprio[v] << 32) | (unsigned int)v;
-            best = k < best ? k : best;
+#pragma unroll
+        for (int k = 0; k < PER; k++) {
+            const int v = (int)threadIdx.x + k * SEQ_BLK;
+            if (v < n) {
+                const unsigned long long key = ((unsigned long long)sprio[v] << 32) | (unsigned int)cid[k];
+                best = key < best ? key : best;
+            }
         }
         best = block_min<SEQ_BLK>(best, shk);
-        const int w = (int)(best & 0xFFFFFFFFull);
         if (threadIdx.x == 0) {
+            const int c = (int)(best & 0xFFFFFFFFull);
+            const int w = iperm ? iperm[c] : c;
             order[j] = w;
             rnd[w] = j;
             inc[w] = (int)sprio[w] - load[w];
@@ -1987,7 +1988,7 @@ __global__ __launch_bounds__(SEQ_BLK) void k_seq_order(int n, const int* __restr
         __syncthreads();
         const int a0 = off[s_win], a1 = off[s_win + 1];
         for (int e = a0 + threadIdx.x; e < a1; e += SEQ_BLK) {
-            const int u = adj[e];
+            const int u = adj[e] & ADJ_ID_MASK;
             if (sprio[u] != 0xFFFFFFFFu) sprio[u] -= 1;
         }
         __syncthreads();
@@ -2142,12 +2143,13 @@ __global__ __launch_bounds__(1024) void k_iter_end(const long long* __restrict__
     }
 }
 
-// load += charge; digest of (v, round); snapshot of the order on improvement.
+// load += charge; digest of (caller id, round); snapshot of the order on
+// improvement.
 __global__ __launch_bounds__(256) void k_finalize(int n, int* __restrict__ load, const int* __restrict__ inc,
                                                   const int* __restrict__ rnd, const int* __restrict__ order,
                                                   int* __restrict__ best_order, const Ctl* ctl,
                                                   unsigned long long* __restrict__ digest_slot, int* __restrict__ w_slot,
-                                                  int* __restrict__ lmax_slot) {
+                                                  int* __restrict__ lmax_slot, const int* __restrict__ perm) {
     __shared__ unsigned long long sh[256 / WAVE];
     __shared__ unsigned int shm[256 / WAVE];
     const bool improved = ctl->improved != 0;
@@ -2159,7 +2161,8 @@ __global__ __launch_bounds__(256) void k_finalize(int n, int* __restrict__ load,
         load[v] = l;
         wmax = max(wmax, (unsigned int)c);
         lmax = max(lmax, (unsigned int)l);
-        h += mix64(((unsigned long long)(unsigned int)v << 32) | (unsigned long long)(unsigned int)rnd[v]);
+        const int cv = perm ? perm[v] : v;  // the digest is over caller ids
+        h += mix64(((unsigned long long)(unsigned int)cv << 32) | (unsigned long long)(unsigned int)rnd[v]);
         if (improved) best_order[v] = order[v];
     }
     h = block_sum<256>(h, sh);
@@ -2207,7 +2210,7 @@ struct BatchPeelOp {
     __device__ __forceinline__ int gather(int u) const { return rnd[u]; }
     template <int EPT>
     __device__ __forceinline__ void resolve(const int (&)[EPT], const int (&)[EPT], int (&)[EPT]) const {}
-    __device__ __forceinline__ bool edge(int v, int u, int ru, int) {
+    __device__ __forceinline__ bool edge(int v, int u, int ru, int, unsigned int) {
         if (ru < 0) {
             unsigned int h = ((unsigned int)u * 0x9E3779B1u) >> (32 - __builtin_ctz(SLOTS));
 #pragma unroll 1
@@ -2595,20 +2598,21 @@ hipError_t launch_build_static_items(const GraphDev& g, hipStream_t s) {
 }
 
 // Degree sum of each owner range, written to rbase[j + 1]: block j sums its
-// single hub ids (j, j + nr, ... below BKT_HUB_IDS) and its lines above (line
-// l covers ids BKT_HUB_IDS + [32 l, 32 l + 32) and belongs to range l mod nr).
-__global__ __launch_bounds__(256) void k_bucket_cap(int n, const int* __restrict__ off, int sb,
+// single ids (j, j + 2^sb, ... below bm.hub) and its lines above (line l
+// covers ids bm.hub + [l 2^ls, (l + 1) 2^ls) and belongs to range l mod 2^sb).
+__global__ __launch_bounds__(256) void k_bucket_cap(int n, const int* __restrict__ off, BktMap bm,
                                                     int* __restrict__ rbase) {
     __shared__ long long sh[256 / WAVE];
     const int j = blockIdx.x;
+    const int sb = bm.sb;
     long long sum = 0;
-    const int nh = min(n, BKT_HUB_IDS);
+    const int nh = min(n, bm.hub);
     for (int u = j + ((int)threadIdx.x << sb); u < nh; u += 256 << sb) sum += off[u + 1] - off[u];
     const long long rest = (long long)n - nh;
-    const long long nlines = (rest + (1 << BKT_LINE) - 1) >> BKT_LINE;
+    const long long nlines = (rest + (1LL << bm.ls) - 1) >> bm.ls;
     for (long long l = j + ((long long)threadIdx.x << sb); l < nlines; l += 256LL << sb) {
-        const long long v0 = nh + (l << BKT_LINE);
-        const long long v1 = min((long long)n, v0 + (1 << BKT_LINE));
+        const long long v0 = nh + (l << bm.ls);
+        const long long v1 = min((long long)n, v0 + (1LL << bm.ls));
         sum += off[v1] - off[v0];
     }
     sum = block_sum<256>(sum, sh);
@@ -2631,8 +2635,99 @@ __global__ __launch_bounds__(1024) void k_bucket_scan(int nr, int* __restrict__ 
 
 hipError_t launch_bucket_bases(const GraphDev& g, hipStream_t s) {
     if (g.nr <= 0) return hipSuccess;
-    k_bucket_cap<<<g.nr, 256, 0, s>>>(g.n, g.off, g.rsbits, g.rbase);
+    k_bucket_cap<<<g.nr, 256, 0, s>>>(g.n, g.off, g.bm, g.rbase);
     k_bucket_scan<<<1, 1024, 0, s>>>(g.nr, g.rbase);
+    return hipGetLastError();
+}
+
+// ============================================================ hub order
+// Built once per graph.  Keys max_deg - degree sort the vertices by
+// non-increasing degree; the radix sort is stable, so ties keep the caller's
+// id order.
+__global__ void k_hub_keys(int n, const int* __restrict__ off, int max_deg, int* __restrict__ key) {
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+        key[v] = max_deg - (off[v + 1] - off[v]);
+}
+
+// perm = the sorted order; iperm its inverse; deg[i] = degree of internal i.
+__global__ void k_hub_perm(int n, const int* __restrict__ order, const int* __restrict__ off, int* __restrict__ perm,
+                           int* __restrict__ iperm, int* __restrict__ deg) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int v = order[i];
+        perm[i] = v;
+        iperm[v] = i;
+        deg[i] = off[v + 1] - off[v];
+    }
+}
+
+// off_h = exclusive prefix sums of deg (tile offsets already scanned in
+// tile_off), off_h[n] = nnz.
+__global__ __launch_bounds__(SCAN_BLK) void k_hub_offsets(int n, const int* __restrict__ deg,
+                                                          const long long* __restrict__ tile_off,
+                                                          int* __restrict__ off_h) {
+    __shared__ int sh[SCAN_BLK / WAVE];
+    const long long base = (long long)blockIdx.x * SCAN_TILE;
+    long long run = tile_off[blockIdx.x];
+    for (int k = 0; k < SCAN_ITEMS; k++) {
+        const long long i = base + k * SCAN_BLK + threadIdx.x;
+        const int d = i < n ? deg[i] : 0;
+        int tot;
+        const int ex = block_excl_scan<SCAN_BLK>(d, &tot, sh);
+        if (i < n) off_h[i] = (int)(run + ex);
+        if (i == n - 1) off_h[n] = (int)(run + ex + d);
+        run += tot;
+    }
+}
+
+// The renumbered rows, edge-parallel over the new adjacency: a block takes
+// SORT_CH consecutive entries, finds the rows holding the first and last by
+// binary search, and each thread finds its entry's row inside that range.
+// Entry x of internal row i is the caller's entry of row perm[i] at the same
+// offset, renumbered, with bit 31 set when its caller id is above perm[i].
+__global__ __launch_bounds__(SORT_BLK) void k_hub_adj(int n, long long nnz, const int* __restrict__ off,
+                                                      const int* __restrict__ adj, const int* __restrict__ off_h,
+                                                      const int* __restrict__ perm, const int* __restrict__ iperm,
+                                                      int* __restrict__ adj_h) {
+    __shared__ int s_k[2];
+    const long long nchunks = (nnz + SORT_CH - 1) / SORT_CH;
+    for (long long c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        const long long x0 = c * SORT_CH, x1 = min(nnz, x0 + SORT_CH);
+        if (threadIdx.x < 2) s_k[threadIdx.x] = row_of_entry(off_h, 0, n - 1, threadIdx.x == 0 ? x0 : x1 - 1);
+        __syncthreads();
+        const int k0 = s_k[0], k1 = s_k[1];
+        for (long long x = x0 + threadIdx.x; x < x1; x += SORT_BLK) {
+            const int i = row_of_entry(off_h, k0, k1, x);
+            const int v = perm[i];
+            const int u = adj[off[v] + (int)(x - off_h[i])];
+            adj_h[x] = iperm[u] | (u > v ? (int)~ADJ_ID_MASK : 0);
+        }
+        __syncthreads();  // s_k is rewritten for the next chunk
+    }
+}
+
+static hipError_t enqueue_radix(const GraphDev& g, const int* key_src, int passes, hipStream_t s);
+
+hipError_t launch_hub_order(const GraphDev& g, int max_deg, int* off_h, int* adj_h, int* perm, int* iperm,
+                            hipStream_t s) {
+    GraphDev d = g;  // the sort below must see the caller's ids
+    d.perm = nullptr;
+    d.iperm = nullptr;
+    int bits = 0;
+    while (bits < 31 && (1LL << bits) <= (long long)max_deg) bits++;
+    const int passes = bits < 8 ? 1 : (bits + 7) / 8;
+    k_hub_keys<<<grid_for(d.n, 256, 4096), 256, 0, s>>>(d.n, d.off, max_deg, d.load);
+    hipError_t e = enqueue_radix(d, d.load, passes, s);
+    if (e != hipSuccess) return e;
+    k_hub_perm<<<grid_for(d.n, 256, 4096), 256, 0, s>>>(d.n, d.order, d.off, perm, iperm, d.A);
+    const int ntiles = ceil_div(d.n, SCAN_TILE);
+    k_scan_tile_sums<<<ntiles, SCAN_BLK, 0, s>>>(d.A, d.n, d.tile_sum);
+    k_scan_top<<<1, 1024, 0, s>>>(d.tile_sum, ntiles, d.tile_off);
+    k_hub_offsets<<<ntiles, SCAN_BLK, 0, s>>>(d.n, d.A, d.tile_sum, off_h);
+    if (d.nnz > 0) {
+        const long long nchunks = (d.nnz + SORT_CH - 1) / SORT_CH;
+        const int grid = (int)(nchunks < 8192 ? nchunks : 8192);
+        k_hub_adj<<<grid, SORT_BLK, 0, s>>>(d.n, d.nnz, d.off, d.adj, off_h, perm, iperm, adj_h);
+    }
     return hipGetLastError();
 }
 
@@ -2658,10 +2753,32 @@ static void enqueue_radix_pass(const GraphDev& g, const int* kin, const int* vin
     k_radix_scatter<<<rt, RBLK, 0, s>>>(kin, vin, kout, vout, g.n, shift, g.rhist, rt, gate);
 }
 
+// out[i] = src[idx[i]]
+__global__ void k_gather_keys(int n, const int* __restrict__ idx, const int* __restrict__ src, int* __restrict__ out) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) out[i] = src[idx[i]];
+}
+
+// First pass input of a stable sort whose ties go to the smaller caller id:
+// the internal ids in caller-id order (iperm) with their keys, under hub
+// order; the identity otherwise.  The gathered keys go to g.kB, which the
+// first pass only reads.
+static void radix_first_input(const GraphDev& g, const int* key_src, const int** kin, const int** vin,
+                              hipStream_t s) {
+    *kin = key_src;
+    *vin = nullptr;
+    if (g.iperm) {
+        k_gather_keys<<<grid_for(g.n, 256, 4096), 256, 0, s>>>(g.n, g.iperm, key_src, g.kB);
+        *kin = g.kB;
+        *vin = g.iperm;
+    }
+}
+
 static hipError_t enqueue_radix(const GraphDev& g, const int* key_src, int passes, hipStream_t s) {
+    const int *k0, *v0;
+    radix_first_input(g, key_src, &k0, &v0, s);
     for (int p = 0; p < passes; p++) {
-        const int* kin = p == 0 ? key_src : ((p - 1) & 1 ? g.kB : g.kA);
-        const int* vin = p == 0 ? nullptr : ((p - 1) & 1 ? g.vB : g.vA);
+        const int* kin = p == 0 ? k0 : ((p - 1) & 1 ? g.kB : g.kA);
+        const int* vin = p == 0 ? v0 : ((p - 1) & 1 ? g.vB : g.vA);
         int* kout = p == passes - 1 ? nullptr : (p & 1 ? g.kB : g.kA);
         int* vout = p == passes - 1 ? g.order : (p & 1 ? g.vB : g.vA);
         enqueue_radix_pass(g, kin, vin, kout, vout, 8 * p, nullptr, s);
@@ -2669,21 +2786,24 @@ static hipError_t enqueue_radix(const GraphDev& g, const int* key_src, int passe
     return hipGetLastError();
 }
 
-// The order by (round, id) after a near-list round loop: a stable sort of the
-// vertices by round.  Rounds number at most n.  Up to 2^16 vertices two passes
+// The order by (round, id) after a near-list round loop, or any round loop
+// under hub order (ids are the caller's): a stable sort of the vertices by
+// round.  Rounds number at most n.  Up to 2^16 vertices two passes
 // suffice; above, the first two passes already leave their result in the
 // order array, and the two upper passes (order -> vA -> order) skip
 // themselves when the iteration had at most 2^16 rounds, as it nearly always
 // has.
 static hipError_t enqueue_sort_by_round(const GraphDev& g, hipStream_t s) {
+    const int *k0, *v0;
+    radix_first_input(g, g.rnd, &k0, &v0, s);
     if (g.n <= 256) {
-        enqueue_radix_pass(g, g.rnd, nullptr, nullptr, g.order, 0, nullptr, s);
+        enqueue_radix_pass(g, k0, v0, nullptr, g.order, 0, nullptr, s);
     } else if (g.n <= (1 << 16)) {
-        enqueue_radix_pass(g, g.rnd, nullptr, g.kA, g.vA, 0, nullptr, s);
+        enqueue_radix_pass(g, k0, v0, g.kA, g.vA, 0, nullptr, s);
         enqueue_radix_pass(g, g.kA, g.vA, nullptr, g.order, 8, nullptr, s);
     } else {
         const int* gate = &g.ctl->nrounds;
-        enqueue_radix_pass(g, g.rnd, nullptr, g.kA, g.vA, 0, nullptr, s);
+        enqueue_radix_pass(g, k0, v0, g.kA, g.vA, 0, nullptr, s);
         enqueue_radix_pass(g, g.kA, g.vA, g.kB, g.order, 8, nullptr, s);
         enqueue_radix_pass(g, g.kB, g.order, g.kA, g.vA, 16, gate, s);
         enqueue_radix_pass(g, g.kA, g.vA, nullptr, g.order, 24, gate, s);
@@ -2701,7 +2821,7 @@ static hipError_t enqueue_alg3(const GraphDev& g, int slot, int nrounds_static, 
     k_iter_end<<<1, 1024, 0, s>>>(g.tile_best, ntiles, g.ctl, g.hist_e, g.hist_v, g.hist_i, g.digest, g.rounds,
                                   g.hist_w, g.hist_lmax, slot, nrounds_static);
     k_finalize<<<grid_for(g.n, 256, 2048), 256, 0, s>>>(g.n, g.load, g.inc, g.rnd, g.order, g.best_order, g.ctl,
-                                                        g.digest + slot, g.hist_w + slot, g.hist_lmax + slot);
+                                                        g.digest + slot, g.hist_w + slot, g.hist_lmax + slot, g.perm);
     return hipGetLastError();
 }
 
@@ -2735,7 +2855,7 @@ hipError_t enqueue_iter_peel(const GraphDev& g, int slot, int eps_num, int eps_d
     a.bkt = g.bkt;
     a.bfill = g.bfill;
     a.rshift = g.rshift;
-    a.rsbits = g.rsbits;
+    a.bm = g.bm;
     a.rbase = g.rbase;
     a.nr = g.nr;
     a.bkt_min_e = bkt_min_e;
@@ -2751,6 +2871,7 @@ hipError_t enqueue_iter_peel(const GraphDev& g, int slot, int eps_num, int eps_d
     a.segN = g.segN;
     a.near_num = NEAR_B_NUM;
     a.near_den = NEAR_B_DEN;
+    a.hub = g.perm ? 1 : 0;
     // one segment per thread of a block (segment tables hold PEEL_BLK entries)
     if (peel_grid > (near ? NEAR_BLK : PEEL_BLK)) return hipErrorInvalidValue;
     void* args[] = {&a};
@@ -2762,11 +2883,11 @@ hipError_t enqueue_iter_peel(const GraphDev& g, int slot, int eps_num, int eps_d
     e = hipLaunchCooperativeKernel(kern, dim3(peel_grid), dim3(near ? NEAR_BLK : PEEL_BLK), args, 0, s);
     if (e != hipSuccess) return e;
     if (ev_b && (e = hipEventRecord(ev_b, s)) != hipSuccess) return e;
-    if (near) {
+    if (near || g.perm) {
         e = enqueue_sort_by_round(g, s);
         if (e != hipSuccess) return e;
     }
-    // the order is by round, ascending id inside a round (written by the
+    // else the order is by round, ascending id inside a round (written by the
     // full-list round loop itself)
     return enqueue_alg3(g, slot, 0, s);
 }
@@ -2816,7 +2937,7 @@ hipError_t enqueue_iter_seq(const GraphDev& g, int slot, hipStream_t s, hipEvent
     hipError_t e;
     if (ev_a && (e = hipEventRecord(ev_a, s)) != hipSuccess) return e;
     k_seq_order<<<1, SEQ_BLK, sizeof(unsigned int) * (size_t)g.n, s>>>(g.n, g.off, g.adj, g.load, g.order, g.rnd,
-                                                                          g.inc);
+                                                                          g.inc, g.perm, g.iperm);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (ev_b && (e = hipEventRecord(ev_b, s)) != hipSuccess) return e;

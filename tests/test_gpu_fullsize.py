@@ -52,16 +52,17 @@ def config2():
     return graphgen.config2(1)
 
 
+@pytest.mark.parametrize("hub", [True, False])
 @pytest.mark.parametrize("golden_name", ["config2", "config2_sort"])
-def test_config2_against_golden(dsg, config2, golden_name):
+def test_config2_against_golden(dsg, config2, golden_name, hub):
     path = os.path.join(HERE, "golden", golden_name + ".json")
     with open(path) as f:
         gd = json.load(f)
     o, a = config2
     assert sha(o) + sha(a) == gd["csr_sha256"], "generator output changed"
     ctx = dsg.Context(0)
-    g = dsg.Graph(ctx, o, a, t_cap=gd["T"])
-    log(f"{golden_name}: running {gd['variant']} T={gd['T']}")
+    g = dsg.Graph(ctx, o, a, t_cap=gd["T"], hub_order=hub)
+    log(f"{golden_name}: running {gd['variant']} T={gd['T']} hub_order={hub}")
     g.run(gd["T"], tuple(gd["eps"]), gd["variant"])
     g.sync()
     dens = g.iter_densities()
@@ -109,15 +110,16 @@ def _compare_golden(g, gd, what):
     assert sha(pos.astype(np.int32)) == gd["last_pos_sha256"], what
 
 
+@pytest.mark.parametrize("hub", [True, False])
 @pytest.mark.parametrize("golden_name", ["config3_sort", "config3_peel"])
-def test_config3_against_golden(dsg, config3, golden_name):
+def test_config3_against_golden(dsg, config3, golden_name, hub):
     with open(os.path.join(HERE, "golden", golden_name + ".json")) as f:
         gd = json.load(f)
     o, a = config3
     assert sha(o) + sha(a) == gd["csr_sha256"], "generator output changed"
     ctx = dsg.Context(0)
-    g = dsg.Graph(ctx, o, a, t_cap=gd["T"], validate=False)
-    log(f"{golden_name}: running {gd['variant']} eps={gd['eps']} T={gd['T']}")
+    g = dsg.Graph(ctx, o, a, t_cap=gd["T"], validate=False, hub_order=hub)
+    log(f"{golden_name}: running {gd['variant']} eps={gd['eps']} T={gd['T']} hub_order={hub}")
     g.run(gd["T"], tuple(gd["eps"]), gd["variant"])
     g.sync()
     _compare_golden(g, gd, golden_name)

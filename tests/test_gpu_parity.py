@@ -294,16 +294,17 @@ def test_peel_bucket_paths(dsg, ctx, name):
 
 
 def test_peel_bucket_more_ranges_than_blocks(dsg, ctx):
-    """n = 12M vertices: 512 owner ranges, more than the round loop's blocks, so blocks apply several ranges per
-    bucketed round (and the last lines of the id space fill only part of the ranges)."""
+    """n = 12M vertices: 367 owner ranges of 32768 ids (512 line-dealt ranges under hub order), more than the round
+    loop's blocks, so blocks apply several ranges per bucketed round (and the last range is partial)."""
     o, a = graphgen.er_planted(14, 12_000_000, 14_000_000, 60, 1, 2)
     ref = oracle.run(o, a, 2, "peel", (1, 10))
     for thr in [0, 1 << 62]:
-        log(f"bucket n=12M threshold={thr}")
-        g = dsg.Graph(ctx, o, a, t_cap=4).set_peel_tuning(thr, thr)
-        g.run(2, (1, 10), "peel")
-        assert_same(g, ref, f"bucket12M/{thr}")
-        g.close()
+        for hub in [False, True]:
+            log(f"bucket n=12M threshold={thr} hub_order={hub}")
+            g = dsg.Graph(ctx, o, a, t_cap=4, hub_order=hub).set_peel_tuning(thr, thr)
+            g.run(2, (1, 10), "peel")
+            assert_same(g, ref, f"bucket12M/{thr}/{hub}")
+            g.close()
 
 
 @pytest.mark.parametrize("name", list(_bucket_cases().keys()))
