@@ -261,6 +261,8 @@ def bench_graph(args):
         it_bytes, it_model = 16.0 * m + 88.0 * n, "16m+(16P+24)n, P=4 radix passes"
     avg_launch_s = (kern_ms / launches) / 1e3 if launches else float("nan")
     achieved = alg_bytes / avg_launch_s / 1e9
+    if g.hub_order:
+        name += "_hub"
     traffic = load_traffic(name, kernel)
     iter_s = elapsed / max(args.steps, 1) / T
     log(f"timed {args.steps} steps: {ms_per_step:.2f} ms/step (last run {run_ms:.2f} ms device), "
@@ -325,7 +327,11 @@ def bench_graph(args):
 
 
 def hub_arg(args):
-    return {"auto": "auto", "on": True, "off": False}[args.hub]
+    """auto: the library's size rule (hub order from 2^23 vertices), and hub order for SORT at any size, whose
+    sweep gains from it on R-MAT scale 22 too (0.51 against 0.71 ms per iteration), unlike PEEL there."""
+    if args.hub == "auto":
+        return True if args.variant == "sort" and args.workload in ("rmat22", "c3") else "auto"
+    return {"on": True, "off": False}[args.hub]
 
 
 def c3_legs(args, dsg, ctx, o_dev, a_dev, n, m, T):

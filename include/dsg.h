@@ -204,12 +204,14 @@ dsg_status dsg_last_run_ms(dsg_graph* g, float* ms);
  * thresholds count the adjacency entries of a round's frontier, and -1
  * selects the default.
  *  - bucket_min_edges: from this size on, a round applies its neighbour-degree
- *    decrements through owner buckets.  The buckets cover contiguous ranges of
- *    up to 32768 vertex ids (at most 2048 ranges, enough for every n the PEEL
- *    path accepts), and each range is summed by one block in an LDS histogram
- *    after an extra grid barrier.  Smaller rounds apply the decrements with
- *    per-chunk aggregated device atomics.  Default 2^20; 0 buckets every
- *    round.
+ *    decrements through owner buckets.  The buckets cover ranges of up to
+ *    32768 vertex ids (at most 2048 ranges, enough for every n the PEEL path
+ *    accepts): contiguous blocks of ids, or under DSG_HUB_ORDER the first
+ *    2^16 ids dealt one by one and the rest by 32-id lines, round robin.  Each
+ *    range is summed by one block in an LDS histogram after an extra grid
+ *    barrier.  Smaller rounds apply the decrements with per-chunk aggregated
+ *    device atomics.  Default 2^20 (2^17 under DSG_HUB_ORDER); 0 buckets
+ *    every round.
  *  - coarse_min_edges: from this size on, a round sweeps 4096-edge chunks;
  *    smaller rounds sweep 1024-edge chunks, so that more blocks share them.
  *    Default 2^20; 0 = always coarse.

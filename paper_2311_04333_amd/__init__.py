@@ -149,11 +149,13 @@ def _check(status: int):
         raise DsgError(status, msg.decode() if msg else "")
 
 
-def _finalize(obj):
+def _finalize(obj, _sys=sys):
     """Garbage-collection release of a handle.  At interpreter exit the HIP
     runtime (and any profiler attached to it) may already be torn down, so no
-    library call is made then: close handles explicitly before exiting."""
-    if sys.is_finalizing():
+    library call is made then: close handles explicitly before exiting.  (The
+    defaults and the callers' bound references keep working while module
+    globals are being cleared.)"""
+    if _sys is None or _sys.is_finalizing():
         return
     try:
         obj.close()
@@ -203,8 +205,8 @@ class Context:
             library().dsg_ctx_destroy(self._h)
             self._h = ctypes.c_void_p()
 
-    def __del__(self):
-        _finalize(self)
+    def __del__(self, _fin=_finalize):
+        _fin(self)
 
 
 class Graph:
@@ -386,8 +388,8 @@ class Graph:
             library().dsg_graph_destroy(self._h)
             self._h = ctypes.c_void_p()
 
-    def __del__(self):
-        _finalize(self)
+    def __del__(self, _fin=_finalize):
+        _fin(self)
 
 
 class Batch:
@@ -503,8 +505,8 @@ class Batch:
             library().dsg_batch_destroy(self._h)
             self._h = ctypes.c_void_p()
 
-    def __del__(self):
-        _finalize(self)
+    def __del__(self, _fin=_finalize):
+        _fin(self)
 
 
 class BatchGraphView:
@@ -633,8 +635,8 @@ class Server:
             library().dsg_server_destroy(self._h)
             self._h = ctypes.c_void_p()
 
-    def __del__(self):
-        _finalize(self)
+    def __del__(self, _fin=_finalize):
+        _fin(self)
 
 
 class _ParResultC(ctypes.Structure):

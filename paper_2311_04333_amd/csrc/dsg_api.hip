@@ -355,7 +355,7 @@ dsg_status graph_init(dsg_graph* g, dsg_ctx* ctx, int32_t n, int64_t nnz, const 
     g->ws_bytes = workspace_bytes;
     g->t_cap = t_cap;
     g->last_variant = -1;
-    g->bkt_min_e = dsg::BKT_DEFAULT_MIN_E;
+    g->bkt_min_e = (flags & DSG_HUB_ORDER) ? dsg::BKT_HUB_DEFAULT_MIN_E : dsg::BKT_DEFAULT_MIN_E;
     g->coarse_min_e = -1;
     g->sort_coarse = -1;
     g->peel_select = -1;
@@ -622,7 +622,9 @@ dsg_status dsg_last_run_ms(dsg_graph* g, float* ms) {
 dsg_status dsg_set_peel_tuning(dsg_graph* g, int64_t bucket_min_edges, int64_t coarse_min_edges) {
     if (!g) return fail(DSG_EINVAL, "graph is NULL");
     if (bucket_min_edges < -1 || coarse_min_edges < -1) return fail(DSG_EINVAL, "thresholds must be >= -1");
-    g->bkt_min_e = bucket_min_edges >= 0 ? bucket_min_edges : dsg::BKT_DEFAULT_MIN_E;
+    g->bkt_min_e = bucket_min_edges >= 0 ? bucket_min_edges
+                   : g->d.perm              ? dsg::BKT_HUB_DEFAULT_MIN_E
+                                            : dsg::BKT_DEFAULT_MIN_E;
     g->coarse_min_e = coarse_min_edges;
     return DSG_OK;
 }

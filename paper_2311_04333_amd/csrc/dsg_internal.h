@@ -46,6 +46,11 @@ constexpr int BKT_HUB_IDS = 1 << 16;  // dealt singly; a multiple of 32 * BKT_MA
 static_assert(BKT_HUB_IDS % ((1 << BKT_LINE) * BKT_MAX_NR) == 0, "hub ids fill whole lines of every range");
 constexpr int BKT_CNT_BITS = 12;  // bucket entry = local id << 12 | (count - 1); count <= PEEL_CH
 constexpr long long BKT_DEFAULT_MIN_E = 1LL << 20;
+// Under hub order the hubs' priorities share a few lines, and direct atomics
+// on them contend, so rounds are bucketed from fewer frontier edges: 2^17
+// took the 40M-vertex Chung-Lu graph's first 8 iterations from 51.8 to
+// 49.8 ms each (2^14: 50.5, every round: 52.6).
+constexpr long long BKT_HUB_DEFAULT_MIN_E = 1LL << 17;
 // Near-list select (k_peel_rounds_near): the near bound is B = thr * 5/4 + 1
 // at each full-list round.  The default from 2^23 vertices: on the 40M-vertex
 // Chung-Lu graph its round loop takes 48.9 ms per iteration against 53.2 ms for

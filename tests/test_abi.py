@@ -72,6 +72,22 @@ def test_workspace_bytes_host_logic(lib):
         dsg.workspace_bytes(10, (1 << 31) - (1 << 16) + 1, 1)
 
 
+def test_workspace_bytes_hub_order(lib):
+    """Hub order adds exactly the renumbered CSR and the two permutations, each region rounded up to 256 bytes."""
+    import paper_2311_04333_amd as dsg
+
+    def up(b):
+        return (b + 255) // 256 * 256
+
+    for n, nnz, t in [(1, 0, 1), (2000, 41216, 16), (4194304, 128312518, 64), ((1 << 26) - 1, 1000, 4)]:
+        plain = dsg.workspace_bytes(n, nnz, t)
+        assert dsg.workspace_bytes(n, nnz, t, dsg.VALIDATE) == plain
+        extra = up(4 * (n + 1)) + up(4 * nnz) + 2 * up(4 * n)
+        assert dsg.workspace_bytes(n, nnz, t, dsg.HUB_ORDER) == plain + extra
+    with pytest.raises(dsg.DsgError):
+        dsg.workspace_bytes(0, 0, 1, dsg.HUB_ORDER)
+
+
 def test_eps_parsing_is_exact():
     import paper_2311_04333_amd as dsg
 
