@@ -58,6 +58,7 @@ constexpr long long BKT_HUB_DEFAULT_MIN_E = 1LL << 17;
 // against 4.6 ms).
 constexpr int NEAR_B_NUM = 5;
 constexpr int NEAR_B_DEN = 4;
+constexpr int NEAR_B_ADD = 1;
 constexpr int NEAR_DEFAULT_MIN_N = 1 << 23;
 // SORT compares coarse ranks first once the position table (4n bytes) no
 // longer fits an XCD's L2.  The 4-bit table (n/2 bytes) fits it up to 2^22
@@ -155,8 +156,9 @@ struct PeelArgs {
     int* X1;
     int* segF;             // full-list segments, by parity: [2][start | len][PEEL_BLK]
     int* segN;             // near-list segments, by round parity: [2][start | len][PEEL_BLK]
-    int near_num;          // near bound B = thr * near_num / near_den + 1
+    int near_num;          // near bound B = thr * near_num / near_den + near_add
     int near_den;
+    int near_add;
     int hub;               // hub order: bit 31 of an entry tells whether the neighbour comes later in a round
 };
 

@@ -1364,28 +1364,34 @@ __device__ __forceinline__ NearPass near_classify(const PeelArgs& a, int r, int 
         while (sj + 1 < nseg && spref[sj + 1] <= idx) sj++;
         return Lin[sstart[sj] + (idx - spref[sj])];
     };
-    int un[NEAR_SEL_U];
+    // The next tile's entries are loaded at the top of a tile and their
+    // priorities in its middle, so a tile waits on neither.  (No block writes
+    // the priority of a vertex in another slice during the select.)
+    int un[NEAR_SEL_U], pn[NEAR_SEL_U];
 #pragma unroll
     for (int k = 0; k < NEAR_SEL_U; k++) {
         u[k] = -1;
         fr[k] = false;
         un[k] = entry(beg + (int)threadIdx.x * NEAR_SEL_U + k);
     }
+#pragma unroll
+    for (int k = 0; k < NEAR_SEL_U; k++) pn[k] = un[k] >= 0 ? a.prio[un[k]] : -1;
     for (int base = beg; base < end; base += TILE) {
         int pu[NEAR_SEL_U];
 #pragma unroll
         for (int k = 0; k < NEAR_SEL_U; k++) {
             u[k] = un[k];
+            pu[k] = pn[k];
             un[k] = entry(base + TILE + (int)threadIdx.x * NEAR_SEL_U + k);
         }
-#pragma unroll
-        for (int k = 0; k < NEAR_SEL_U; k++) pu[k] = u[k] >= 0 ? a.prio[u[k]] : -1;
 #pragma unroll
         for (int k = 0; k < NEAR_SEL_U; k++) {
             fr[k] = pu[k] >= 0 && (long long)pu[k] <= thr;
             o0[k] = fr[k] ? a.off[u[k]] : 0;
             o1[k] = fr[k] ? a.off[u[k] + 1] : 0;
         }
+#pragma unroll
+        for (int k = 0; k < NEAR_SEL_U; k++) pn[k] = un[k] >= 0 ? a.prio[un[k]] : -1;
         // packed per-thread counts: [near: 0-15][full-list survivors: 16-31][frontier: 32-47][items: 48-63]
         unsigned long long val = 0;
         // frontier marks of this thread's entries, one atomic per state word
@@ -1551,7 +1557,7 @@ __global__ __launch_bounds__(NEAR_BLK, 1) void k_peel_rounds_near(PeelArgs a) {
                 thr = ((q + p) * (long long)mn) / q;
                 if (MONO && r > 0) thr = max(thr, thr_prev);
             }
-            B = min(thr * a.near_num / a.near_den + 1, (long long)0x7FFFFFFE);
+            B = min(thr * a.near_num / a.near_den + a.near_add, (long long)0x7FFFFFFE);
             const long long per = (ftot + nblocks - 1) / nblocks;
             beg = (int)min(ftot, (long long)blockIdx.x * per);
             end = (int)min(ftot, (long long)beg + per);
@@ -2871,6 +2877,7 @@ hipError_t enqueue_iter_peel(const GraphDev& g, int slot, int eps_num, int eps_d
     a.segN = g.segN;
     a.near_num = NEAR_B_NUM;
     a.near_den = NEAR_B_DEN;
+    a.near_add = NEAR_B_ADD;
     a.hub = g.perm ? 1 : 0;
     // one segment per thread of a block (segment tables hold PEEL_BLK entries)
     if (peel_grid > (near ? NEAR_BLK : PEEL_BLK)) return hipErrorInvalidValue;
