@@ -1013,23 +1013,27 @@ __global__ __launch_bounds__(PEEL_BLK, PEEL_BLOCKS_PER_CU) void k_peel_rounds(Pe
         auto entry = [&](int idx) -> int {
             return (idx < end && map_ok) ? ((r == 0) ? idx : Lin[phys(idx)]) : -1;
         };
-        int un[SEL_U];
+        // (and their priorities in the middle of the tile before)
+        int un[SEL_U], pn[SEL_U];
 #pragma unroll
         for (int k = 0; k < SEL_U; k++) un[k] = entry(beg + (int)threadIdx.x * SEL_U + k);
+#pragma unroll
+        for (int k = 0; k < SEL_U; k++) pn[k] = un[k] >= 0 ? a.prio[un[k]] : 0;
         for (int base = beg; base < end; base += TILE) {
 #pragma unroll
             for (int k = 0; k < SEL_U; k++) {
                 u[k] = un[k];
+                pu[k] = pn[k];
                 un[k] = entry(base + TILE + (int)threadIdx.x * SEL_U + k);
             }
-#pragma unroll
-            for (int k = 0; k < SEL_U; k++) pu[k] = u[k] >= 0 ? a.prio[u[k]] : 0;
 #pragma unroll
             for (int k = 0; k < SEL_U; k++) {
                 const bool fr = u[k] >= 0 && (long long)pu[k] <= thr;
                 o0[k] = fr ? a.off[u[k]] : 0;
                 o1[k] = fr ? a.off[u[k] + 1] : 0;
             }
+#pragma unroll
+            for (int k = 0; k < SEL_U; k++) pn[k] = un[k] >= 0 ? a.prio[un[k]] : 0;
             // packed per-thread counts: [survivors: bits 0-15][items: 16-31]
             unsigned int val = 0;
 #pragma unroll
