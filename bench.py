@@ -154,7 +154,7 @@ def main():
     ap.add_argument("--select", type=int, default=-1, choices=[-1, 0, 1],
                     help="PEEL select: -1 = by size (near list from 2^23 vertices), 0 = full list, 1 = near list")
     ap.add_argument("--hub", default="auto", choices=["auto", "on", "off"],
-                    help="hub order (vertices renumbered by degree inside the library): auto = from 2^23 vertices")
+                    help="hub order (vertices renumbered by degree inside the library): auto = from 2^22 vertices")
     ap.add_argument("--count", type=int, default=4096, help="graphs in the batched mix")
     ap.add_argument("--plain-sample", type=int, default=256, help="graphs of the mix timed on the plain path")
     ap.add_argument("--T", type=int, default=None, help="iterations per step (default: 50 for c3, 20 otherwise)")
@@ -327,11 +327,8 @@ def bench_graph(args):
 
 
 def hub_arg(args):
-    """auto: the library's size rule (hub order from 2^23 vertices), and hub order for SORT at any size, whose
-    sweep gains from it on R-MAT scale 22 too (0.51 against 0.71 ms per iteration), unlike PEEL there."""
-    if args.hub == "auto":
-        return True if args.variant == "sort" and args.workload in ("rmat22", "c3") else "auto"
-    return {"on": True, "off": False}[args.hub]
+    """auto: the binding's size rule (hub order from 2^22 vertices)."""
+    return {"auto": "auto", "on": True, "off": False}[args.hub]
 
 
 def c3_legs(args, dsg, ctx, o_dev, a_dev, n, m, T):

@@ -31,7 +31,7 @@ STATUS = {0: "DSG_OK", -1: "DSG_EINVAL", -2: "DSG_ENOMEM", -3: "DSG_EDEVICE", -4
 VALIDATE = 1
 HUB_ORDER = 2
 # Graph(hub_order="auto") renumbers by degree from this many vertices on
-HUB_AUTO_MIN_N = 1 << 23
+HUB_AUTO_MIN_N = 1 << 22
 
 # every entry point declared in include/dsg.h: (name, restype, argtypes)
 _P = ctypes.c_void_p

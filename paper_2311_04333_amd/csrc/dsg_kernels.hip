@@ -852,6 +852,32 @@ struct PeelEdgeOp {
     }
 };
 
+// Under hub order, the order in which the first full-list pass of an
+// iteration visits the vertices (and so the order of the full list after it):
+// 32-id lines read column by column from a 256-column row-major layout of the
+// lines.  Every block's slice then samples the whole id space, so the blocks
+// share the frontier evenly although vertices of similar degree, which tend
+// to leave in the same rounds, have neighbouring ids.  A bijection of [0, n);
+// the partial last line stays in place.
+__device__ __forceinline__ int spread_id(int idx, int n) {
+    constexpr int S = 256;
+    const int nl = n >> 5;
+    const int line = idx >> 5;
+    if (line >= nl) return idx;
+    const int rows = (nl + S - 1) / S;
+    const int cfull = nl - (rows - 1) * S;  // columns with `rows` lines
+    int col, row;
+    if (line < cfull * rows) {
+        col = line / rows;
+        row = line - col * rows;
+    } else {
+        const int p = line - cfull * rows;
+        col = cfull + p / (rows - 1);
+        row = p - (col - cfull) * (rows - 1);
+    }
+    return ((row * S + col) << 5) | (idx & 31);
+}
+
 constexpr unsigned long long FCNT_SHIFT = 38;
 constexpr unsigned long long FCNT_MASK = (1ull << FCNT_SHIFT) - 1;
 // Alive-list entries per thread per select tile.  The round kernel is
@@ -1010,8 +1036,11 @@ __global__ __launch_bounds__(PEEL_BLK, PEEL_BLOCKS_PER_CU) void k_peel_rounds(Pe
         int s_run = 0, f_run = 0, i_run = 0;  // survivors, frontier and items so far (uniform)
         // the tile's entries; a tile's successor is loaded before the tile is
         // classified, so its round trip overlaps the classification
+        // (round 0 visits every vertex: in id order, or under hub order in
+        // spread_id order, which the alive lists then keep; the order by
+        // round is then sorted after the loop)
         auto entry = [&](int idx) -> int {
-            return (idx < end && map_ok) ? ((r == 0) ? idx : Lin[phys(idx)]) : -1;
+            return (idx < end && map_ok) ? ((r == 0) ? (a.hub ? spread_id(idx, a.n) : idx) : Lin[phys(idx)]) : -1;
         };
         // (and their priorities in the middle of the tile before)
         int un[SEL_U], pn[SEL_U];
@@ -1294,32 +1323,6 @@ __device__ __forceinline__ long long build_map(const int* __restrict__ tab, int 
     }
     __syncthreads();
     return (long long)tot;
-}
-
-// Under hub order, the order in which the first full-list pass of an
-// iteration visits the vertices (and so the order of the full list after it):
-// 32-id lines read column by column from a 256-column row-major layout of the
-// lines.  Every block's slice then samples the whole id space, so the blocks
-// share the frontier evenly although vertices of similar degree, which tend
-// to leave in the same rounds, have neighbouring ids.  A bijection of [0, n);
-// the partial last line stays in place.
-__device__ __forceinline__ int spread_id(int idx, int n) {
-    constexpr int S = 256;
-    const int nl = n >> 5;
-    const int line = idx >> 5;
-    if (line >= nl) return idx;
-    const int rows = (nl + S - 1) / S;
-    const int cfull = nl - (rows - 1) * S;  // columns with `rows` lines
-    int col, row;
-    if (line < cfull * rows) {
-        col = line / rows;
-        row = line - col * rows;
-    } else {
-        const int p = line - cfull * rows;
-        col = cfull + p / (rows - 1);
-        row = p - (col - cfull) * (rows - 1);
-    }
-    return ((row * S + col) << 5) | (idx & 31);
 }
 
 // Per-block result of one classification pass over a list slice.
