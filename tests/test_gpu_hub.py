@@ -111,3 +111,39 @@ def test_hub_order_large_equals_plain(dsg, ctx):
     assert np.array_equal(hr, pr) and np.array_equal(hp, pp) and hn == pn
     h.close()
     p.close()
+
+
+@pytest.mark.parametrize("variant", ["peel", "sort", "seq"])
+def test_hub_order_graph_replay_and_bounds(dsg, ctx, variant):
+    """Under hub order a run captured into a HIP graph (with the caller-order gathers of the sorts) replays to the
+    oracle's results, with eager work between replays; the width and load bounds and the certificate stop equal the
+    oracle's too."""
+    eps = (1, 10) if variant == "peel" else (0, 1)
+    o, a = graphgen.er_planted(23, 3000, 24000, 40, 1, 2)
+    ref = oracle.run(o, a, 4, variant, eps)
+    other = dsg.Graph(ctx, *graphgen.rmat(4, 12, 16 << 12), t_cap=4, hub_order=True)
+    g = dsg.Graph(ctx, o, a, t_cap=8, hub_order=True).set_graph_replay(True)
+    for rep in range(3):
+        g.reset().run(4, eps, variant)
+        assert g.graph_replay_state() == 1
+        assert_same(g, ref, f"hub {variant} replay {rep}")
+        other.reset().run(2, (1, 10), "peel")
+        other.sync()
+    g.close()
+    other.close()
+    h = dsg.Graph(ctx, o, a, t_cap=8, hub_order=True).run(4, eps, variant)
+    p = dsg.Graph(ctx, o, a, t_cap=8, hub_order=False).run(4, eps, variant)
+    assert h.iter_bounds() == p.iter_bounds()
+    h.close()
+    p.close()
+    st, stop = None, None
+    for t in range(1, 31):
+        st = oracle.run(o, a, 1, variant, eps, state=st)
+        if int(st.loads.max()) * int(st.best[1]) * 100 <= t * int(st.best[0]) * 101:
+            stop = t
+            break
+    g = dsg.Graph(ctx, o, a, t_cap=30, hub_order=True)
+    it, ok = g.run_until(30, eps, variant, (1, 100))
+    assert ok == (stop is not None) and it == (stop if stop is not None else 30)
+    assert_same(g, st, f"hub run_until {variant}")
+    g.close()
