@@ -1540,26 +1540,38 @@ __global__ __launch_bounds__(NEAR_BLK, 1) void k_peel_rounds_near(PeelArgs a) {
         if (full) {
             long long ftot = a.n;
             if (!f_all) ftot = build_map(a.segF + fpar * 2 * SEG_STRIDE, (int)nblocks, lds.spref, lds.sstart, shs);
+            // F is compacted (its survivors written to the other buffer) only
+            // once more than a quarter of its entries are peeled; until then a
+            // full-list pass reads it as it is (a peeled vertex has priority
+            // -1), and before the first compaction it reads no list at all
+            const bool compact = ftot - alive > ftot / 4;
             if (!exact) {
-                // N ran empty: compact F into the other buffer and find the exact minimum first
+                // N ran empty: find the exact minimum first
                 const long long per = (ftot + nblocks - 1) / nblocks;
                 beg = (int)min(ftot, (long long)blockIdx.x * per);
                 end = (int)min(ftot, (long long)beg + per);
                 const int* Fin = fpar ? a.L1 : a.L0;
-                int* Fout = fpar ? a.L0 : a.L1;
-                P = near_classify<true>(a, r, f_all ? 0 : 1, Fin, nullptr, ftot, beg, end, -2, -1, Fout, Nout,
-                                        lds.spref, lds.sstart, shs, u, fr, o0, o1);
-                int* segFout = a.segF + (fpar ^ 1) * 2 * SEG_STRIDE;
-                if (threadIdx.x == 0) {
-                    segFout[blockIdx.x] = beg;
-                    segFout[SEG_STRIDE + blockIdx.x] = P.s_run;
+                if (compact) {
+                    int* Fout = fpar ? a.L0 : a.L1;
+                    P = near_classify<true>(a, r, f_all ? 0 : 1, Fin, nullptr, ftot, beg, end, -2, -1, Fout, Nout,
+                                            lds.spref, lds.sstart, shs, u, fr, o0, o1);
+                    int* segFout = a.segF + (fpar ^ 1) * 2 * SEG_STRIDE;
+                    if (threadIdx.x == 0) {
+                        segFout[blockIdx.x] = beg;
+                        segFout[SEG_STRIDE + blockIdx.x] = P.s_run;
+                    }
+                } else {
+                    P = near_classify<false>(a, r, f_all ? 0 : 1, Fin, nullptr, ftot, beg, end, -2, -1, nullptr, Nout,
+                                             lds.spref, lds.sstart, shs, u, fr, o0, o1);
                 }
                 const unsigned int bmin = block_min<NEAR_BLK>(P.lmin, shm);
                 if (threadIdx.x == 0 && bmin != 0xFFFFFFFFu) atomicMin(&ctl->mn2[slot], bmin);
                 grid_sync(bar);
-                fpar ^= 1;
-                f_all = false;
-                ftot = build_map(a.segF + fpar * 2 * SEG_STRIDE, (int)nblocks, lds.spref, lds.sstart, shs);
+                if (compact) {
+                    fpar ^= 1;
+                    f_all = false;
+                    ftot = build_map(a.segF + fpar * 2 * SEG_STRIDE, (int)nblocks, lds.spref, lds.sstart, shs);
+                }
                 mn = ld_agent(&ctl->mn2[slot]);
                 thr = ((q + p) * (long long)mn) / q;
                 if (MONO && r > 0) thr = max(thr, thr_prev);
@@ -1569,7 +1581,7 @@ __global__ __launch_bounds__(NEAR_BLK, 1) void k_peel_rounds_near(PeelArgs a) {
             beg = (int)min(ftot, (long long)blockIdx.x * per);
             end = (int)min(ftot, (long long)beg + per);
             const int* Fin = fpar ? a.L1 : a.L0;
-            if (exact) {
+            if (exact && compact) {
                 // one pass: survivors to the other F buffer, near survivors to N
                 int* Fout = fpar ? a.L0 : a.L1;
                 P = near_classify<true>(a, r, f_all ? 0 : 1, Fin, nullptr, ftot, beg, end, thr, B, Fout, Nout,
@@ -1582,8 +1594,8 @@ __global__ __launch_bounds__(NEAR_BLK, 1) void k_peel_rounds_near(PeelArgs a) {
                 fpar ^= 1;
                 f_all = false;
             } else {
-                P = near_classify<false>(a, r, 1, Fin, nullptr, ftot, beg, end, thr, B, nullptr, Nout, lds.spref,
-                                         lds.sstart, shs, u, fr, o0, o1);
+                P = near_classify<false>(a, r, f_all ? 0 : 1, Fin, nullptr, ftot, beg, end, thr, B, nullptr, Nout,
+                                         lds.spref, lds.sstart, shs, u, fr, o0, o1);
             }
         } else {
             const long long per = (nin + nblocks - 1) / nblocks;
