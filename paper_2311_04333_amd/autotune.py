@@ -94,7 +94,7 @@ def tune_batch(ctx, graphs, T: int = 2, eps=(1, 10), sample: int = 256, use_cach
 
 # Single-graph PEEL round loop: (select, bucket_min_edges, coarse_min_edges).  select 0 = full-list, 1 = near-list;
 # the two thresholds count a round's frontier adjacency entries (owner buckets, 4096-edge chunks from that size).
-PEEL_CANDIDATES = [(s, b, c) for s in (0, 1) for b in (1 << 18, 1 << 20, 1 << 22, 1 << 62) for c in (1 << 18, 1 << 20)]
+PEEL_CANDIDATES = [(s, b, c) for s in (0, 1) for b in (1 << 14, 1 << 17, 1 << 20, 1 << 62) for c in (1 << 18, 1 << 20)]
 
 
 def peel_size_bucket(n: int, nnz: int) -> str:
