@@ -9,7 +9,10 @@ iterations of round-synchronous peeling with eps = 1/20.  Each iteration
 does init, the persistent round loop (select, sweep with the charges and the
 delayed degree decrements, the order by round), Algorithm 3, and the load
 and best updates.  `--workload rmat22` runs R-MAT scale 22 with PEEL
-eps = 1/10, T = 20 per step instead.
+eps = 1/10, T = 20 per step instead.  Both graphs are bound with hub order
+(vertices renumbered by degree inside the library, `--hub`); the renumbering
+is part of graph creation, outside the timed steps, and its time is printed
+under `setup`.
 
 Metric: edge-visits/s = 2m * T * steps / wall time of the timed steps.
 
