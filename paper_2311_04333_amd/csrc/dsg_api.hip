@@ -401,6 +401,24 @@ dsg_status graph_init(dsg_graph* g, dsg_ctx* ctx, int32_t n, int64_t nnz, const 
     if ((e = hipMemcpy(&items, g->d.tile_off, sizeof(long long), hipMemcpyDeviceToHost)) != hipSuccess)
         return hip_fail(e, "hipMemcpy(items)");
     g->d.n_items = (int)items;
+    if ((flags & DSG_HUB_ORDER) && g->d.nr > 0 && n > dsg::BKT_HUB_IDS) {
+        // narrow bucket apply: ranges of 2^16 local ids, when every vertex past
+        // the hub ids (internal ids by non-increasing degree) has degree < 2^16
+        int cl = 0;
+        while ((1LL << cl) < (long long)n) cl++;
+        const int sb = cl - dsg::BKT_NARROW_SHIFT;
+        int od[2] = {0, 0};
+        if (sb >= dsg::BKT_NARROW_MIN_SB && (1 << sb) <= dsg::BKT_MAX_NR) {
+            if ((e = hipMemcpy(od, g->d.hub_off + dsg::BKT_HUB_IDS, sizeof od, hipMemcpyDeviceToHost)) != hipSuccess)
+                return hip_fail(e, "hipMemcpy(degree)");
+            if (od[1] - od[0] < (1 << 16)) {
+                g->d.narrow = 1;
+                g->d.rshift = dsg::BKT_NARROW_SHIFT;
+                g->d.bm = dsg::BktMap{sb, dsg::BKT_LINE, dsg::BKT_HUB_IDS};
+                g->d.nr = 1 << sb;
+            }
+        }
+    }
     if ((e = dsg::launch_bucket_bases(g->d, s)) != hipSuccess) return hip_fail(e, "bucket bases");
     if ((e = dsg::launch_reset_state(g->d, s)) != hipSuccess) return hip_fail(e, "reset");
     if (events) {

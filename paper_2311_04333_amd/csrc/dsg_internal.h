@@ -43,6 +43,11 @@ constexpr int BKT_MAX_SHIFT = 15;
 constexpr int BKT_MAX_NR = 2048;
 constexpr int BKT_LINE = 5;  // 32 ids per line
 constexpr int BKT_HUB_IDS = 1 << 16;  // dealt singly; a multiple of 32 * BKT_MAX_NR
+// Narrow bucket apply (16-bit counters, 2^16 local ids per range): under hub
+// order when n needs at least 2^BKT_NARROW_MIN_SB such ranges and every
+// vertex past the hub ids has degree below 2^16.
+constexpr int BKT_NARROW_SHIFT = 16;
+constexpr int BKT_NARROW_MIN_SB = 8;
 static_assert(BKT_HUB_IDS % ((1 << BKT_LINE) * BKT_MAX_NR) == 0, "hub ids fill whole lines of every range");
 constexpr int BKT_CNT_BITS = 12;  // bucket entry = local id << 12 | (count - 1); count <= PEEL_CH
 constexpr long long BKT_DEFAULT_MIN_E = 1LL << 20;
@@ -160,6 +165,7 @@ struct PeelArgs {
     int near_den;
     int near_add;
     int hub;               // hub order: bit 31 of an entry tells whether the neighbour comes later in a round
+    int narrow;            // bucket apply with 16-bit counters (rshift = BKT_NARROW_SHIFT)
 };
 
 struct SweepArgs {
@@ -237,6 +243,7 @@ struct GraphDev {
     int rshift;   // local id bits of a range
     BktMap bm;
     int nr;
+    int narrow;   // 16-bit bucket apply (hub order, see BKT_NARROW_SHIFT)
     unsigned int* cb;  // SORT coarse ranks
     int* cr_bounds;    // first position of each coarse class
     int* cr_samp;      // degrees at the sampled positions

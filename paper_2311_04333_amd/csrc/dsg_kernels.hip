@@ -633,6 +633,45 @@ struct PeelSweepLds {
     SweepLds<PEEL_CH> sw;
     DecTable dec;
 };
+// The bucket apply's per-range histogram in LDS.  Wide: one int counter per
+// local id (2^15 ids).  Narrow (hub order when every vertex past the hub ids
+// has degree below 2^16, so no count of one round reaches 2^16): 16-bit
+// counters, two per int, for 2^16 local ids, and the range's first nh local
+// ids (the hubs, of any degree) in ints of their own.  Halving the ranges
+// halves the apply's per-range round trips and the flush's reservations.
+struct DenseHist {
+    int* d;    // 2^BKT_MAX_SHIFT ints
+    int* hub;  // nh ints (narrow)
+    int nh;
+    bool narrow;
+    unsigned int limit;  // local ids below this have a counter
+    __device__ __forceinline__ void clear(int tid, int blk) const {
+        for (int i = tid; i < (narrow ? (1 << BKT_MAX_SHIFT) : (int)limit); i += blk) d[i] = 0;
+        if (narrow)
+            for (int i = tid; i < nh; i += blk) hub[i] = 0;
+    }
+    __device__ __forceinline__ void add(unsigned int li, int c) const {
+        if (li >= limit) return;
+        if (!narrow) {
+            atomicAdd(&d[li], c);
+        } else if ((int)li < nh) {
+            atomicAdd(&hub[li], c);
+        } else {
+            const unsigned int k = li - (unsigned int)nh;
+            atomicAdd(&d[k >> 1], c << ((k & 1u) * 16));
+        }
+    }
+    // the count of local id li (< limit), cleared
+    __device__ __forceinline__ int take(unsigned int li) const {
+        if (!narrow) return atomicExch(&d[li], 0);
+        if ((int)li < nh) return atomicExch(&hub[li], 0);
+        const unsigned int k = li - (unsigned int)nh;
+        const int sh = (int)(k & 1u) * 16;
+        const int old = atomicAnd(&d[k >> 1], ~(0xFFFF << sh));
+        return (old >> sh) & 0xFFFF;
+    }
+};
+
 struct PeelLds {
     union {
         PeelSweepLds m;                     // the sweep
@@ -917,6 +956,7 @@ static_assert(PEEL_BLK * SEL_U < (1 << 16), "tile counts must fit their packed f
 template <bool MONO>
 __global__ __launch_bounds__(PEEL_BLK, PEEL_BLOCKS_PER_CU) void k_peel_rounds(PeelArgs a) {
     __shared__ PeelLds lds;
+    __shared__ int s_hubh[BKT_HUB_IDS >> BKT_NARROW_MIN_SB];  // narrow apply: the hubs' counters
     __shared__ unsigned long long shs[PEEL_BLK / WAVE];
     __shared__ unsigned int shm[PEEL_BLK / WAVE];
     __shared__ unsigned long long s_fbase;
@@ -1184,9 +1224,9 @@ __global__ __launch_bounds__(PEEL_BLK, PEEL_BLOCKS_PER_CU) void k_peel_rounds(Pe
             // read-modify-write (no other block touches it until the next
             // grid sync).  Work follows the entries, not the range size, and
             // every range leaves the histogram clear for the next one.
-            const int R = 1 << a.rshift;
+            const DenseHist H{lds.dense, s_hubh, a.bm.hub >> a.bm.sb, a.narrow != 0, 1u << a.rshift};
             if ((int)blockIdx.x < a.nr) {
-                for (int i = threadIdx.x; i < R; i += PEEL_BLK) lds.dense[i] = 0;  // it aliases the sweep's LDS
+                H.clear(threadIdx.x, PEEL_BLK);  // it aliases the sweep's LDS
                 lds_barrier();
             }
             for (int j = blockIdx.x; j < a.nr; j += nblocks) {
@@ -1196,14 +1236,13 @@ __global__ __launch_bounds__(PEEL_BLK, PEEL_BLOCKS_PER_CU) void k_peel_rounds(Pe
                 const int cnt = min((int)ld_agent(&a.bfill[j]), a.rbase[j + 1] - lo);
                 for (int i = threadIdx.x; i < cnt; i += PEEL_BLK) {
                     const unsigned int e = (unsigned int)a.bkt[lo + i];
-                    const unsigned int li = e >> BKT_CNT_BITS;
-                    if (li < (unsigned int)R) atomicAdd(&lds.dense[li], (int)(e & ((1u << BKT_CNT_BITS) - 1)) + 1);
+                    H.add(e >> BKT_CNT_BITS, (int)(e & ((1u << BKT_CNT_BITS) - 1)) + 1);
                 }
                 lds_barrier();
                 for (int i = threadIdx.x; i < cnt; i += PEEL_BLK) {
                     const unsigned int li = (unsigned int)a.bkt[lo + i] >> BKT_CNT_BITS;
-                    if (li < (unsigned int)R) {
-                        const int c = atomicExch(&lds.dense[li], 0);
+                    if (li < H.limit) {
+                        const int c = H.take(li);
                         const int u = a.bm.global(j, (int)li);
                         if (c && u < a.n) {
                             const int pu = a.prio[u] - c;
@@ -1462,6 +1501,7 @@ __global__ __launch_bounds__(NEAR_BLK, 1) void k_peel_rounds_near(PeelArgs a) {
     __shared__ long long s_ntot;  // entries in the near list's segments (map built at the previous round's end)
     __shared__ unsigned int s_xn;     // staged crossings
     __shared__ int s_meta[2 * APPLY_META];  // bucket apply: start and entry count of each of the block's ranges
+    __shared__ int s_hubh[BKT_HUB_IDS >> BKT_NARROW_MIN_SB];  // narrow apply: the hubs' counters
     __shared__ unsigned int s_xbase;  // their reserved start in the global list
     Ctl* ctl = a.ctl;
     GridSync* gs = a.gs;
@@ -1688,7 +1728,7 @@ __global__ __launch_bounds__(NEAR_BLK, 1) void k_peel_rounds_near(PeelArgs a) {
             // APPLY_REG * NEAR_BLK entries of a range in registers between the
             // two passes.  A decrement that crosses B appends its vertex to the
             // crossing list.
-            const int R = 1 << a.rshift;
+            const DenseHist H{lds.dense, s_hubh, a.bm.hub >> a.bm.sb, a.narrow != 0, 1u << a.rshift};
             const int my_nr = (int)blockIdx.x < a.nr ? (a.nr - (int)blockIdx.x + (int)nblocks - 1) / (int)nblocks : 0;
             if (my_nr > 0) {
                 for (int t = threadIdx.x; t < min(my_nr, APPLY_META); t += NEAR_BLK) {
@@ -1699,12 +1739,11 @@ __global__ __launch_bounds__(NEAR_BLK, 1) void k_peel_rounds_near(PeelArgs a) {
                     // flagged) but still counted: never read past the range
                     s_meta[2 * t + 1] = min((int)ld_agent(&a.bfill[j]), a.rbase[j + 1] - lo);
                 }
-                for (int i = threadIdx.x; i < R; i += NEAR_BLK) lds.dense[i] = 0;  // it aliases the sweep's LDS
+                H.clear(threadIdx.x, NEAR_BLK);  // it aliases the sweep's LDS
                 lds_barrier();
             }
             for (int k = 0; k < my_nr; k++) {
                 const int j = (int)blockIdx.x + k * (int)nblocks;
-                const unsigned int span = (unsigned int)R;
                 int lo, cnt;
                 if (k < APPLY_META) {
                     lo = s_meta[2 * k];
@@ -1721,14 +1760,10 @@ __global__ __launch_bounds__(NEAR_BLK, 1) void k_peel_rounds_near(PeelArgs a) {
                     ent[q] = i < cnt ? (unsigned int)a.bkt[lo + i] : 0xFFFFFFFFu;  // local id 2^20 - 1: no slot
                 }
 #pragma unroll
-                for (int q = 0; q < APPLY_REG; q++) {
-                    const unsigned int li = ent[q] >> BKT_CNT_BITS;
-                    if (li < span) atomicAdd(&lds.dense[li], (int)(ent[q] & CMASK) + 1);
-                }
+                for (int q = 0; q < APPLY_REG; q++) H.add(ent[q] >> BKT_CNT_BITS, (int)(ent[q] & CMASK) + 1);
                 for (int i = (int)threadIdx.x + APPLY_REG * NEAR_BLK; i < cnt; i += NEAR_BLK) {
                     const unsigned int e = (unsigned int)a.bkt[lo + i];
-                    const unsigned int li = e >> BKT_CNT_BITS;
-                    if (li < span) atomicAdd(&lds.dense[li], (int)(e & CMASK) + 1);
+                    H.add(e >> BKT_CNT_BITS, (int)(e & CMASK) + 1);
                 }
                 lds_barrier();
                 // the first entry of each vertex takes (and clears) its slot
@@ -1736,8 +1771,8 @@ __global__ __launch_bounds__(NEAR_BLK, 1) void k_peel_rounds_near(PeelArgs a) {
                     bool x = false;
                     int w = 0;
                     const unsigned int li = e >> BKT_CNT_BITS;
-                    if (li < span) {
-                        const int c = atomicExch(&lds.dense[li], 0);
+                    if (li < H.limit) {
+                        const int c = H.take(li);
                         const int u = a.bm.global(j, (int)li);
                         if (c && u < a.n) {
                             w = u;
@@ -2880,6 +2915,7 @@ hipError_t enqueue_iter_peel(const GraphDev& g, int slot, int eps_num, int eps_d
     a.bkt = g.bkt;
     a.bfill = g.bfill;
     a.rshift = g.rshift;
+    a.narrow = g.narrow;
     a.bm = g.bm;
     a.rbase = g.rbase;
     a.nr = g.nr;
