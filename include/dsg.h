@@ -207,7 +207,9 @@ dsg_status dsg_last_run_ms(dsg_graph* g, float* ms);
  *    decrements through owner buckets.  The buckets cover ranges of up to
  *    32768 vertex ids (at most 2048 ranges, enough for every n the PEEL path
  *    accepts): contiguous blocks of ids, or under DSG_HUB_ORDER the first
- *    2^16 ids dealt one by one and the rest by 32-id lines, round robin.  Each
+ *    2^16 ids dealt one by one and the rest by 32-id lines, round robin (with
+ *    65536 ids per range when n > 2^24 and every vertex past the first 2^16
+ *    ids has degree below 2^16).  Each
  *    range is summed by one block in an LDS histogram after an extra grid
  *    barrier.  Smaller rounds apply the decrements with per-chunk aggregated
  *    device atomics.  Default 2^20 (2^17 under DSG_HUB_ORDER); 0 buckets
