@@ -294,8 +294,9 @@ def test_peel_bucket_paths(dsg, ctx, name):
 
 
 def test_peel_bucket_more_ranges_than_blocks(dsg, ctx):
-    """n = 12M vertices: 367 owner ranges of 32768 ids (512 line-dealt ranges under hub order), more than the round
-    loop's blocks, so blocks apply several ranges per bucketed round (and the last range is partial)."""
+    """n = 12M vertices: 367 owner ranges of 32768 ids, more than the round loop's blocks, so blocks apply several
+    ranges per bucketed round (and the last range is partial).  Under hub order the graph takes the narrow apply
+    (256 line-dealt ranges of 2^16 ids with 16-bit counters, the hubs' counters apart)."""
     o, a = graphgen.er_planted(14, 12_000_000, 14_000_000, 60, 1, 2)
     ref = oracle.run(o, a, 2, "peel", (1, 10))
     for thr in [0, 1 << 62]:
