@@ -953,7 +953,9 @@ static_assert(PEEL_BLK * SEL_U < (1 << 16), "tile counts must fit their packed f
 //     (positions by round, ascending id inside a round).
 // L_0 is implicit (all vertices).  The loop ends when L_r is empty.  Every
 // block reads the same counters after a grid sync, so all leave together.
-template <bool MONO>
+// HUB: the graph is hub-ordered (a.hub), as a template argument so that the
+// caller-order instantiation carries none of its registers.
+template <bool MONO, bool HUB>
 __global__ __launch_bounds__(PEEL_BLK, PEEL_BLOCKS_PER_CU) void k_peel_rounds(PeelArgs a) {
     __shared__ PeelLds lds;
     __shared__ int s_hubh[BKT_HUB_IDS >> BKT_NARROW_MIN_SB];  // narrow apply: the hubs' counters
@@ -1080,7 +1082,7 @@ __global__ __launch_bounds__(PEEL_BLK, PEEL_BLOCKS_PER_CU) void k_peel_rounds(Pe
         // spread_id order, which the alive lists then keep; the order by
         // round is then sorted after the loop)
         auto entry = [&](int idx) -> int {
-            return (idx < end && map_ok) ? ((r == 0) ? (a.hub ? spread_id(idx, a.n) : idx) : Lin[phys(idx)]) : -1;
+            return (idx < end && map_ok) ? ((r == 0) ? (HUB ? spread_id(idx, a.n) : idx) : Lin[phys(idx)]) : -1;
         };
         // (and their priorities in the middle of the tile before)
         int un[SEL_U], pn[SEL_U];
@@ -1206,7 +1208,7 @@ __global__ __launch_bounds__(PEEL_BLK, PEEL_BLOCKS_PER_CU) void k_peel_rounds(Pe
         const bool bucket = a.nr > 0 && E >= a.bkt_min_e;
         PeelEdgeOp<PEEL_BLK> op{a.st2, a.prio, r, lmin, ctl, &lds.m.dec, bucket, a.bm, a.nr, a.n, a.rbase, a.bkt,
                                 a.bfill, lds.bcnt, lds.bbase};
-        op.hub = a.hub != 0;
+        op.hub = HUB;
         if (E >= a.coarse_min_e)
             sweep_chunks<PEEL_BLK, PEEL_CH, PEEL_CH / PEEL_MARK>(K, E, ivr, a.ie, a.ir, a.cfirst, a.clast, a.adj,
                                                                  a.inc, op, lds.m.sw, blockIdx.x, nblocks,
@@ -1224,7 +1226,7 @@ __global__ __launch_bounds__(PEEL_BLK, PEEL_BLOCKS_PER_CU) void k_peel_rounds(Pe
             // read-modify-write (no other block touches it until the next
             // grid sync).  Work follows the entries, not the range size, and
             // every range leaves the histogram clear for the next one.
-            const DenseHist H{lds.dense, s_hubh, a.bm.hub >> a.bm.sb, a.narrow != 0, 1u << a.rshift};
+            const DenseHist H{lds.dense, s_hubh, a.bm.hub >> a.bm.sb, HUB && a.narrow != 0, 1u << a.rshift};
             if ((int)blockIdx.x < a.nr) {
                 H.clear(threadIdx.x, PEEL_BLK);  // it aliases the sweep's LDS
                 lds_barrier();
@@ -2615,7 +2617,7 @@ int ctl_bytes() { return (int)sizeof(Ctl); }
 
 int peel_blocks_per_cu() {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(k_peel_rounds<false>), PEEL_BLK, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(k_peel_rounds<false, false>), PEEL_BLK, 0) !=
         hipSuccess)
         return 1;
     return nb < 1 ? 1 : nb;
@@ -2940,8 +2942,10 @@ hipError_t enqueue_iter_peel(const GraphDev& g, int slot, int eps_num, int eps_d
     if (ev_a && (e = hipEventRecord(ev_a, s)) != hipSuccess) return e;
     const void* kern = near ? (mono ? reinterpret_cast<const void*>(k_peel_rounds_near<true>)
                                     : reinterpret_cast<const void*>(k_peel_rounds_near<false>))
-                            : (mono ? reinterpret_cast<const void*>(k_peel_rounds<true>)
-                                    : reinterpret_cast<const void*>(k_peel_rounds<false>));
+                            : (mono ? (a.hub ? reinterpret_cast<const void*>(k_peel_rounds<true, true>)
+                                             : reinterpret_cast<const void*>(k_peel_rounds<true, false>))
+                                    : (a.hub ? reinterpret_cast<const void*>(k_peel_rounds<false, true>)
+                                             : reinterpret_cast<const void*>(k_peel_rounds<false, false>)));
     e = hipLaunchCooperativeKernel(kern, dim3(peel_grid), dim3(near ? NEAR_BLK : PEEL_BLK), args, 0, s);
     if (e != hipSuccess) return e;
     if (ev_b && (e = hipEventRecord(ev_b, s)) != hipSuccess) return e;
