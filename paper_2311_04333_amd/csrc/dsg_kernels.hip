@@ -1320,12 +1320,16 @@ __global__ __launch_bounds__(PEEL_BLK, PEEL_BLOCKS_PER_CU) void k_peel_rounds(Pe
 //     after N's own entries;
 //   * a round whose threshold is at most B has its whole frontier in N and
 //     scans only N.  Every other round (round 0, a threshold above B, or an
-//     empty N) scans the full list F: it drops the vertices peeled since F was
-//     last written, sets B = thr * near_num / near_den + 1 and rebuilds N;
+//     empty N) scans the full list F, sets B = thr * near_num / near_den +
+//     near_add and rebuilds N.  F is compacted (the vertices peeled since it
+//     was last written dropped) only once more than a quarter of it is
+//     peeled, and is not stored at all before its first compaction;
 //   * the next round's minimum is exact whenever N is not empty: every near
 //     vertex bids its priority, and every other alive vertex is above B.  When
 //     N runs empty, the next round first rescans F for the exact minimum (one
 //     more pass over F and one more grid sync), then classifies F;
+//   * under hub order the first pass visits the ids in spread_id order, which
+//     F keeps, so that every block's slice samples the whole id space;
 //   * peeled vertices get priority -1, which marks them dead in F;
 //   * a round's frontier comes out of N in list order, not id order, so the
 //     positions (by round, ascending id inside a round) are sorted after the
