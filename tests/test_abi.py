@@ -50,6 +50,15 @@ def test_variant_codes_match_the_header():
     assert codes == {"DSG_" + k.upper(): v for k, v in dsg.VARIANTS.items()}
 
 
+def test_flag_values_match_the_header():
+    """The binding's graph flags are the header's #defines."""
+    import paper_2311_04333_amd as dsg
+
+    text = open(HEADER).read()
+    flags = {name: int(v) for name, v in re.findall(r"#define (DSG_VALIDATE|DSG_HUB_ORDER)\s+(\d+)", text)}
+    assert flags == {"DSG_VALIDATE": dsg.VALIDATE, "DSG_HUB_ORDER": dsg.HUB_ORDER}
+
+
 def test_workspace_bytes_host_logic(lib):
     import paper_2311_04333_amd as dsg
 
